@@ -1,0 +1,122 @@
+"""Synthetic background atmosphere and vortex (inputs only).
+
+Background: constant Brunt-Vaisala frequency N_bv over a surface potential
+temperature theta_s, in hydrostatic balance:
+
+    theta0(z) = theta_s exp(N^2 z / g)
+    pi0(z)    = 1 + g^2 / (c_p theta_s N^2) (exp(-N^2 z / g) - 1)
+    rho0(z)   = p00 pi0^(c_v/R_d) / (R_d theta0)
+    dtheta0/dz= theta0 N^2 / g
+
+Vortex: axisymmetric about the domain centre, tangential wind
+v(r, z) = V(r) T(r) Zv(z) with a modified-Rankine V (linear to V_max at r_max,
+then V_max (r_max/r)^0.5), the paper's sixth-power radial taper
+T = exp(-(r/D2)^6) with D2 = L/4 (which makes the field periodic to e^-64),
+and a linear vertical decay Zv = max(0, 1 - z/z_v).  The pressure perturbation
+is in gradient-wind balance with the reference density,
+dp'/dr = rho0(z) (v^2/r + f v), integrated inward from r = L/2 where p' = 0;
+the density perturbation is hydrostatic, rho' = -(1/g) dp'/dz; theta' follows
+from the ideal-gas state (rho0 + rho', p0 + p'), plus seeded uniform noise.
+"""
+
+import numpy as np
+
+from . import noise
+
+
+def background(z, theta_s, N_bv, g, R_d, c_p, p00):
+    z = np.asarray(z, dtype=np.float64)
+    c_v = c_p - R_d
+    N2 = N_bv * N_bv
+    theta0 = theta_s * np.exp(N2 * z / g)
+    pi0 = 1.0 + g * g / (c_p * theta_s * N2) * (np.exp(-N2 * z / g) - 1.0)
+    rho0 = p00 * pi0 ** (c_v / R_d) / (R_d * theta0)
+    dtheta0 = theta0 * N2 / g
+    # d rho0/dz = rho0 ((c_v/R_d) pi0'/pi0 - theta0'/theta0), pi0' = -g/(c_p theta0)
+    dpi0 = -g / (c_p * theta0)
+    drho0 = rho0 * ((c_v / R_d) * dpi0 / pi0 - dtheta0 / theta0)
+    p0 = p00 * pi0 ** (c_p / R_d)
+    return dict(theta0=theta0, pi0=pi0, rho0=rho0, dtheta0dz=dtheta0,
+                drho0dz=drho0, p0=p0)
+
+
+def rankine(r, v_max, r_max, tail=0.5):
+    r = np.asarray(r, dtype=np.float64)
+    inner = v_max * r / r_max
+    outer = v_max * (r_max / np.maximum(r, 1e-30)) ** tail
+    return np.where(r <= r_max, inner, outer)
+
+
+class Vortex:
+    """Tabulated radial integrals of the balanced vortex."""
+
+    def __init__(self, v_max, r_max, D2, R_out, z_top_v, f, n_tab=400001):
+        self.v_max, self.r_max, self.D2 = v_max, r_max, D2
+        self.R_out, self.z_top_v, self.f = R_out, z_top_v, f
+        # radial grid with r_max on a grid point
+        n1 = max(2, int(round((n_tab - 1) * r_max / R_out)))
+        r1 = np.linspace(0.0, r_max, n1 + 1)
+        r2 = np.linspace(r_max, R_out, n_tab - n1)[1:]
+        self.r = np.concatenate([r1, r2])
+        vt = self.vt_surface(self.r)
+        s = np.maximum(self.r, 1e-30)
+        fa = np.where(self.r > 0, vt * vt / s, 0.0)
+        fb = vt
+        dr = np.diff(self.r)
+        # integrals from r to R_out (trapezoid, accumulated inward)
+        ca = np.concatenate([[0.0], np.cumsum(0.5 * dr * (fa[1:] + fa[:-1]))])
+        cb = np.concatenate([[0.0], np.cumsum(0.5 * dr * (fb[1:] + fb[:-1]))])
+        self.A = ca[-1] - ca
+        self.B = cb[-1] - cb
+
+    def vt_surface(self, r):
+        return rankine(r, self.v_max, self.r_max) * np.exp(-(np.asarray(r) / self.D2) ** 6)
+
+    def zv(self, z):
+        return np.maximum(0.0, 1.0 - np.asarray(z) / self.z_top_v)
+
+    def dzv(self, z):
+        return np.where(np.asarray(z) < self.z_top_v, -1.0 / self.z_top_v, 0.0)
+
+    def integrals(self, r):
+        r = np.asarray(r)
+        A = np.interp(r, self.r, self.A, right=0.0)
+        B = np.interp(r, self.r, self.B, right=0.0)
+        return A, B
+
+    def vorticity_surface(self, r, h=1.0):
+        """zeta = (1/r) d(r v)/dr at z = 0 (central difference)."""
+        r = np.maximum(np.asarray(r, dtype=np.float64), 2 * h)
+        rv = lambda s: s * self.vt_surface(s)
+        return (rv(r + h) - rv(r - h)) / (2 * h) / r
+
+
+def initial_state(xyz, bg_fn, vortex, phys, noise_amp, noise_ztop, seed, Lx, Ly):
+    """(rho', u, v, w, theta') at points xyz (n, 3)."""
+    x, y, z = xyz[:, 0], xyz[:, 1], xyz[:, 2]
+    g, R_d, c_p, p00 = phys["g"], phys["R_d"], phys["c_p"], phys["p00"]
+    c_v = c_p - R_d
+    bg = bg_fn(z)
+    r = np.sqrt(x * x + y * y)
+    Zv, dZv = vortex.zv(z), vortex.dzv(z)
+    vt = vortex.vt_surface(r) * Zv
+    rs = np.where(r > 0, r, 1.0)
+    u = np.where(r > 0, -vt * y / rs, 0.0)
+    v = np.where(r > 0, vt * x / rs, 0.0)
+    A, B = vortex.integrals(r)
+    f = vortex.f
+    S = Zv * Zv * A + f * Zv * B
+    dS = 2.0 * Zv * dZv * A + f * dZv * B
+    p_p = -bg["rho0"] * S
+    dp_dz = -bg["drho0dz"] * S - bg["rho0"] * dS
+    rho_p = -dp_dz / g
+    rho = bg["rho0"] + rho_p
+    p = bg["p0"] + p_p
+    theta = p00 / (R_d * rho) * (p / p00) ** (c_v / c_p)
+    theta_p = theta - bg["theta0"]
+    if noise_amp > 0.0:
+        U = noise.uniform01(xyz, Lx, Ly, seed)
+        mask = z <= noise_ztop + 1e-6
+        theta_p = theta_p + np.where(mask, noise_amp * (2.0 * U - 1.0), 0.0)
+    w = np.zeros_like(u)
+    return np.stack([rho_p, u, v, w, theta_p])
