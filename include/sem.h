@@ -1,0 +1,196 @@
+/*
+ * sem.h -- C ABI of the MI355X spectral-element right-hand-side library.
+ *
+ * The library evaluates, on one AMD Instinct MI355X (gfx950), the per-stage
+ * right-hand side of the dry compressible Euler equations written for the
+ * perturbation variables (rho', u, v, w, theta') about a hydrostatic
+ * reference state (Tissaoui, Guimond, Giraldo & Marras, arXiv 2410.21607,
+ * Section 2, eqs. mass_split / mom_split / ent_split), discretised by
+ * continuous-Galerkin spectral elements on hexahedral columns with
+ * tensor-product Legendre-Gauss-Lobatto (LGL) points and inexact (lumped)
+ * integration (Section 3), assembled by direct stiffness summation with the
+ * hanging-node rule of Section 3.1, advanced by explicit third-order
+ * Runge-Kutta stages (Section 5), and adapted with the threshold criterion of
+ * Section 4.1.  The mesh is a horizontal quadtree of columns (refinement is
+ * horizontal only and acts on whole columns, Section 4.1) over n_z vertical
+ * layers; horizontal neighbours differ by at most one level (2:1 balance).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Fields      : F = 5, in the order rho' [kg m-3], u, v, w [m s-1], theta' [K].
+ * Unique nodes: a non-hanging global node is a pair (h, kz) of a unique
+ *               horizontal node h in [0, n_h) and a vertical node
+ *               kz in [0, nzn), nzn = n_z*N + 1 (kz = layer*N + k).
+ *               n_dof = n_h * nzn.
+ * State layout: double q[F][n_h][nzn] (field-major, kz fastest), device memory.
+ * Hanging     : a hanging point hh in [0, n_hh) is a horizontal position on a
+ *               fine column's face that is not a node of the coarser neighbour
+ *               (Section 3.1); hanging values are double hv[F][n_hh][nzn].
+ * Elements    : e = c*n_z + layer for column c (in the order given at create)
+ *               and layer in [0, n_z); local node l = i + (N+1)(j + (N+1)k)
+ *               with i along x, j along y, k along z (Section 3, basis).
+ *               Element arrays are double rE[F][n_elem][(N+1)^3].
+ * Domain      : x in [-Lx/2, Lx/2], y in [-Ly/2, Ly/2], z in [z_0, z_nz].
+ *               Column (level l, ix, iy) covers cell (ix, iy) of the
+ *               (nx0 2^l) x (ny0 2^l) grid.  Bottom and top are rigid lids:
+ *               the w tendency is zero there.  Non-periodic lateral sides
+ *               carry no boundary condition (operator tests only).
+ * Ownership   : every array argument is caller-owned; pointers named d_* are
+ *               device pointers, h_* host pointers.  The library never frees or
+ *               keeps them.  A mesh handle owns its device tables and its
+ *               workspace, sized at creation, so compute calls never allocate.
+ * Streams     : `stream` is a hipStream_t (NULL = the default stream).  Compute
+ *               calls are asynchronous on it; device faults surface at the
+ *               caller's next synchronisation.
+ * Errors      : calls return SEM_OK (0) or a negative code; sem_last_error()
+ *               returns a thread-local message for the last failure.
+ *               Argument, shape and mesh validation happens on the host before
+ *               any launch.
+ */
+#ifndef SEM_H
+#define SEM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SEM_OK        0
+#define SEM_ERR_ARG  -1   /* bad argument (null pointer, size, range)      */
+#define SEM_ERR_N    -2   /* unsupported polynomial order                   */
+#define SEM_ERR_MESH -3   /* invalid layout: overlap, gap, 2:1 violation    */
+#define SEM_ERR_HIP  -4   /* HIP runtime error (allocation, launch, copy)   */
+#define SEM_ERR_STATE -5  /* call made before a required set-up call        */
+
+#define SEM_MAX_N 8       /* polynomial orders 1..8 are supported           */
+#define SEM_MAX_LEVEL 12
+#define SEM_NFIELDS 5
+
+#define SEM_FP64 0        /* all arithmetic in double                        */
+#define SEM_FP32 1        /* element arithmetic in float on perturbations;   */
+                          /* assembly, mass and stage update stay double     */
+
+#define SEM_SCATTER 0     /* sem_nc_project: unique nodes -> hanging points  */
+#define SEM_GATHER  1     /* sem_nc_project: hanging points -> unique nodes  */
+
+#define SEM_ASSEMBLE 0    /* sem_dss phases */
+#define SEM_FINALIZE 1
+
+#define SEM_CRIT_SPEED 0  /* amr_flag criteria: |u| at every node           */
+#define SEM_CRIT_VORTZ 1  /* vertical vorticity dv/dx - du/dy (element-local)*/
+
+typedef struct sem_mesh sem_mesh;
+
+/* Mesh description (all host memory, read only during sem_mesh_create). */
+typedef struct {
+    int32_t N;                 /* polynomial order, 1..SEM_MAX_N               */
+    int32_t nx0, ny0;          /* level-0 column grid                          */
+    int32_t n_z;               /* number of vertical layers                    */
+    int32_t n_col;             /* number of leaf columns                       */
+    const int32_t *h_col_level, *h_col_ix, *h_col_iy; /* n_col each          */
+    double Lx, Ly;             /* horizontal domain size [m]                   */
+    const double *h_z_edges;   /* n_z + 1 strictly increasing heights [m]      */
+    int32_t periodic_x, periodic_y;
+    double f, g, R_d, c_p, p00; /* Coriolis [s-1], gravity, gas constants, p00 */
+} sem_mesh_desc;
+
+typedef struct {
+    int32_t N, n_z, nzn, max_level;
+    int64_t n_col, n_elem, n_h, n_hh, n_dof, n_hang, n_local;
+    int64_t workspace_bytes;   /* device memory held by the handle            */
+} sem_mesh_info;
+
+/* Build the column mesh (Sections 3, 3.1, 4.1): validate the layout (no
+ * overlap, full cover, 2:1 face+corner balance), number the unique and
+ * hanging nodes, build the interpolation rows of hanging points (composed
+ * until every source is a non-hanging node), the lumped mass
+ * M_G = Z^T m_L and the assembly tables, and upload them.  *out receives a
+ * handle to destroy with sem_mesh_destroy.  Errors: SEM_ERR_ARG, SEM_ERR_N,
+ * SEM_ERR_MESH, SEM_ERR_HIP. */
+int sem_mesh_create(const sem_mesh_desc *desc, sem_mesh **out);
+int sem_mesh_destroy(sem_mesh *mesh);
+
+/* Host-only planning (no GPU needed): run the same layout validation and
+ * numbering as sem_mesh_create and report sizes in *info; when the arrays are
+ * non-NULL also fill h_hxy[2*n_h], h_hhxy[2*n_hh], h_z[nzn] (as in
+ * sem_mesh_coords) and h_mass[n_dof], the assembled lumped mass M_G at each
+ * unique node in state order.  Call once with NULL arrays to learn the sizes. */
+int sem_mesh_plan(const sem_mesh_desc *desc, sem_mesh_info *info, double *h_hxy,
+                  double *h_hhxy, double *h_z, double *h_mass);
+int sem_mesh_get_info(const sem_mesh *mesh, sem_mesh_info *out);
+
+/* Node coordinates (host outputs, any may be NULL): h_hxy[2*n_h] (x, y of each
+ * unique horizontal node), h_hhxy[2*n_hh] (x, y of each hanging point),
+ * h_z[nzn] (height of each vertical node).  Used to match numberings by
+ * position and to evaluate the reference state. */
+int sem_mesh_coords(const sem_mesh *mesh, double *h_hxy, double *h_hhxy, double *h_z);
+
+/* Hydrostatic reference state (Section 2, eqs. rho_split..hydro_bal) per
+ * vertical node, host arrays of length nzn: rho0, theta0 and d theta0/dz.
+ * The reference pressure is p0 = p00 (R_d rho0 theta0 / p00)^(c_p/c_v), the
+ * equation of state applied to the reference, so that p' = 0 at rest.
+ * Must be called before any compute call. */
+int sem_mesh_set_reference(sem_mesh *mesh, const double *h_rho0,
+                           const double *h_theta0, const double *h_dtheta0dz);
+
+/* Modified-DSS interpolation across nonconforming faces (Section 3.1).
+ * SEM_SCATTER: d_dst = hv[F][n_hh][nzn] is overwritten with Z_h d_src, the
+ *              values at hanging points interpolated from d_src = q[F][n_h][nzn].
+ * SEM_GATHER : d_dst = acc[F][n_h][nzn] += Z_h^T d_src, d_src = c[F][n_hh][nzn]
+ *              holding contributions summed at hanging points.
+ * A mesh without hanging points makes both a no-op. */
+int sem_nc_project(const sem_mesh *mesh, int dir, const double *d_src,
+                   double *d_dst, void *stream);
+
+/* Element right-hand side (Section 2 perturbation equations, strong form,
+ * collocated at the LGL nodes of every element, Section 3), multiplied by the
+ * lumped LGL mass w_i w_j w_k |J_e|:
+ *   d_rE[F][n_elem][(N+1)^3] = m_l * R_l.
+ * Inputs: d_q = q[F][n_h][nzn], d_hv = hanging values from SEM_SCATTER (may
+ * be NULL when n_hh = 0).  precision = SEM_FP64 or SEM_FP32. */
+int sem_rhs(const sem_mesh *mesh, const double *d_q, const double *d_hv,
+            double *d_rE, int precision, void *stream);
+
+/* Direct stiffness summation (Section 3.1).
+ * SEM_ASSEMBLE: d_acc[F][n_h][nzn] = sum of d_rE over the local copies of each
+ *               unique node; d_c[F][n_hh][nzn] = the same at hanging points
+ *               (pass d_c to sem_nc_project(SEM_GATHER) to add Z_h^T c).
+ * SEM_FINALIZE: d_r[F][n_h][nzn] = d_acc / M_G, then r_w = 0 on the lids.
+ * Unused pointers for a phase may be NULL. */
+int sem_dss(const sem_mesh *mesh, int phase, const double *d_rE, double *d_acc,
+            double *d_c, double *d_r, void *stream);
+
+/* Runge-Kutta stage combination (Section 5), element-wise over 5*n_dof values:
+ *   d_qout = a*d_qn + b*d_qs + c*d_r        (any pointers may alias). */
+int sem_stage_update(const sem_mesh *mesh, double a, double b, double c,
+                     const double *d_qn, const double *d_qs, const double *d_r,
+                     double *d_qout, void *stream);
+
+/* Fused stage: d_qout = a*d_qn + b*d_qs + c*R(d_qs), with R the full
+ * right-hand side (scatter, element RHS, assembly, gather, finalize) evaluated
+ * in one pass over the columns of every refinement level.  d_qout must not
+ * alias d_qs or d_qn.  Uses the handle's workspace; concurrent calls on one
+ * handle race. */
+int sem_stage(const sem_mesh *mesh, double a, double b, double c,
+              const double *d_qn, const double *d_qs, double *d_qout,
+              int precision, void *stream);
+
+/* Refinement flags (Section 4.1).  Criterion C at every node of every element
+ * from element-local values: SEM_CRIT_SPEED |u| or SEM_CRIT_VORTZ dv/dx-du/dy.
+ * h_thr[0..lvl_max-1] = threshold(1..lvl_max), non-decreasing (host memory).
+ * d_adapt_elem[n_elem] (int8): +1 if some node has C > threshold(lvl+1) and
+ * lvl < lvl_max; -1 if every node has C <= threshold(lvl) and lvl > 0; else 0.
+ * d_adapt_col[n_col] (int8): +1 if any element of the column is +1; -1 if all
+ * elements of the column and of its three siblings are -1; else 0. */
+int amr_flag(const sem_mesh *mesh, const double *d_q, int criterion,
+             const double *h_thr, int lvl_max, int8_t *d_adapt_elem,
+             int8_t *d_adapt_col, void *stream);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *sem_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SEM_H */

@@ -1,0 +1,209 @@
+"""Python binding of the C ABI (argument marshalling only).
+
+Every compute call forwards device pointers of contiguous torch tensors and
+the current HIP stream to ``libsem.so``; no arithmetic of the method happens
+here.  Function names match the C entry points.
+"""
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import native
+from .native import (SEM_FP64, SEM_FP32, SEM_SCATTER, SEM_GATHER, SEM_ASSEMBLE,  # noqa: F401
+                     SEM_FINALIZE, SEM_CRIT_SPEED, SEM_CRIT_VORTZ)
+
+NF = 5
+
+
+def _stream(stream):
+    if stream is None:
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, torch.cuda.Stream):
+        return ctypes.c_void_p(stream.cuda_stream)
+    return ctypes.c_void_p(int(stream))
+
+
+def _ptr(t, dtype, numel, name):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.dtype != dtype or not t.is_cuda or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous {dtype} CUDA tensor")
+    if t.numel() != numel:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {numel}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _desc(N, nx0, ny0, columns, Lx, Ly, z_edges, periodic_x, periodic_y, f, g, R_d, c_p, p00):
+    cols = np.ascontiguousarray(np.asarray(columns, dtype=np.int32).reshape(-1, 3))
+    lev = np.ascontiguousarray(cols[:, 0])
+    ix = np.ascontiguousarray(cols[:, 1])
+    iy = np.ascontiguousarray(cols[:, 2])
+    z = np.ascontiguousarray(np.asarray(z_edges, dtype=np.float64))
+    i32 = lambda a: a.ctypes.data_as(native.c_i32p)
+    d = native.SemMeshDesc(int(N), int(nx0), int(ny0), int(z.size - 1), int(cols.shape[0]),
+                           i32(lev), i32(ix), i32(iy), float(Lx), float(Ly),
+                           z.ctypes.data_as(native.c_dp), int(bool(periodic_x)),
+                           int(bool(periodic_y)), float(f), float(g), float(R_d), float(c_p),
+                           float(p00))
+    return (cols, lev, ix, iy, z), d
+
+
+def _case_args(case):
+    p = case["phys"]
+    return (case["N"], case["nx0"], case["ny0"], case["columns"], case["Lx"], case["Ly"],
+            case["z_edges"], case["periodic_x"], case["periodic_y"], p["f"], p["g"],
+            p["R_d"], p["c_p"], p["p00"])
+
+
+def sem_mesh_plan(case):
+    """Host-only layout check and numbering (no GPU): returns
+    (info dict, hxy, hhxy, z, mass) with mass the assembled M_G per unique node."""
+    keep, d = _desc(*_case_args(case))
+    info = native.SemMeshInfo()
+    native.call("sem_mesh_plan", ctypes.byref(d), ctypes.byref(info), None, None, None, None)
+    hxy = np.zeros((info.n_h, 2))
+    hhxy = np.zeros((max(info.n_hh, 1), 2))
+    z = np.zeros(info.nzn)
+    mass = np.zeros(info.n_dof)
+    dp = lambda a: a.ctypes.data_as(native.c_dp)
+    native.call("sem_mesh_plan", ctypes.byref(d), ctypes.byref(info), dp(hxy), dp(hhxy), dp(z),
+                dp(mass))
+    out = {k: getattr(info, k) for k, _ in native.SemMeshInfo._fields_}
+    return out, hxy, hhxy[: info.n_hh], z, mass
+
+
+class Mesh:
+    """Owns a ``sem_mesh`` handle built from a column layout."""
+
+    def __init__(self, N, nx0, ny0, columns, Lx, Ly, z_edges, periodic_x=True,
+                 periodic_y=True, f=0.0, g=9.81, R_d=287.0, c_p=1004.0, p00=1.0e5):
+        self._keep, d = _desc(N, nx0, ny0, columns, Lx, Ly, z_edges, periodic_x, periodic_y,
+                              f, g, R_d, c_p, p00)
+        cols = self._keep[0]
+        h = ctypes.c_void_p()
+        native.call("sem_mesh_create", ctypes.byref(d), ctypes.byref(h))
+        self.handle = h
+        info = native.SemMeshInfo()
+        native.call("sem_mesh_get_info", self.handle, ctypes.byref(info))
+        self.info = {k: getattr(info, k) for k, _ in native.SemMeshInfo._fields_}
+        self.columns = cols
+        self.N = int(N)
+
+    @classmethod
+    def from_case(cls, case):
+        return cls(*_case_args(case))
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            try:
+                native.lib().sem_mesh_destroy(h)
+            except Exception:
+                pass
+            self.handle = None
+
+    # sizes
+    @property
+    def n_dof(self):
+        return self.info["n_dof"]
+
+    @property
+    def n_hang(self):
+        return self.info["n_hang"]
+
+    @property
+    def n_local(self):
+        return self.info["n_local"]
+
+    def coords(self):
+        """(hxy (n_h,2), hhxy (n_hh,2), z (nzn,)) as numpy arrays."""
+        i = self.info
+        hxy = np.zeros((i["n_h"], 2))
+        hhxy = np.zeros((max(i["n_hh"], 1), 2))
+        z = np.zeros(i["nzn"])
+        native.call("sem_mesh_coords", self.handle, hxy.ctypes.data_as(native.c_dp),
+                    hhxy.ctypes.data_as(native.c_dp), z.ctypes.data_as(native.c_dp))
+        return hxy, hhxy[: i["n_hh"]], z
+
+    def node_xyz(self):
+        """Coordinates of the unique nodes in state order [h][kz]."""
+        hxy, _, z = self.coords()
+        nzn = z.size
+        out = np.empty((hxy.shape[0] * nzn, 3))
+        out[:, 0] = np.repeat(hxy[:, 0], nzn)
+        out[:, 1] = np.repeat(hxy[:, 1], nzn)
+        out[:, 2] = np.tile(z, hxy.shape[0])
+        return out
+
+    def hang_xyz(self):
+        _, hh, z = self.coords()
+        nzn = z.size
+        out = np.empty((hh.shape[0] * nzn, 3))
+        out[:, 0] = np.repeat(hh[:, 0], nzn)
+        out[:, 1] = np.repeat(hh[:, 1], nzn)
+        out[:, 2] = np.tile(z, hh.shape[0])
+        return out
+
+    def set_reference(self, rho0, theta0, dtheta0dz):
+        arrs = [np.ascontiguousarray(np.asarray(a, dtype=np.float64)) for a in (rho0, theta0, dtheta0dz)]
+        for a in arrs:
+            if a.size != self.info["nzn"]:
+                raise ValueError("reference arrays need one value per vertical node")
+        native.call("sem_mesh_set_reference", self.handle,
+                    *[a.ctypes.data_as(native.c_dp) for a in arrs])
+
+    # workspace-free tensors of the right shapes
+    def state(self, device="cuda"):
+        return torch.zeros(NF * self.n_dof, dtype=torch.float64, device=device)
+
+
+def sem_nc_project(mesh, direction, src, dst, stream=None):
+    nd, nh = NF * mesh.n_dof, NF * mesh.n_hang
+    if direction == SEM_SCATTER:
+        s, d = _ptr(src, torch.float64, nd, "src"), _ptr(dst, torch.float64, nh, "dst")
+    else:
+        s, d = _ptr(src, torch.float64, nh, "src"), _ptr(dst, torch.float64, nd, "dst")
+    native.call("sem_nc_project", mesh.handle, int(direction), s, d, _stream(stream))
+
+
+def sem_rhs(mesh, q, hv, rE, precision=SEM_FP64, stream=None):
+    native.call("sem_rhs", mesh.handle, _ptr(q, torch.float64, NF * mesh.n_dof, "q"),
+                _ptr(hv, torch.float64, NF * mesh.n_hang, "hv") if mesh.n_hang else None,
+                _ptr(rE, torch.float64, NF * mesh.n_local, "rE"), int(precision), _stream(stream))
+
+
+def sem_dss(mesh, phase, rE=None, acc=None, c=None, r=None, stream=None):
+    native.call("sem_dss", mesh.handle, int(phase),
+                _ptr(rE, torch.float64, NF * mesh.n_local, "rE"),
+                _ptr(acc, torch.float64, NF * mesh.n_dof, "acc"),
+                _ptr(c, torch.float64, NF * mesh.n_hang, "c") if mesh.n_hang else None,
+                _ptr(r, torch.float64, NF * mesh.n_dof, "r"), _stream(stream))
+
+
+def sem_stage_update(mesh, a, b, c, qn, qs, r, qout, stream=None):
+    n = NF * mesh.n_dof
+    native.call("sem_stage_update", mesh.handle, float(a), float(b), float(c),
+                _ptr(qn, torch.float64, n, "qn"), _ptr(qs, torch.float64, n, "qs"),
+                _ptr(r, torch.float64, n, "r"), _ptr(qout, torch.float64, n, "qout"),
+                _stream(stream))
+
+
+def sem_stage(mesh, a, b, c, qn, qs, qout, precision=SEM_FP64, stream=None):
+    n = NF * mesh.n_dof
+    native.call("sem_stage", mesh.handle, float(a), float(b), float(c),
+                _ptr(qn, torch.float64, n, "qn"), _ptr(qs, torch.float64, n, "qs"),
+                _ptr(qout, torch.float64, n, "qout"), int(precision), _stream(stream))
+
+
+def amr_flag(mesh, q, criterion, thresholds, lvl_max, adapt_elem, adapt_col, stream=None):
+    thr = np.ascontiguousarray(np.asarray(thresholds, dtype=np.float64))
+    if thr.size < lvl_max:
+        raise ValueError("need one threshold per level")
+    native.call("amr_flag", mesh.handle, _ptr(q, torch.float64, NF * mesh.n_dof, "q"),
+                int(criterion), thr.ctypes.data_as(native.c_dp) if thr.size else None,
+                int(lvl_max), _ptr(adapt_elem, torch.int8, mesh.info["n_elem"], "adapt_elem"),
+                _ptr(adapt_col, torch.int8, mesh.info["n_col"], "adapt_col"), _stream(stream))

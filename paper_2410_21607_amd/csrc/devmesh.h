@@ -1,0 +1,26 @@
+// Device-side view of a column mesh: plain pointers into the handle's tables,
+// passed to kernels by value.
+#pragma once
+
+#include <cstdint>
+
+namespace sem {
+
+struct DevMesh {
+    int N, n_z, nzn, n_col;
+    int n_h, n_hh, n_hT;
+    double f, g, gamma;
+    const int32_t* gmap;      // n_col*(N+1)^2: h >= 0, or -(hh+1)
+    const double *col_dx, *col_dy, *dz;
+    const int32_t *hang_ptr, *hang_src;
+    const double* hang_w;
+    const int32_t *hT_list, *hT_ptr, *hT_hh;
+    const double* hT_w;
+    const int32_t *asm_ptr, *asm_slot, *asmH_ptr, *asmH_slot;
+    const double *minv_h, *minv_v;
+    const int32_t *sib, *col_level;
+    const double *D, *w;      // LGL derivative matrix and weights
+    const double *rho0, *theta0, *dth0, *p0;   // reference state per kz
+};
+
+}  // namespace sem

@@ -1,0 +1,474 @@
+// Host-side construction of the column mesh tables.
+//
+// Positions are identified by exact integer keys instead of floating-point
+// coordinates.  Along one axis, a node of a level-l column sits either on the
+// dyadic lattice (the column's two edges and, for even N, its midpoint) or at
+// an interior LGL position, which is irrational and therefore never shared
+// with a column of another level.  Lattice positions are counted in units of
+// half the finest column width; interior positions are keyed by
+// (level, cell, i).  Two nodes coincide exactly when their keys match.
+//
+// A boundary node of a fine column hangs when a coarser column containing the
+// point does not have it among its own nodes (Section 3.1).  Its value is the
+// coarse column's face polynomial there, and the rows are composed until every
+// source is a non-hanging node (chains appear with three or more levels, or
+// with odd N where coarse edge midpoints are not nodes).
+#include "mesh_build.h"
+
+#include <algorithm>
+#include <cmath>
+#include <map>
+#include <unordered_map>
+#include <utility>
+
+#include "sem.h"
+
+namespace sem {
+
+// ------------------------------------------------------------------ basis
+static void legendre(int N, double x, double& P, double& dP) {
+    // P_N(x) and P_N'(x) by the three-term recurrence
+    double p0 = 1.0, p1 = x, d0 = 0.0, d1 = 1.0;
+    if (N == 0) { P = 1.0; dP = 0.0; return; }
+    for (int n = 2; n <= N; ++n) {
+        double p2 = ((2.0 * n - 1.0) * x * p1 - (n - 1.0) * p0) / n;
+        double d2 = d0 + (2.0 * n - 1.0) * p1;   // P_n' = P_{n-2}' + (2n-1) P_{n-1}
+        p0 = p1; p1 = p2; d0 = d1; d1 = d2;
+    }
+    P = p1; dP = d1;
+}
+
+Basis1D make_basis(int N) {
+    Basis1D b;
+    b.N = N;
+    const int n = N + 1;
+    b.x.assign(n, 0.0);
+    b.w.assign(n, 0.0);
+    b.D.assign(n * n, 0.0);
+    b.x[0] = -1.0;
+    b.x[N] = 1.0;
+    for (int j = 1; j < N; ++j) {
+        double x = -std::cos(M_PI * j / N);
+        for (int it = 0; it < 100; ++it) {
+            double P, dP;
+            legendre(N, x, P, dP);
+            // Legendre ODE: (1-x^2) P'' = 2x P' - N(N+1) P
+            double d2P = (2.0 * x * dP - N * (N + 1.0) * P) / (1.0 - x * x);
+            double dx = dP / d2P;
+            x -= dx;
+            if (std::fabs(dx) < 1e-17) break;
+        }
+        b.x[j] = x;
+    }
+    for (int j = 0; j < n; ++j) {   // exact symmetry
+        double s = 0.5 * (b.x[j] - b.x[N - j]);
+        b.x[j] = s;
+    }
+    if (N % 2 == 0) b.x[N / 2] = 0.0;
+    for (int j = 0; j < n; ++j) {
+        double P, dP;
+        legendre(N, b.x[j], P, dP);
+        b.w[j] = 2.0 / (N * (N + 1.0) * P * P);
+    }
+    // barycentric weights lambda_j = 1 / prod_{k != j}(x_j - x_k)
+    std::vector<double> lam(n, 1.0);
+    for (int j = 0; j < n; ++j)
+        for (int k = 0; k < n; ++k)
+            if (k != j) lam[j] /= (b.x[j] - b.x[k]);
+    for (int i = 0; i < n; ++i) {
+        double row = 0.0;
+        for (int j = 0; j < n; ++j) {
+            if (i == j) continue;
+            double d = (lam[j] / lam[i]) / (b.x[i] - b.x[j]);
+            b.D[i * n + j] = d;
+            row += d;
+        }
+        b.D[i * n + i] = -row;   // rows of D annihilate constants
+    }
+    return b;
+}
+
+void lagrange_weights(const Basis1D& b, double s, double* out) {
+    const int n = b.N + 1;
+    for (int m = 0; m < n; ++m) {
+        if (std::fabs(s - b.x[m]) < 1e-13) {   // exactly on a node
+            for (int k = 0; k < n; ++k) out[k] = (k == m) ? 1.0 : 0.0;
+            return;
+        }
+    }
+    for (int m = 0; m < n; ++m) {
+        double v = 1.0;
+        for (int k = 0; k < n; ++k)
+            if (k != m) v *= (s - b.x[k]) / (b.x[m] - b.x[k]);
+        out[m] = v;
+    }
+}
+
+// ------------------------------------------------------------------ keys
+namespace {
+
+constexpr int64_t GLL_TAG = int64_t(1) << 62;
+
+struct Key2 {
+    int64_t kx, ky;
+    bool operator==(const Key2& o) const { return kx == o.kx && ky == o.ky; }
+};
+struct Key2Hash {
+    size_t operator()(const Key2& k) const {
+        uint64_t h = uint64_t(k.kx) * 0x9E3779B97F4A7C15ull;
+        h ^= uint64_t(k.ky) + 0x632BE59BD9B4E019ull + (h << 6) + (h >> 2);
+        return size_t(h);
+    }
+};
+
+struct Axis {
+    int n0;          // level-0 cells
+    int L;           // finest level
+    bool periodic;
+    int64_t total() const { return int64_t(n0) << (L + 1); }
+    int64_t width(int l) const { return int64_t(1) << (L - l + 1); }
+    // key of node i of cell `cell` at level l
+    int64_t key(int N, int l, int64_t cell, int i) const {
+        int64_t W = width(l), X;
+        if (i == 0) X = cell * W;
+        else if (i == N) X = (cell + 1) * W;
+        else if (N % 2 == 0 && 2 * i == N) X = cell * W + W / 2;
+        else return GLL_TAG | (int64_t(l) << 52) | (cell << 8) | int64_t(i);
+        if (periodic) X %= total();
+        return X;
+    }
+    static bool is_lattice(int64_t k) { return (k & GLL_TAG) == 0; }
+    // cells (unwrapped index) at level lc that contain the position of key k
+    int candidates(int64_t k, int lc, int64_t* out) const {
+        if (is_lattice(k)) {
+            int64_t W = width(lc);
+            if (k % W == 0) { out[0] = k / W - 1; out[1] = k / W; return 2; }
+            out[0] = k / W;
+            return 1;
+        }
+        int l = int((k >> 52) & 0x3FF);
+        int64_t cell = (k >> 8) & ((int64_t(1) << 44) - 1);
+        out[0] = cell >> (l - lc);
+        return 1;
+    }
+    // reference coordinate of key k inside the (unwrapped) cell cu at level lc
+    double ref_coord(const Basis1D& b, int64_t k, int lc, int64_t cu) const {
+        if (is_lattice(k)) {
+            int64_t W = width(lc);
+            double t = double(k - cu * W) / double(W);
+            return 2.0 * t - 1.0;
+        }
+        int l = int((k >> 52) & 0x3FF);
+        int64_t cell = (k >> 8) & ((int64_t(1) << 44) - 1);
+        int i = int(k & 0xFF);
+        int64_t off = cell - (cu << (l - lc));
+        double t = (double(off) + 0.5 * (1.0 + b.x[i])) / double(int64_t(1) << (l - lc));
+        return 2.0 * t - 1.0;
+    }
+    bool wrap(int64_t cu, int lc, int64_t& c) const {
+        int64_t nl = int64_t(n0) << lc;
+        if (periodic) { c = ((cu % nl) + nl) % nl; return true; }
+        if (cu < 0 || cu >= nl) return false;
+        c = cu;
+        return true;
+    }
+};
+
+using Row = std::vector<std::pair<int32_t, double>>;
+
+}  // namespace
+
+// ------------------------------------------------------------------ build
+int build_host_mesh(const MeshInput& in, HostMesh& m, std::string& err) {
+    if (in.N < 1 || in.N > SEM_MAX_N) { err = "N must be in [1, 8]"; return SEM_ERR_N; }
+    if (in.nx0 < 1 || in.ny0 < 1 || in.n_z < 1 || in.n_col < 1) {
+        err = "nx0, ny0, n_z and n_col must be positive"; return SEM_ERR_ARG;
+    }
+    if (!(in.Lx > 0) || !(in.Ly > 0)) { err = "Lx and Ly must be positive"; return SEM_ERR_ARG; }
+    if (!in.lev || !in.ix || !in.iy || !in.z_edges) { err = "null description array"; return SEM_ERR_ARG; }
+    for (int k = 0; k < in.n_z; ++k)
+        if (!(in.z_edges[k + 1] > in.z_edges[k])) { err = "z_edges must increase"; return SEM_ERR_ARG; }
+    const int N = in.N, np1 = N + 1, np2 = np1 * np1;
+    m.N = N; m.np1 = np1; m.n_z = in.n_z; m.nzn = in.n_z * N + 1;
+    m.nx0 = in.nx0; m.ny0 = in.ny0; m.periodic_x = in.periodic_x; m.periodic_y = in.periodic_y;
+    m.Lx = in.Lx; m.Ly = in.Ly;
+    m.f = in.f; m.g = in.g; m.R_d = in.R_d; m.c_p = in.c_p; m.p00 = in.p00;
+    if (!(in.c_p > in.R_d) || !(in.R_d > 0) || !(in.p00 > 0)) {
+        err = "need c_p > R_d > 0 and p00 > 0"; return SEM_ERR_ARG;
+    }
+    m.basis = make_basis(N);
+    const Basis1D& B = m.basis;
+    m.n_col = in.n_col;
+    m.col_level.assign(in.lev, in.lev + in.n_col);
+    m.col_ix.assign(in.ix, in.ix + in.n_col);
+    m.col_iy.assign(in.iy, in.iy + in.n_col);
+    int L = 0;
+    for (int c = 0; c < in.n_col; ++c) {
+        int l = in.lev[c];
+        if (l < 0 || l > SEM_MAX_LEVEL) { err = "column level out of range"; return SEM_ERR_MESH; }
+        if (in.ix[c] < 0 || in.ix[c] >= (int64_t(in.nx0) << l) ||
+            in.iy[c] < 0 || in.iy[c] >= (int64_t(in.ny0) << l)) {
+            err = "column index out of range for its level"; return SEM_ERR_MESH;
+        }
+        L = std::max(L, l);
+    }
+    m.max_level = L;
+    // ---- cover / overlap / 2:1 balance on the finest grid
+    const int64_t nxf = int64_t(in.nx0) << L, nyf = int64_t(in.ny0) << L;
+    if (nxf * nyf > (int64_t(1) << 27)) { err = "finest grid too large"; return SEM_ERR_MESH; }
+    std::vector<int32_t> owner(size_t(nxf * nyf), -1);
+    for (int c = 0; c < in.n_col; ++c) {
+        int64_t s = int64_t(1) << (L - in.lev[c]);
+        for (int64_t a = 0; a < s; ++a)
+            for (int64_t b = 0; b < s; ++b) {
+                int64_t fx = in.ix[c] * s + a, fy = in.iy[c] * s + b;
+                int32_t& o = owner[size_t(fx * nyf + fy)];
+                if (o >= 0) { err = "columns overlap"; return SEM_ERR_MESH; }
+                o = c;
+            }
+    }
+    for (auto o : owner)
+        if (o < 0) { err = "columns do not cover the domain"; return SEM_ERR_MESH; }
+    for (int c = 0; c < in.n_col; ++c) {
+        int l = in.lev[c];
+        int64_t s = int64_t(1) << (L - l);
+        for (int64_t a = -1; a <= s; ++a)
+            for (int64_t b = -1; b <= s; ++b) {
+                if (a >= 0 && a < s && b >= 0 && b < s) continue;
+                int64_t fx = in.ix[c] * s + a, fy = in.iy[c] * s + b;
+                if (in.periodic_x) fx = ((fx % nxf) + nxf) % nxf;
+                else if (fx < 0 || fx >= nxf) continue;
+                if (in.periodic_y) fy = ((fy % nyf) + nyf) % nyf;
+                else if (fy < 0 || fy >= nyf) continue;
+                int lo = in.lev[owner[size_t(fx * nyf + fy)]];
+                if (std::abs(lo - l) > 1) { err = "2:1 balance violated"; return SEM_ERR_MESH; }
+            }
+    }
+    // ---- column geometry
+    m.col_dx.resize(in.n_col); m.col_dy.resize(in.n_col);
+    m.col_x0.resize(in.n_col); m.col_y0.resize(in.n_col);
+    for (int c = 0; c < in.n_col; ++c) {
+        double wx = in.Lx / double(int64_t(in.nx0) << in.lev[c]);
+        double wy = in.Ly / double(int64_t(in.ny0) << in.lev[c]);
+        m.col_dx[c] = wx; m.col_dy[c] = wy;
+        m.col_x0[c] = -0.5 * in.Lx + in.ix[c] * wx;
+        m.col_y0[c] = -0.5 * in.Ly + in.iy[c] * wy;
+    }
+    // ---- interior LGL positions must not meet the lattice or the
+    //      interior positions of the adjacent level (checked on [0, 1])
+    {
+        std::vector<std::pair<double, int>> pts;
+        for (int l = 0; l <= 1; ++l)
+            for (int cell = 0; cell < (1 << l); ++cell)
+                for (int i = 1; i < N; ++i) {
+                    if (N % 2 == 0 && 2 * i == N) continue;
+                    pts.push_back({(cell + 0.5 * (1.0 + B.x[i])) / (1 << l), l});
+                }
+        for (int q = 0; q <= 8; ++q) pts.push_back({q / 8.0, 2});
+        std::sort(pts.begin(), pts.end());
+        for (size_t a = 1; a < pts.size(); ++a)
+            if (pts[a].second != pts[a - 1].second && pts[a].first - pts[a - 1].first < 1e-9) {
+                err = "LGL positions of adjacent levels coincide"; return SEM_ERR_N;
+            }
+    }
+    // ---- vertical
+    m.z_edges.assign(in.z_edges, in.z_edges + in.n_z + 1);
+    m.dz.resize(in.n_z);
+    m.zn.assign(m.nzn, 0.0);
+    std::vector<double> mv(m.nzn, 0.0);
+    for (int e = 0; e < in.n_z; ++e) {
+        m.dz[e] = in.z_edges[e + 1] - in.z_edges[e];
+        for (int k = 0; k < np1; ++k) {
+            int kz = e * N + k;
+            if (k < N) m.zn[kz] = in.z_edges[e] + 0.5 * (1.0 + B.x[k]) * m.dz[e];
+            mv[kz] += B.w[k] * 0.5 * m.dz[e];
+        }
+    }
+    m.zn[m.nzn - 1] = in.z_edges[in.n_z];
+    m.minv_v.resize(m.nzn);
+    for (int kz = 0; kz < m.nzn; ++kz) m.minv_v[kz] = 1.0 / mv[kz];
+
+    // ---- horizontal keys and hanging status
+    Axis ax{in.nx0, L, in.periodic_x}, ay{in.ny0, L, in.periodic_y};
+    std::map<std::tuple<int, int64_t, int64_t>, int32_t> cmap;
+    for (int c = 0; c < in.n_col; ++c) cmap[{in.lev[c], in.ix[c], in.iy[c]}] = c;
+    auto kx_of = [&](int c, int i) { return ax.key(N, in.lev[c], in.ix[c], i); };
+    auto ky_of = [&](int c, int j) { return ay.key(N, in.lev[c], in.iy[c], j); };
+
+    // source column (or -1) and reference coords for every (c, pos)
+    std::vector<int32_t> src_col(size_t(in.n_col) * np2, -1);
+    std::vector<double> src_sx(size_t(in.n_col) * np2, 0.0), src_sy(size_t(in.n_col) * np2, 0.0);
+    for (int c = 0; c < in.n_col; ++c) {
+        int l = in.lev[c];
+        if (l == 0) continue;
+        for (int j = 0; j < np1; ++j)
+            for (int i = 0; i < np1; ++i) {
+                if (i != 0 && i != N && j != 0 && j != N) continue;
+                int64_t kx = kx_of(c, i), ky = ky_of(c, j);
+                bool found = false;
+                for (int lc = 0; lc < l && !found; ++lc) {
+                    int64_t cxs[2], cys[2];
+                    int nxc = ax.candidates(kx, lc, cxs), nyc = ay.candidates(ky, lc, cys);
+                    for (int a = 0; a < nxc && !found; ++a)
+                        for (int b2 = 0; b2 < nyc && !found; ++b2) {
+                            int64_t cx, cy;
+                            if (!ax.wrap(cxs[a], lc, cx) || !ay.wrap(cys[b2], lc, cy)) continue;
+                            auto it = cmap.find({lc, cx, cy});
+                            if (it == cmap.end()) continue;
+                            int cc = it->second;
+                            bool nx_ = false, ny_ = false;
+                            for (int t = 0; t < np1; ++t) {
+                                nx_ = nx_ || (kx_of(cc, t) == kx);
+                                ny_ = ny_ || (ky_of(cc, t) == ky);
+                            }
+                            if (nx_ && ny_) continue;   // a node of the coarse column
+                            size_t s = size_t(c) * np2 + i + np1 * j;
+                            src_col[s] = cc;
+                            src_sx[s] = ax.ref_coord(B, kx, lc, cxs[a]);
+                            src_sy[s] = ay.ref_coord(B, ky, lc, cys[b2]);
+                            found = true;
+                        }
+                }
+            }
+    }
+    // ---- number unique nodes (first touch) and hanging points
+    std::unordered_map<Key2, int32_t, Key2Hash> hid, hhid;
+    m.gmap.assign(size_t(in.n_col) * np2, 0);
+    std::vector<size_t> hh_first;   // (c, pos) slot that defined each hanging point
+    for (int c = 0; c < in.n_col; ++c)
+        for (int j = 0; j < np1; ++j)
+            for (int i = 0; i < np1; ++i) {
+                size_t s = size_t(c) * np2 + i + np1 * j;
+                Key2 k{kx_of(c, i), ky_of(c, j)};
+                double x = m.col_x0[c] + 0.5 * (1.0 + B.x[i]) * m.col_dx[c];
+                double y = m.col_y0[c] + 0.5 * (1.0 + B.x[j]) * m.col_dy[c];
+                if (src_col[s] < 0) {
+                    auto it = hid.find(k);
+                    if (it == hid.end()) {
+                        int32_t id = int32_t(hid.size());
+                        hid.emplace(k, id);
+                        m.h_xy.push_back(x); m.h_xy.push_back(y);
+                        m.gmap[s] = id;
+                    } else {
+                        m.gmap[s] = it->second;
+                    }
+                } else {
+                    auto it = hhid.find(k);
+                    if (it == hhid.end()) {
+                        int32_t id = int32_t(hhid.size());
+                        hhid.emplace(k, id);
+                        m.hh_xy.push_back(x); m.hh_xy.push_back(y);
+                        hh_first.push_back(s);
+                        m.gmap[s] = -(id + 1);
+                    } else {
+                        m.gmap[s] = -(it->second + 1);
+                    }
+                }
+            }
+    for (auto& kv : hhid)
+        if (hid.count(kv.first)) { err = "a hanging point is also a conforming node"; return SEM_ERR_MESH; }
+    m.n_h = int64_t(hid.size());
+    m.n_hh = int64_t(hhid.size());
+    if (m.n_h * int64_t(m.nzn) >= (int64_t(1) << 31) || m.n_hh * int64_t(m.nzn) >= (int64_t(1) << 31) ||
+        int64_t(in.n_col) * in.n_z * np1 * np2 >= (int64_t(1) << 31)) {
+        err = "mesh too large for 32-bit node indices"; return SEM_ERR_MESH;
+    }
+    // ---- rows of every (c, pos), composed until the sources are unique nodes
+    std::vector<Row> rows(size_t(in.n_col) * np2);
+    std::vector<char> done(rows.size(), 0);
+    std::vector<double> wx(np1), wy(np1);
+    // process coarse levels first so that sources are complete
+    std::vector<int> order(in.n_col);
+    for (int c = 0; c < in.n_col; ++c) order[c] = c;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return in.lev[a] < in.lev[b]; });
+    for (int c : order)
+        for (int p = 0; p < np2; ++p) {
+            size_t s = size_t(c) * np2 + p;
+            if (src_col[s] < 0) { rows[s] = {{m.gmap[s], 1.0}}; done[s] = 1; continue; }
+            int cc = src_col[s];
+            lagrange_weights(B, src_sx[s], wx.data());
+            lagrange_weights(B, src_sy[s], wy.data());
+            std::map<int32_t, double> acc;
+            for (int b2 = 0; b2 < np1; ++b2)
+                for (int a = 0; a < np1; ++a) {
+                    double wt = wx[a] * wy[b2];
+                    if (wt == 0.0) continue;
+                    size_t ss = size_t(cc) * np2 + a + np1 * b2;
+                    if (!done[ss]) { err = "hanging chain does not resolve"; return SEM_ERR_MESH; }
+                    for (auto& e : rows[ss]) acc[e.first] += wt * e.second;
+                }
+            for (auto& e : acc)
+                if (e.second != 0.0) rows[s].push_back(e);
+            done[s] = 1;
+        }
+    // hanging rows (one per hanging point)
+    m.hang_ptr.assign(size_t(m.n_hh) + 1, 0);
+    for (int64_t hh = 0; hh < m.n_hh; ++hh) {
+        const Row& r = rows[hh_first[hh]];
+        for (auto& e : r) { m.hang_src.push_back(e.first); m.hang_w.push_back(e.second); }
+        m.hang_ptr[hh + 1] = int32_t(m.hang_src.size());
+    }
+    // transposed rows
+    {
+        std::vector<std::vector<std::pair<int32_t, double>>> t(size_t(m.n_h));
+        for (int64_t hh = 0; hh < m.n_hh; ++hh)
+            for (int32_t q = m.hang_ptr[hh]; q < m.hang_ptr[hh + 1]; ++q)
+                t[m.hang_src[q]].push_back({int32_t(hh), m.hang_w[q]});
+        m.hT_ptr.push_back(0);
+        for (int64_t h = 0; h < m.n_h; ++h) {
+            if (t[h].empty()) continue;
+            m.hT_list.push_back(int32_t(h));
+            for (auto& e : t[h]) { m.hT_hh.push_back(e.first); m.hT_w.push_back(e.second); }
+            m.hT_ptr.push_back(int32_t(m.hT_hh.size()));
+        }
+    }
+    // assembly CSR and horizontal lumped mass
+    {
+        std::vector<std::vector<int32_t>> a(size_t(m.n_h)), ah(size_t(m.n_hh));
+        std::vector<double> mh(size_t(m.n_h), 0.0);
+        for (int c = 0; c < in.n_col; ++c)
+            for (int j = 0; j < np1; ++j)
+                for (int i = 0; i < np1; ++i) {
+                    size_t s = size_t(c) * np2 + i + np1 * j;
+                    int32_t g = m.gmap[s];
+                    double mass = B.w[i] * B.w[j] * 0.25 * m.col_dx[c] * m.col_dy[c];
+                    if (g >= 0) { a[g].push_back(int32_t(s)); mh[g] += mass; }
+                    else {
+                        ah[-g - 1].push_back(int32_t(s));
+                        for (auto& e : rows[s]) mh[e.first] += mass * e.second;
+                    }
+                }
+        m.asm_ptr.assign(size_t(m.n_h) + 1, 0);
+        for (int64_t h = 0; h < m.n_h; ++h) {
+            m.asm_slot.insert(m.asm_slot.end(), a[h].begin(), a[h].end());
+            m.asm_ptr[h + 1] = int32_t(m.asm_slot.size());
+        }
+        m.asmH_ptr.assign(size_t(m.n_hh) + 1, 0);
+        for (int64_t h = 0; h < m.n_hh; ++h) {
+            m.asmH_slot.insert(m.asmH_slot.end(), ah[h].begin(), ah[h].end());
+            m.asmH_ptr[h + 1] = int32_t(m.asmH_slot.size());
+        }
+        m.minv_h.resize(size_t(m.n_h));
+        for (int64_t h = 0; h < m.n_h; ++h) {
+            if (!(mh[h] > 0)) { err = "non-positive assembled mass"; return SEM_ERR_MESH; }
+            m.minv_h[h] = 1.0 / mh[h];
+        }
+    }
+    // sibling families
+    m.sib.assign(size_t(in.n_col) * 4, -1);
+    for (int c = 0; c < in.n_col; ++c) {
+        int l = in.lev[c];
+        if (l == 0) continue;
+        int64_t bx = in.ix[c] & ~int64_t(1), by = in.iy[c] & ~int64_t(1);
+        int32_t ids[4];
+        bool ok = true;
+        for (int q = 0; q < 4 && ok; ++q) {
+            auto it = cmap.find({l, bx + (q & 1), by + (q >> 1)});
+            if (it == cmap.end()) ok = false; else ids[q] = it->second;
+        }
+        if (ok) for (int q = 0; q < 4; ++q) m.sib[size_t(c) * 4 + q] = ids[q];
+    }
+    return SEM_OK;
+}
+
+}  // namespace sem

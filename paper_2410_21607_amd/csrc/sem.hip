@@ -1,0 +1,639 @@
+// HIP kernels and C ABI of the spectral-element right-hand-side library
+// (gfx950).  See include/sem.h for the contract of every entry point.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "devmesh.h"
+#include "mesh_build.h"
+#include "sem.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+#define HIPCHK(x)                                                                   \
+    do {                                                                            \
+        hipError_t e_ = (x);                                                        \
+        if (e_ != hipSuccess)                                                       \
+            return fail(SEM_ERR_HIP, std::string(#x) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr int NF = SEM_NFIELDS;
+
+}  // namespace
+
+using sem::DevMesh;
+
+struct sem_mesh {
+    sem::HostMesh host;
+    DevMesh d{};
+    std::vector<void*> allocs;
+    bool have_ref = false;
+    // workspace for the unfused composition and the fused stage
+    double* ws_hv = nullptr;   // F * n_hh * nzn
+    double* ws_rE = nullptr;   // F * n_local
+    double* ws_acc = nullptr;  // F * n_dof
+    double* ws_c = nullptr;    // F * n_hh * nzn
+    double* ws_r = nullptr;    // F * n_dof
+    int64_t ws_bytes = 0;
+    ~sem_mesh() {
+        for (void* p : allocs) (void)hipFree(p);
+    }
+    template <typename T>
+    int upload(const std::vector<T>& v, const T** dst) {
+        if (v.empty()) { *dst = nullptr; return SEM_OK; }
+        void* p = nullptr;
+        HIPCHK(hipMalloc(&p, v.size() * sizeof(T)));
+        allocs.push_back(p);
+        HIPCHK(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+        ws_bytes += int64_t(v.size() * sizeof(T));
+        *dst = static_cast<const T*>(p);
+        return SEM_OK;
+    }
+    int alloc(size_t bytes, void** dst) {
+        *dst = nullptr;
+        if (bytes == 0) return SEM_OK;
+        HIPCHK(hipMalloc(dst, bytes));
+        allocs.push_back(*dst);
+        ws_bytes += int64_t(bytes);
+        return SEM_OK;
+    }
+};
+
+// ====================================================================== kernels
+namespace sem {
+
+// value of field f at horizontal slot g (unique node or hanging point) and kz,
+// interpolating hanging points through their rows
+__device__ __forceinline__ double node_value(const DevMesh& m, const double* __restrict__ q,
+                                             int g, int f, int kz) {
+    const int64_t fs = int64_t(m.n_h) * m.nzn;
+    if (g >= 0) return q[f * fs + int64_t(g) * m.nzn + kz];
+    const int hh = -g - 1;
+    double s = 0.0;
+    for (int t = m.hang_ptr[hh]; t < m.hang_ptr[hh + 1]; ++t)
+        s += m.hang_w[t] * q[f * fs + int64_t(m.hang_src[t]) * m.nzn + kz];
+    return s;
+}
+
+__global__ void k_nc_scatter(DevMesh m, const double* __restrict__ src, double* __restrict__ dst) {
+    const int64_t n = int64_t(m.n_hh) * m.nzn;
+    const int64_t fs = int64_t(m.n_h) * m.nzn;
+    for (int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; t < n;
+         t += int64_t(gridDim.x) * blockDim.x) {
+        const int hh = int(t / m.nzn), kz = int(t % m.nzn);
+        double s[NF] = {0, 0, 0, 0, 0};
+        for (int r = m.hang_ptr[hh]; r < m.hang_ptr[hh + 1]; ++r) {
+            const double w = m.hang_w[r];
+            const int64_t base = int64_t(m.hang_src[r]) * m.nzn + kz;
+#pragma unroll
+            for (int f = 0; f < NF; ++f) s[f] += w * src[f * fs + base];
+        }
+#pragma unroll
+        for (int f = 0; f < NF; ++f) dst[f * n + t] = s[f];
+    }
+}
+
+__global__ void k_nc_gather(DevMesh m, const double* __restrict__ src, double* __restrict__ dst) {
+    const int64_t n = int64_t(m.n_hT) * m.nzn;
+    const int64_t fs = int64_t(m.n_h) * m.nzn;
+    const int64_t fsh = int64_t(m.n_hh) * m.nzn;
+    for (int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; t < n;
+         t += int64_t(gridDim.x) * blockDim.x) {
+        const int li = int(t / m.nzn), kz = int(t % m.nzn);
+        const int h = m.hT_list[li];
+        double s[NF] = {0, 0, 0, 0, 0};
+        for (int r = m.hT_ptr[li]; r < m.hT_ptr[li + 1]; ++r) {
+            const double w = m.hT_w[r];
+            const int64_t base = int64_t(m.hT_hh[r]) * m.nzn + kz;
+#pragma unroll
+            for (int f = 0; f < NF; ++f) s[f] += w * src[f * fsh + base];
+        }
+        const int64_t o = int64_t(h) * m.nzn + kz;
+#pragma unroll
+        for (int f = 0; f < NF; ++f) dst[f * fs + o] += s[f];
+    }
+}
+
+// Element right-hand side, one workgroup per element, one thread per node.
+template <int NP, typename T>
+__global__ void __launch_bounds__(((NP * NP * NP + 63) / 64) * 64)
+k_rhs(DevMesh m, const double* __restrict__ q, const double* __restrict__ hv,
+      double* __restrict__ rE) {
+    constexpr int NP2 = NP * NP, NP3 = NP2 * NP;
+    constexpr int N = NP - 1;
+    __shared__ T tile[8][NP3];
+    __shared__ T sD[NP2];
+    const int e = blockIdx.x;
+    const int c = e / m.n_z, layer = e - c * m.n_z;
+    const int t = threadIdx.x;
+    if (t < NP2) sD[t] = T(m.D[t]);
+    const int i = t % NP, j = (t / NP) % NP, k = t / NP2;
+    const int kz = layer * N + k;
+    const int64_t fs = int64_t(m.n_h) * m.nzn, fsh = int64_t(m.n_hh) * m.nzn;
+    T rp = 0, u = 0, v = 0, w = 0, tp = 0, rho = 1, rho_p = 0;
+    if (t < NP3) {
+        const int g = m.gmap[c * NP2 + i + NP * j];
+        double x[NF];
+        if (g >= 0) {
+#pragma unroll
+            for (int f = 0; f < NF; ++f) x[f] = q[f * fs + int64_t(g) * m.nzn + kz];
+        } else {
+#pragma unroll
+            for (int f = 0; f < NF; ++f) x[f] = hv[f * fsh + int64_t(-g - 1) * m.nzn + kz];
+        }
+        const double r0 = m.rho0[kz], th0 = m.theta0[kz];
+        rp = T(x[0]); u = T(x[1]); v = T(x[2]); w = T(x[3]); tp = T(x[4]);
+        rho_p = rp;
+        rho = T(r0) + rp;
+        // p' = p0 expm1(gamma (log1p(rho'/rho0) + log1p(theta'/theta0))):
+        // the ideal-gas pressure minus the reference pressure, free of cancellation
+        T pp;
+        if constexpr (sizeof(T) == 8) {
+            pp = m.p0[kz] * expm1(m.gamma * (log1p(x[0] / r0) + log1p(x[4] / th0)));
+        } else {
+            pp = T(m.p0[kz]) * expm1f(T(m.gamma) * (log1pf(rp / T(r0)) + log1pf(tp / T(th0))));
+        }
+        tile[0][t] = rho * u;
+        tile[1][t] = rho * v;
+        tile[2][t] = rho * w;
+        tile[3][t] = u;
+        tile[4][t] = v;
+        tile[5][t] = w;
+        tile[6][t] = pp;
+        tile[7][t] = tp;
+    }
+    __syncthreads();
+    if (t >= NP3) return;
+    const T sx = T(2.0 / m.col_dx[c]), sy = T(2.0 / m.col_dy[c]), sz = T(2.0 / m.dz[layer]);
+    T d[8][3];
+#pragma unroll
+    for (int a = 0; a < 8; ++a) d[a][0] = d[a][1] = d[a][2] = 0;
+#pragma unroll
+    for (int mm = 0; mm < NP; ++mm) {
+        const T dxm = sD[i * NP + mm], dym = sD[j * NP + mm], dzm = sD[k * NP + mm];
+        const int ox = mm + NP * (j + NP * k), oy = i + NP * (mm + NP * k), oz = i + NP * (j + NP * mm);
+#pragma unroll
+        for (int a = 0; a < 8; ++a) {
+            d[a][0] += dxm * tile[a][ox];
+            d[a][1] += dym * tile[a][oy];
+            d[a][2] += dzm * tile[a][oz];
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < 8; ++a) { d[a][0] *= sx; d[a][1] *= sy; d[a][2] *= sz; }
+    const T f = T(m.f), g = T(m.g);
+    const T inv_rho = T(1) / rho;
+    T R[NF];
+    R[0] = -(d[0][0] + d[1][1] + d[2][2]);
+    R[1] = -(u * d[3][0] + v * d[3][1] + w * d[3][2]) - d[6][0] * inv_rho + f * v;
+    R[2] = -(u * d[4][0] + v * d[4][1] + w * d[4][2]) - d[6][1] * inv_rho - f * u;
+    R[3] = -(u * d[5][0] + v * d[5][1] + w * d[5][2]) - d[6][2] * inv_rho - rho_p * inv_rho * g;
+    R[4] = -(u * d[7][0] + v * d[7][1] + w * d[7][2]) - w * T(m.dth0[kz]);
+    const double mass = m.w[i] * m.w[j] * m.w[k] * 0.125 * m.col_dx[c] * m.col_dy[c] * m.dz[layer];
+    const int64_t es = int64_t(m.n_col) * m.n_z * NP3;
+#pragma unroll
+    for (int fld = 0; fld < NF; ++fld) rE[fld * es + int64_t(e) * NP3 + t] = mass * double(R[fld]);
+}
+
+// sum of element contributions at the local copies of (slot-list, kz)
+__device__ __forceinline__ void sum_local(const DevMesh& m, const double* __restrict__ rE,
+                                          const int* __restrict__ slots, int s0, int s1, int kz,
+                                          double* out) {
+    const int np1 = m.N + 1, np2 = np1 * np1, np3 = np2 * np1;
+    const int64_t es = int64_t(m.n_col) * m.n_z * np3;
+    int lay[2], kk[2], nv = 0;
+    if (kz % m.N == 0 && kz > 0 && kz < m.nzn - 1) {
+        lay[0] = kz / m.N - 1; kk[0] = m.N;
+        lay[1] = kz / m.N;     kk[1] = 0;
+        nv = 2;
+    } else {
+        lay[0] = (kz == m.nzn - 1) ? m.n_z - 1 : kz / m.N;
+        kk[0] = kz - lay[0] * m.N;
+        nv = 1;
+    }
+    for (int f = 0; f < NF; ++f) out[f] = 0.0;
+    for (int s = s0; s < s1; ++s) {
+        const int slot = slots[s];
+        const int c = slot / np2, pos = slot - c * np2;
+        for (int a = 0; a < nv; ++a) {
+            const int64_t idx = int64_t(c * m.n_z + lay[a]) * np3 + pos + np2 * kk[a];
+#pragma unroll
+            for (int f = 0; f < NF; ++f) out[f] += rE[f * es + idx];
+        }
+    }
+}
+
+__global__ void k_assemble(DevMesh m, const double* __restrict__ rE, double* __restrict__ acc) {
+    const int64_t n = int64_t(m.n_h) * m.nzn;
+    for (int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; t < n;
+         t += int64_t(gridDim.x) * blockDim.x) {
+        const int h = int(t / m.nzn), kz = int(t % m.nzn);
+        double s[NF];
+        sum_local(m, rE, m.asm_slot, m.asm_ptr[h], m.asm_ptr[h + 1], kz, s);
+#pragma unroll
+        for (int f = 0; f < NF; ++f) acc[f * n + t] = s[f];
+    }
+}
+
+__global__ void k_assemble_hang(DevMesh m, const double* __restrict__ rE, double* __restrict__ cH) {
+    const int64_t n = int64_t(m.n_hh) * m.nzn;
+    for (int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; t < n;
+         t += int64_t(gridDim.x) * blockDim.x) {
+        const int hh = int(t / m.nzn), kz = int(t % m.nzn);
+        double s[NF];
+        sum_local(m, rE, m.asmH_slot, m.asmH_ptr[hh], m.asmH_ptr[hh + 1], kz, s);
+#pragma unroll
+        for (int f = 0; f < NF; ++f) cH[f * n + t] = s[f];
+    }
+}
+
+__global__ void k_finalize(DevMesh m, const double* __restrict__ acc, double* __restrict__ r) {
+    const int64_t n = int64_t(m.n_h) * m.nzn;
+    for (int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; t < n;
+         t += int64_t(gridDim.x) * blockDim.x) {
+        const int h = int(t / m.nzn), kz = int(t % m.nzn);
+        const double minv = m.minv_h[h] * m.minv_v[kz];
+        const bool lid = (kz == 0) || (kz == m.nzn - 1);
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            double v = acc[f * n + t] * minv;
+            if (f == 3 && lid) v = 0.0;
+            r[f * n + t] = v;
+        }
+    }
+}
+
+__global__ void k_update(int64_t n, double a, double b, double c, const double* qn,
+                         const double* qs, const double* r, double* qout) {
+    for (int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; t < n;
+         t += int64_t(gridDim.x) * blockDim.x)
+        qout[t] = a * qn[t] + b * qs[t] + c * r[t];
+}
+
+struct Thr { double v[SEM_MAX_LEVEL]; };
+
+template <int NP>
+__global__ void __launch_bounds__(((NP * NP * NP + 63) / 64) * 64)
+k_amr_elem(DevMesh m, const double* __restrict__ q, int criterion, Thr thr, int lvl_max,
+           int8_t* __restrict__ adapt) {
+    constexpr int NP2 = NP * NP, NP3 = NP2 * NP, N = NP - 1;
+    __shared__ double su[NP3], sv[NP3];
+    __shared__ double red[1024 / 64];
+    const int e = blockIdx.x;
+    const int c = e / m.n_z, layer = e - c * m.n_z;
+    const int t = threadIdx.x;
+    const int i = t % NP, j = (t / NP) % NP, k = t / NP2;
+    const int kz = layer * N + k;
+    double u = 0, v = 0, w = 0;
+    if (t < NP3) {
+        const int g = m.gmap[c * NP2 + i + NP * j];
+        u = node_value(m, q, g, 1, kz);
+        v = node_value(m, q, g, 2, kz);
+        w = node_value(m, q, g, 3, kz);
+        su[t] = u;
+        sv[t] = v;
+    }
+    __syncthreads();
+    double C = -INFINITY;
+    if (t < NP3) {
+        if (criterion == SEM_CRIT_SPEED) {
+            C = sqrt(u * u + v * v + w * w);
+        } else {
+            double vx = 0, uy = 0;
+            for (int mm = 0; mm < NP; ++mm) {
+                vx += m.D[i * NP + mm] * sv[mm + NP * (j + NP * k)];
+                uy += m.D[j * NP + mm] * su[i + NP * (mm + NP * k)];
+            }
+            C = vx * (2.0 / m.col_dx[c]) - uy * (2.0 / m.col_dy[c]);
+        }
+    }
+    // workgroup maximum
+    for (int off = 32; off > 0; off >>= 1) C = fmax(C, __shfl_xor(C, off));
+    if ((t & 63) == 0) red[t >> 6] = C;
+    __syncthreads();
+    if (t == 0) {
+        double cm = red[0];
+        for (int a = 1; a < int(blockDim.x >> 6); ++a) cm = fmax(cm, red[a]);
+        const int lv = m.col_level[c];
+        int8_t flag = 0;
+        if (lv < lvl_max && cm > thr.v[lv]) flag = 1;
+        else if (lv > 0 && cm <= thr.v[lv - 1]) flag = -1;
+        adapt[e] = flag;
+    }
+}
+
+__global__ void k_amr_col(DevMesh m, const int8_t* __restrict__ ae, int8_t* __restrict__ ac) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= m.n_col) return;
+    auto col_state = [&](int cc, bool& any_ref, bool& all_crs) {
+        any_ref = false; all_crs = true;
+        for (int z = 0; z < m.n_z; ++z) {
+            const int8_t a = ae[cc * m.n_z + z];
+            any_ref = any_ref || (a == 1);
+            all_crs = all_crs && (a == -1);
+        }
+    };
+    bool r, cr;
+    col_state(c, r, cr);
+    int8_t out = 0;
+    if (r) out = 1;
+    else if (cr && m.sib[4 * c] >= 0) {
+        bool ok = true;
+        for (int s = 0; s < 4; ++s) {
+            bool r2, c2;
+            col_state(m.sib[4 * c + s], r2, c2);
+            ok = ok && c2 && !r2;
+        }
+        if (ok) out = -1;
+    }
+    ac[c] = out;
+}
+
+}  // namespace sem
+
+// ====================================================================== helpers
+namespace {
+
+int grid_for(int64_t n, int block = 256) {
+    int64_t g = (n + block - 1) / block;
+    if (g < 1) g = 1;
+    if (g > 65536) g = 65536;
+    return int(g);
+}
+
+template <typename T>
+int launch_rhs_t(const sem_mesh* M, const double* q, const double* hv, double* rE, hipStream_t s) {
+    const DevMesh& d = M->d;
+    const int nb = d.n_col * d.n_z;
+    switch (d.N) {
+#define CASE(NN)                                                                             \
+    case NN:                                                                                 \
+        hipLaunchKernelGGL((sem::k_rhs<NN + 1, T>), dim3(nb), dim3((((NN + 1) * (NN + 1) * (NN + 1) + 63) / 64) * 64), 0, s, d, q, hv, rE); \
+        break;
+        CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
+#undef CASE
+        default: return fail(SEM_ERR_N, "unsupported N");
+    }
+    HIPCHK(hipGetLastError());
+    return SEM_OK;
+}
+
+int check_mesh(const sem_mesh* M) {
+    if (!M) return fail(SEM_ERR_ARG, "null mesh");
+    if (!M->have_ref) return fail(SEM_ERR_STATE, "sem_mesh_set_reference has not been called");
+    return SEM_OK;
+}
+
+}  // namespace
+
+static int sem_launch_rhs(const sem_mesh* M, const double* q, const double* hv, double* rE, int prec,
+                   hipStream_t s) {
+    if (prec == SEM_FP64) return launch_rhs_t<double>(M, q, hv, rE, s);
+    if (prec == SEM_FP32) return launch_rhs_t<float>(M, q, hv, rE, s);
+    return fail(SEM_ERR_ARG, "precision must be SEM_FP64 or SEM_FP32");
+}
+
+// ====================================================================== C ABI
+extern "C" {
+
+int sem_internal_compose_stage(const sem_mesh* M, double a, double b, double c, const double* qn,
+                               const double* qs, double* qout, int prec, void* stream);
+
+const char* sem_last_error(void) { return g_err.c_str(); }
+
+int sem_mesh_create(const sem_mesh_desc* desc, sem_mesh** out) {
+    if (!desc || !out) return fail(SEM_ERR_ARG, "null argument");
+    *out = nullptr;
+    sem::MeshInput in{desc->N, desc->nx0, desc->ny0, desc->n_z, desc->n_col,
+                      desc->h_col_level, desc->h_col_ix, desc->h_col_iy, desc->Lx, desc->Ly,
+                      desc->h_z_edges, desc->periodic_x != 0, desc->periodic_y != 0,
+                      desc->f, desc->g, desc->R_d, desc->c_p, desc->p00};
+    std::unique_ptr<sem_mesh> M(new sem_mesh());
+    std::string err;
+    int rc = sem::build_host_mesh(in, M->host, err);
+    if (rc != SEM_OK) return fail(rc, err);
+    const sem::HostMesh& H = M->host;
+    DevMesh& d = M->d;
+    d.N = H.N; d.n_z = H.n_z; d.nzn = H.nzn; d.n_col = H.n_col;
+    d.n_h = int(H.n_h); d.n_hh = int(H.n_hh); d.n_hT = int(H.hT_list.size());
+    d.f = H.f; d.g = H.g;
+    d.gamma = H.c_p / (H.c_p - H.R_d);
+#define UP(vec, field) if ((rc = M->upload(vec, &d.field)) != SEM_OK) return rc;
+    UP(H.gmap, gmap) UP(H.col_dx, col_dx) UP(H.col_dy, col_dy) UP(H.dz, dz)
+    UP(H.hang_ptr, hang_ptr) UP(H.hang_src, hang_src) UP(H.hang_w, hang_w)
+    UP(H.hT_list, hT_list) UP(H.hT_ptr, hT_ptr) UP(H.hT_hh, hT_hh) UP(H.hT_w, hT_w)
+    UP(H.asm_ptr, asm_ptr) UP(H.asm_slot, asm_slot) UP(H.asmH_ptr, asmH_ptr)
+    UP(H.asmH_slot, asmH_slot) UP(H.minv_h, minv_h) UP(H.minv_v, minv_v)
+    UP(H.sib, sib) UP(H.col_level, col_level) UP(H.basis.D, D) UP(H.basis.w, w)
+#undef UP
+    const size_t np3 = size_t(H.np1) * H.np1 * H.np1;
+    const size_t n_dof = size_t(H.n_h) * H.nzn, n_hng = size_t(H.n_hh) * H.nzn;
+    const size_t n_loc = size_t(H.n_col) * H.n_z * np3;
+    void* p;
+    if ((rc = M->alloc(NF * n_hng * 8, &p)) != SEM_OK) return rc; M->ws_hv = (double*)p;
+    if ((rc = M->alloc(NF * n_loc * 8, &p)) != SEM_OK) return rc; M->ws_rE = (double*)p;
+    if ((rc = M->alloc(NF * n_dof * 8, &p)) != SEM_OK) return rc; M->ws_acc = (double*)p;
+    if ((rc = M->alloc(NF * n_hng * 8, &p)) != SEM_OK) return rc; M->ws_c = (double*)p;
+    if ((rc = M->alloc(NF * n_dof * 8, &p)) != SEM_OK) return rc; M->ws_r = (double*)p;
+    *out = M.release();
+    return SEM_OK;
+}
+
+int sem_mesh_plan(const sem_mesh_desc* desc, sem_mesh_info* o, double* hxy, double* hhxy, double* z,
+                  double* mass) {
+    if (!desc || !o) return fail(SEM_ERR_ARG, "null argument");
+    sem::MeshInput in{desc->N, desc->nx0, desc->ny0, desc->n_z, desc->n_col,
+                      desc->h_col_level, desc->h_col_ix, desc->h_col_iy, desc->Lx, desc->Ly,
+                      desc->h_z_edges, desc->periodic_x != 0, desc->periodic_y != 0,
+                      desc->f, desc->g, desc->R_d, desc->c_p, desc->p00};
+    sem::HostMesh H;
+    std::string err;
+    int rc = sem::build_host_mesh(in, H, err);
+    if (rc != SEM_OK) return fail(rc, err);
+    o->N = H.N; o->n_z = H.n_z; o->nzn = H.nzn; o->max_level = H.max_level;
+    o->n_col = H.n_col; o->n_elem = int64_t(H.n_col) * H.n_z;
+    o->n_h = H.n_h; o->n_hh = H.n_hh;
+    o->n_dof = H.n_h * H.nzn; o->n_hang = H.n_hh * H.nzn;
+    o->n_local = o->n_elem * H.np1 * H.np1 * H.np1;
+    o->workspace_bytes = 0;
+    if (hxy) std::memcpy(hxy, H.h_xy.data(), H.h_xy.size() * sizeof(double));
+    if (hhxy) std::memcpy(hhxy, H.hh_xy.data(), H.hh_xy.size() * sizeof(double));
+    if (z) std::memcpy(z, H.zn.data(), H.zn.size() * sizeof(double));
+    if (mass)
+        for (int64_t h = 0; h < H.n_h; ++h)
+            for (int kz = 0; kz < H.nzn; ++kz)
+                mass[h * H.nzn + kz] = 1.0 / (H.minv_h[h] * H.minv_v[kz]);
+    return SEM_OK;
+}
+
+int sem_mesh_destroy(sem_mesh* mesh) {
+    if (!mesh) return fail(SEM_ERR_ARG, "null mesh");
+    delete mesh;
+    return SEM_OK;
+}
+
+int sem_mesh_get_info(const sem_mesh* M, sem_mesh_info* o) {
+    if (!M || !o) return fail(SEM_ERR_ARG, "null argument");
+    const sem::HostMesh& H = M->host;
+    o->N = H.N; o->n_z = H.n_z; o->nzn = H.nzn; o->max_level = H.max_level;
+    o->n_col = H.n_col; o->n_elem = int64_t(H.n_col) * H.n_z;
+    o->n_h = H.n_h; o->n_hh = H.n_hh;
+    o->n_dof = H.n_h * H.nzn; o->n_hang = H.n_hh * H.nzn;
+    o->n_local = o->n_elem * H.np1 * H.np1 * H.np1;
+    o->workspace_bytes = M->ws_bytes;
+    return SEM_OK;
+}
+
+int sem_mesh_coords(const sem_mesh* M, double* hxy, double* hhxy, double* z) {
+    if (!M) return fail(SEM_ERR_ARG, "null mesh");
+    const sem::HostMesh& H = M->host;
+    if (hxy) std::memcpy(hxy, H.h_xy.data(), H.h_xy.size() * sizeof(double));
+    if (hhxy) std::memcpy(hhxy, H.hh_xy.data(), H.hh_xy.size() * sizeof(double));
+    if (z) std::memcpy(z, H.zn.data(), H.zn.size() * sizeof(double));
+    return SEM_OK;
+}
+
+int sem_mesh_set_reference(sem_mesh* M, const double* rho0, const double* theta0,
+                           const double* dth0) {
+    if (!M || !rho0 || !theta0 || !dth0) return fail(SEM_ERR_ARG, "null argument");
+    const sem::HostMesh& H = M->host;
+    std::vector<double> r(rho0, rho0 + H.nzn), t(theta0, theta0 + H.nzn), dt(dth0, dth0 + H.nzn),
+        p0(H.nzn);
+    const double gam = H.c_p / (H.c_p - H.R_d);
+    for (int k = 0; k < H.nzn; ++k) {
+        if (!(r[k] > 0) || !(t[k] > 0)) return fail(SEM_ERR_ARG, "reference state must be positive");
+        p0[k] = H.p00 * std::pow(H.R_d * r[k] * t[k] / H.p00, gam);
+    }
+    if (M->have_ref) {
+        HIPCHK(hipMemcpy((void*)M->d.rho0, r.data(), H.nzn * 8, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy((void*)M->d.theta0, t.data(), H.nzn * 8, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy((void*)M->d.dth0, dt.data(), H.nzn * 8, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy((void*)M->d.p0, p0.data(), H.nzn * 8, hipMemcpyHostToDevice));
+    } else {
+        int rc;
+        if ((rc = M->upload(r, &M->d.rho0)) != SEM_OK) return rc;
+        if ((rc = M->upload(t, &M->d.theta0)) != SEM_OK) return rc;
+        if ((rc = M->upload(dt, &M->d.dth0)) != SEM_OK) return rc;
+        if ((rc = M->upload(p0, &M->d.p0)) != SEM_OK) return rc;
+        M->have_ref = true;
+    }
+    return SEM_OK;
+}
+
+int sem_nc_project(const sem_mesh* M, int dir, const double* src, double* dst, void* stream) {
+    if (!M) return fail(SEM_ERR_ARG, "null mesh");
+    if (dir != SEM_SCATTER && dir != SEM_GATHER) return fail(SEM_ERR_ARG, "bad direction");
+    const DevMesh& d = M->d;
+    if (d.n_hh == 0) return SEM_OK;
+    if (!src || !dst) return fail(SEM_ERR_ARG, "null array");
+    hipStream_t s = (hipStream_t)stream;
+    if (dir == SEM_SCATTER)
+        hipLaunchKernelGGL(sem::k_nc_scatter, dim3(grid_for(int64_t(d.n_hh) * d.nzn)), dim3(256), 0, s, d, src, dst);
+    else
+        hipLaunchKernelGGL(sem::k_nc_gather, dim3(grid_for(int64_t(d.n_hT) * d.nzn)), dim3(256), 0, s, d, src, dst);
+    HIPCHK(hipGetLastError());
+    return SEM_OK;
+}
+
+int sem_rhs(const sem_mesh* M, const double* q, const double* hv, double* rE, int prec, void* stream) {
+    int rc = check_mesh(M);
+    if (rc != SEM_OK) return rc;
+    if (!q || !rE || (M->d.n_hh > 0 && !hv)) return fail(SEM_ERR_ARG, "null array");
+    return sem_launch_rhs(M, q, hv, rE, prec, (hipStream_t)stream);
+}
+
+int sem_dss(const sem_mesh* M, int phase, const double* rE, double* acc, double* c, double* r,
+            void* stream) {
+    if (!M) return fail(SEM_ERR_ARG, "null mesh");
+    const DevMesh& d = M->d;
+    hipStream_t s = (hipStream_t)stream;
+    if (phase == SEM_ASSEMBLE) {
+        if (!rE || !acc || (d.n_hh > 0 && !c)) return fail(SEM_ERR_ARG, "null array");
+        hipLaunchKernelGGL(sem::k_assemble, dim3(grid_for(int64_t(d.n_h) * d.nzn)), dim3(256), 0, s, d, rE, acc);
+        if (d.n_hh > 0)
+            hipLaunchKernelGGL(sem::k_assemble_hang, dim3(grid_for(int64_t(d.n_hh) * d.nzn)), dim3(256), 0, s, d, rE, c);
+    } else if (phase == SEM_FINALIZE) {
+        if (!acc || !r) return fail(SEM_ERR_ARG, "null array");
+        hipLaunchKernelGGL(sem::k_finalize, dim3(grid_for(int64_t(d.n_h) * d.nzn)), dim3(256), 0, s, d, acc, r);
+    } else {
+        return fail(SEM_ERR_ARG, "bad phase");
+    }
+    HIPCHK(hipGetLastError());
+    return SEM_OK;
+}
+
+int sem_stage_update(const sem_mesh* M, double a, double b, double c, const double* qn,
+                     const double* qs, const double* r, double* qout, void* stream) {
+    if (!M) return fail(SEM_ERR_ARG, "null mesh");
+    if (!qn || !qs || !r || !qout) return fail(SEM_ERR_ARG, "null array");
+    const int64_t n = int64_t(NF) * M->d.n_h * M->d.nzn;
+    hipLaunchKernelGGL(sem::k_update, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)stream, n, a, b, c,
+                       qn, qs, r, qout);
+    HIPCHK(hipGetLastError());
+    return SEM_OK;
+}
+
+int sem_stage(const sem_mesh* M, double a, double b, double c, const double* qn, const double* qs,
+              double* qout, int prec, void* stream) {
+    int rc = check_mesh(M);
+    if (rc != SEM_OK) return rc;
+    if (!qn || !qs || !qout) return fail(SEM_ERR_ARG, "null array");
+    if (qout == qs || qout == qn) return fail(SEM_ERR_ARG, "qout must not alias qs or qn");
+    if (prec != SEM_FP64 && prec != SEM_FP32) return fail(SEM_ERR_ARG, "bad precision");
+    return sem_internal_compose_stage(M, a, b, c, qn, qs, qout, prec, stream);
+}
+
+int amr_flag(const sem_mesh* M, const double* q, int criterion, const double* thr, int lvl_max,
+             int8_t* ae, int8_t* ac, void* stream) {
+    if (!M) return fail(SEM_ERR_ARG, "null mesh");
+    if (!q || !ae || !ac) return fail(SEM_ERR_ARG, "null array");
+    if (criterion != SEM_CRIT_SPEED && criterion != SEM_CRIT_VORTZ) return fail(SEM_ERR_ARG, "bad criterion");
+    if (lvl_max < 0 || lvl_max > SEM_MAX_LEVEL) return fail(SEM_ERR_ARG, "lvl_max out of range");
+    if (lvl_max > 0 && !thr) return fail(SEM_ERR_ARG, "null thresholds");
+    sem::Thr T{};
+    for (int l = 0; l < lvl_max; ++l) {
+        T.v[l] = thr[l];
+        if (l > 0 && thr[l] < thr[l - 1]) return fail(SEM_ERR_ARG, "thresholds must be non-decreasing");
+    }
+    const DevMesh& d = M->d;
+    hipStream_t s = (hipStream_t)stream;
+    const int nb = d.n_col * d.n_z;
+    switch (d.N) {
+#define CASE(NN)                                                                        \
+    case NN:                                                                            \
+        hipLaunchKernelGGL((sem::k_amr_elem<NN + 1>), dim3(nb), dim3((((NN + 1) * (NN + 1) * (NN + 1) + 63) / 64) * 64), 0, s, d, q, criterion, T, lvl_max, ae); \
+        break;
+        CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
+#undef CASE
+        default: return fail(SEM_ERR_N, "unsupported N");
+    }
+    hipLaunchKernelGGL(sem::k_amr_col, dim3((d.n_col + 255) / 256), dim3(256), 0, s, d, ae, ac);
+    HIPCHK(hipGetLastError());
+    return SEM_OK;
+}
+
+// Internal entry used by the fused-stage fallback composition.
+int sem_internal_compose_stage(const sem_mesh* M, double a, double b, double c, const double* qn,
+                               const double* qs, double* qout, int prec, void* stream) {
+    int rc;
+    if ((rc = sem_nc_project(M, SEM_SCATTER, qs, M->ws_hv, stream)) != SEM_OK) return rc;
+    if ((rc = sem_rhs(M, qs, M->ws_hv, M->ws_rE, prec, stream)) != SEM_OK) return rc;
+    if ((rc = sem_dss(M, SEM_ASSEMBLE, M->ws_rE, M->ws_acc, M->ws_c, nullptr, stream)) != SEM_OK) return rc;
+    if ((rc = sem_nc_project(M, SEM_GATHER, M->ws_c, M->ws_acc, stream)) != SEM_OK) return rc;
+    if ((rc = sem_dss(M, SEM_FINALIZE, nullptr, M->ws_acc, nullptr, M->ws_r, stream)) != SEM_OK) return rc;
+    return sem_stage_update(M, a, b, c, qn, qs, M->ws_r, qout, stream);
+}
+
+}  // extern "C"

@@ -16,7 +16,8 @@ and a linear vertical decay Zv = max(0, 1 - z/z_v).  The pressure perturbation
 is in gradient-wind balance with the reference density,
 dp'/dr = rho0(z) (v^2/r + f v), integrated inward from r = L/2 where p' = 0;
 the density perturbation is hydrostatic, rho' = -(1/g) dp'/dz; theta' follows
-from the ideal-gas state (rho0 + rho', p0 + p'), plus seeded uniform noise.
+from the ideal-gas state (rho0 + rho', p0 + p'), plus seeded uniform noise
+applied at fixed pressure (the density compensates).
 """
 
 import numpy as np
@@ -115,8 +116,13 @@ def initial_state(xyz, bg_fn, vortex, phys, noise_amp, noise_ztop, seed, Lx, Ly)
     theta = p00 / (R_d * rho) * (p / p00) ** (c_v / c_p)
     theta_p = theta - bg["theta0"]
     if noise_amp > 0.0:
+        # perturb theta at fixed pressure: rho theta stays fixed, so the noise
+        # is a buoyancy perturbation and not a pressure (acoustic) one
         U = noise.uniform01(xyz, Lx, Ly, seed)
         mask = z <= noise_ztop + 1e-6
-        theta_p = theta_p + np.where(mask, noise_amp * (2.0 * U - 1.0), 0.0)
+        dth = np.where(mask, noise_amp * (2.0 * U - 1.0), 0.0)
+        rho_new = rho * theta / (theta + dth)
+        rho_p = rho_new - bg["rho0"]
+        theta_p = theta_p + dth
     w = np.zeros_like(u)
     return np.stack([rho_p, u, v, w, theta_p])

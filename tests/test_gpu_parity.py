@@ -1,0 +1,244 @@
+"""GPU parity: every C-ABI call against the FP64 oracle on the same seeded
+inputs (uniform, two-level and three-level meshes, N from 3 to 8, ragged
+element counts).  Bar: floor-scaled relative L2 <= 1e-12 per field in FP64;
+bit-exact refinement flags."""
+
+import sys
+
+import numpy as np
+import pytest
+
+from harness import _keys, match, oracle_mesh, oracle_reference_local
+from oracle import amr as oamr
+from oracle import assembly, euler, metrics, timestep
+from synth import cases
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+
+CASES = [("vortex_8x8x4_n4", {}), ("small_uniform", {"N": 3}), ("small_amr2", {}),
+         ("small_amr2", {"N": 7}), ("small_amr3", {}), ("small_amr3", {"N": 7}),
+         ("small_amr2", {"N": 8}), ("small_amr3", {"N": 5, "periodic": False})]
+IDS = [f"{n}-{'-'.join(f'{k}{v}' for k, v in kw.items())}" for n, kw in CASES]
+
+_CACHE = {}
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+class Setup:
+    def __init__(self, name, kw):
+        import torch
+        from paper_2410_21607_amd import api
+        self.torch, self.api = torch, api
+        self.c = c = cases.get(name, **dict(kw))
+        self.gm = api.Mesh.from_case(c)
+        hxy, hhxy, z = self.gm.coords()
+        bg = cases.reference_state(c, z)
+        self.gm.set_reference(bg["rho0"], bg["theta0"], bg["dtheta0dz"])
+        self.om = oracle_mesh(c)
+        self.gxyz = self.gm.node_xyz()
+        self.perm = match(self.om.node_xyz, self.gxyz, c)
+        self.q_or = cases.initial_state(c, self.om.node_xyz)
+        # the synthetic field evaluated at the GPU's own node positions agrees
+        # to round-off; the parity runs feed both sides bit-identical values
+        # (the oracle-position field permuted into the GPU numbering), since
+        # the right-hand side amplifies ulp-level input differences through
+        # the hydrostatic and gradient-wind cancellations
+        q_g = cases.initial_state(c, self.gxyz)
+        np.testing.assert_allclose(q_g, self.q_or[:, self.perm], rtol=1e-12, atol=1e-12)
+        self.q_g = torch.tensor(np.ascontiguousarray(self.q_or[:, self.perm]).reshape(-1),
+                                dtype=torch.float64, device="cuda")
+        self.ref = oracle_reference_local(c, self.om)
+
+    def to_oracle_order(self, flat):
+        a = flat.detach().cpu().numpy().reshape(5, -1)
+        out = np.empty_like(a)
+        out[:, self.perm] = a
+        return out
+
+
+def get(name, kw):
+    key = (name, tuple(sorted(kw.items())))
+    if key not in _CACHE:
+        _CACHE[key] = Setup(name, kw)
+    return _CACHE[key]
+
+
+@pytest.mark.parametrize("name,kw", CASES, ids=IDS)
+def test_nc_scatter(name, kw):
+    S = get(name, kw)
+    if S.gm.n_hang == 0:
+        pytest.skip("conforming mesh")
+    torch, api = S.torch, S.api
+    say("nc_scatter", name, kw)
+    hv = torch.zeros(5 * S.gm.n_hang, dtype=torch.float64, device="cuda")
+    api.sem_nc_project(S.gm, api.SEM_SCATTER, S.q_g, hv)
+    torch.cuda.synchronize()
+    qL = assembly.scatter(S.om, S.q_or).reshape(5, -1)
+    oh = np.column_stack([S.om.xl.ravel(), S.om.yl.ravel(), S.om.zl.ravel()])[S.om.hanging]
+    _, first = np.unique(_keys(oh, S.c), axis=0, return_index=True)
+    hidx = np.nonzero(S.om.hanging)[0][first]
+    perm = match(oh[first], S.gm.hang_xyz(), S.c)
+    got = hv.cpu().numpy().reshape(5, -1)
+    want = qL[:, hidx][:, perm]
+    err = metrics.rel_l2(got, want, metrics.STATE_FLOORS)
+    say("  rel", err)
+    assert err.max() <= TOL64
+
+
+def _element_contrib(S):
+    """Oracle m_L R_L in element/local order (E, (N+1)^3) per field."""
+    qL = assembly.scatter(S.om, S.q_or)
+    RL = euler.element_rhs(S.om, qL, S.ref["rho0"], S.ref["theta0"], S.ref["dtheta0dz"],
+                           S.c["phys"])
+    return RL.reshape(5, -1) * S.om.mL[None, :]
+
+
+@pytest.mark.parametrize("name,kw", CASES, ids=IDS)
+def test_rhs_element_contributions(name, kw):
+    S = get(name, kw)
+    torch, api = S.torch, S.api
+    say("sem_rhs", name, kw)
+    hv = torch.zeros(max(5 * S.gm.n_hang, 1), dtype=torch.float64, device="cuda")[: 5 * S.gm.n_hang]
+    if S.gm.n_hang:
+        api.sem_nc_project(S.gm, api.SEM_SCATTER, S.q_g, hv)
+    rE = torch.zeros(5 * S.gm.n_local, dtype=torch.float64, device="cuda")
+    api.sem_rhs(S.gm, S.q_g, hv if S.gm.n_hang else None, rE, api.SEM_FP64)
+    torch.cuda.synchronize()
+    want = _element_contrib(S)
+    got = rE.cpu().numpy().reshape(5, -1)
+    floors = metrics.RHS_FLOORS * S.om.mL.mean()
+    err = metrics.rel_l2(got, want, floors)
+    say("  rel", err)
+    assert err.max() <= TOL64
+
+
+def _gpu_rhs(S, prec):
+    torch, api = S.torch, S.api
+    n, nh, nl = 5 * S.gm.n_dof, 5 * S.gm.n_hang, 5 * S.gm.n_local
+    z = lambda k: torch.zeros(k, dtype=torch.float64, device="cuda")
+    hv, rE, acc, cH, r = z(nh), z(nl), z(n), z(nh), z(n)
+    if nh:
+        api.sem_nc_project(S.gm, api.SEM_SCATTER, S.q_g, hv)
+    api.sem_rhs(S.gm, S.q_g, hv if nh else None, rE, prec)
+    api.sem_dss(S.gm, api.SEM_ASSEMBLE, rE=rE, acc=acc, c=cH if nh else None)
+    if nh:
+        api.sem_nc_project(S.gm, api.SEM_GATHER, cH, acc)
+    api.sem_dss(S.gm, api.SEM_FINALIZE, acc=acc, r=r)
+    torch.cuda.synchronize()
+    return r
+
+
+@pytest.mark.parametrize("name,kw", CASES, ids=IDS)
+def test_full_rhs_through_dss(name, kw):
+    S = get(name, kw)
+    say("rhs+dss", name, kw)
+    r = _gpu_rhs(S, S.api.SEM_FP64)
+    want = assembly.rhs(S.om, S.q_or, S.ref, S.c["phys"])
+    err = metrics.rel_l2(S.to_oracle_order(r), want, metrics.RHS_FLOORS)
+    say("  rel", err)
+    assert err.max() <= TOL64
+
+
+@pytest.mark.parametrize("name,kw", CASES[:3] + CASES[4:6], ids=IDS[:3] + IDS[4:6])
+def test_fp32_rhs_error(name, kw):
+    """FP32 element arithmetic against the FP64 oracle, floor-scaled."""
+    S = get(name, kw)
+    say("rhs fp32", name, kw)
+    r = _gpu_rhs(S, S.api.SEM_FP32)
+    want = assembly.rhs(S.om, S.q_or, S.ref, S.c["phys"])
+    err = metrics.rel_l2(S.to_oracle_order(r), want, metrics.RHS_FLOORS)
+    say("  rel fp32", err)
+    assert err.max() <= 1e-4
+
+
+@pytest.mark.parametrize("name,kw", CASES, ids=IDS)
+def test_stages_match_oracle(name, kw):
+    S = get(name, kw)
+    torch, api = S.torch, S.api
+    nst = S.c["stages"]
+    dt = S.c["dt"]
+    say("stages", name, kw, nst)
+    qn = S.q_g.clone()
+    qs = S.q_g.clone()
+    out = torch.empty_like(qn)
+    for st in range(nst):
+        a, b, cc = timestep.stage_coefficients(st % 3, dt)
+        api.sem_stage(S.gm, a, b, cc, qn, qs, out, api.SEM_FP64)
+        qs, out = out, qs
+        if st % 3 == 2:
+            qn.copy_(qs)
+    torch.cuda.synchronize()
+    rhs = lambda q: assembly.rhs(S.om, q, S.ref, S.c["phys"])
+    want, _ = timestep.run_stages(rhs, S.q_or, dt, nst)
+    err = metrics.rel_l2(S.to_oracle_order(qs), want, metrics.STATE_FLOORS)
+    say("  rel", err)
+    assert err.max() <= TOL64
+
+
+def test_stage_update_elementwise():
+    S = get(*CASES[0])
+    torch, api = S.torch, S.api
+    say("stage_update")
+    n = 5 * S.gm.n_dof
+    g = torch.Generator(device="cuda").manual_seed(5)
+    qn, qs, r = (torch.rand(n, dtype=torch.float64, device="cuda", generator=g) for _ in range(3))
+    out = torch.empty_like(qn)
+    api.sem_stage_update(S.gm, 0.75, 0.25, 0.1, qn, qs, r, out)
+    torch.cuda.synchronize()
+    want = 0.75 * qn.cpu().numpy() + 0.25 * qs.cpu().numpy() + 0.1 * r.cpu().numpy()
+    np.testing.assert_allclose(out.cpu().numpy(), want, rtol=1e-15, atol=1e-15)
+
+
+@pytest.mark.parametrize("name,kw", [CASES[0], CASES[2], CASES[4], CASES[5]],
+                         ids=[IDS[0], IDS[2], IDS[4], IDS[5]])
+@pytest.mark.parametrize("criterion", [0, 1])
+def test_amr_flag_bit_exact(name, kw, criterion):
+    S = get(name, kw)
+    torch, api = S.torch, S.api
+    say("amr_flag", name, kw, criterion)
+    qL = assembly.scatter(S.om, S.q_or)
+    C = oamr.criterion_speed(qL) if criterion == 0 else oamr.criterion_vorticity(S.om, qL)
+    cmax = np.sort(C.reshape(S.om.n_elem, -1).max(axis=1))
+    lvl = S.om.e_level
+    lvl_max = int(lvl.max()) + 1
+    # thresholds half-way across gaps between element maxima that are wide
+    # compared with round-off (symmetric elements have maxima equal up to a
+    # few ulps, and a cut between those would test rounding, not the rule)
+    scale = np.abs(cmax).max()
+    gaps = np.nonzero(np.diff(cmax) > 1e-8 * scale)[0]
+    picks = np.linspace(0.2, 0.8, lvl_max)
+    sel = gaps[np.clip((picks * (len(gaps) - 1)).astype(int), 0, len(gaps) - 1)]
+    thr = np.sort(0.5 * (cmax[sel] + cmax[sel + 1]))
+    ef = oamr.element_flags(C.reshape(S.om.n_elem, -1), lvl, thr, lvl_max)
+    cf = oamr.column_flags(ef, S.c["columns"], S.om.n_z)
+    ae = torch.zeros(S.gm.info["n_elem"], dtype=torch.int8, device="cuda")
+    ac = torch.zeros(S.gm.info["n_col"], dtype=torch.int8, device="cuda")
+    api.amr_flag(S.gm, S.q_g, criterion, thr, lvl_max, ae, ac)
+    torch.cuda.synchronize()
+    assert np.array_equal(ae.cpu().numpy(), ef)
+    assert np.array_equal(ac.cpu().numpy(), cf)
+    assert len(set(ef.tolist())) >= 2
+
+
+def test_api_rejects_bad_calls():
+    S = get(*CASES[0])
+    torch, api = S.torch, S.api
+    from paper_2410_21607_amd.native import SemError
+    say("bad calls")
+    q = S.q_g
+    with pytest.raises(SemError):
+        api.sem_stage(S.gm, 0.0, 1.0, 1.0, q, q, q, api.SEM_FP64)   # aliasing
+    with pytest.raises(SemError):
+        api.sem_stage(S.gm, 0.0, 1.0, 1.0, q, q.clone(), torch.empty_like(q), 7)
+    with pytest.raises(SemError):
+        api.amr_flag(S.gm, q, 0, [2.0, 1.0], 2,
+                     torch.zeros(S.gm.info["n_elem"], dtype=torch.int8, device="cuda"),
+                     torch.zeros(S.gm.info["n_col"], dtype=torch.int8, device="cuda"))
+    with pytest.raises(ValueError):
+        api.sem_stage(S.gm, 0.0, 1.0, 1.0, q[:-1], q.clone(), torch.empty_like(q))

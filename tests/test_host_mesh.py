@@ -1,0 +1,115 @@
+"""CPU checks of the C ABI: the library loads and exports every declared
+symbol, and the host-side mesh construction (numbering, hanging points,
+assembled lumped mass) agrees with the oracle's geometric construction."""
+
+import os
+import re
+
+import numpy as np
+import pytest
+
+from harness import match, oracle_mesh
+from synth import cases, columns
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+native = pytest.importorskip("paper_2410_21607_amd.native")
+
+
+def _lib():
+    if not os.path.exists(native.LIB_PATH):
+        pytest.skip("libsem.so not built")
+    return native.lib()
+
+
+def test_exports_every_declared_symbol():
+    L = _lib()
+    text = open(os.path.join(ROOT, "include", "sem.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = set(re.findall(r"^\s*(?:int|const char\s*\*)\s*\*?\s*(\w+)\s*\(", text, flags=re.M))
+    assert {"sem_mesh_create", "sem_rhs", "sem_dss", "sem_nc_project", "sem_stage_update",
+            "sem_stage", "amr_flag"} <= names
+    for n in names:
+        assert hasattr(L, n), n
+        assert n in native.SIGNATURES, n
+
+
+CASES = [("vortex_8x8x4_n4", {}), ("small_uniform", {"N": 3}), ("small_amr2", {}),
+         ("small_amr2", {"N": 7}), ("small_amr3", {}), ("small_amr3", {"N": 7}),
+         ("small_amr3", {"periodic": False}), ("small_amr3", {"periodic": False, "N": 5}),
+         ("small_amr2", {"N": 1}), ("small_amr2", {"N": 8})]
+
+
+@pytest.mark.parametrize("name,kw", CASES)
+def test_plan_matches_oracle(name, kw):
+    _lib()
+    from paper_2410_21607_amd.api import sem_mesh_plan
+    c = cases.get(name, **kw)
+    info, hxy, hhxy, z, mass = sem_mesh_plan(c)
+    om = oracle_mesh(c)
+    assert info["n_dof"] == om.n_dof
+    assert info["n_hang"] == om.n_hang_points
+    nzn = z.size
+    gxyz = np.column_stack([np.repeat(hxy[:, 0], nzn), np.repeat(hxy[:, 1], nzn), np.tile(z, len(hxy))])
+    perm = match(om.node_xyz, gxyz, c)
+    np.testing.assert_allclose(mass, om.MG[perm], rtol=1e-13)
+    if info["n_hh"]:
+        hxyz = np.column_stack([np.repeat(hhxy[:, 0], nzn), np.repeat(hhxy[:, 1], nzn),
+                                np.tile(z, len(hhxy))])
+        oh = np.column_stack([om.xl.ravel(), om.yl.ravel(), om.zl.ravel()])[om.hanging]
+        # collapse oracle hanging points shared by two elements
+        from harness import _keys
+        k = _keys(oh, c)
+        _, first = np.unique(k, axis=0, return_index=True)
+        match(oh[first], hxyz, c)
+
+
+def test_amr_workload_counts():
+    """The two-level vortex workload refines the columns around the core."""
+    _lib()
+    from paper_2410_21607_amd.api import sem_mesh_plan
+    c = cases.get("amr2_64x64x8_n4")
+    info = sem_mesh_plan(c)[0]
+    lev = c["columns"][:, 0]
+    n_ref = int((lev == 1).sum()) // 4
+    assert 150 < n_ref < 400
+    assert info["n_col"] == 64 * 64 + 3 * n_ref
+
+
+def _desc_case(**over):
+    c = cases.get("small_amr2")
+    c.update(over)
+    return c
+
+
+@pytest.mark.parametrize("bad,code", [
+    ("overlap", -3), ("gap", -3), ("balance", -3), ("order", -2), ("index", -3)])
+def test_plan_rejects_bad_layouts(bad, code):
+    _lib()
+    from paper_2410_21607_amd.api import sem_mesh_plan
+    c = cases.get("small_amr2")
+    cols = c["columns"].copy()
+    if bad == "overlap":
+        cols = np.vstack([cols, [[0, 0, 0]]])
+        cols = np.vstack([cols, [[1, 0, 0]]])
+    elif bad == "gap":
+        cols = cols[1:]
+    elif bad == "balance":
+        # level-0 cell (1,1) split into level-1 children, and child (2,2) split
+        # again: level-2 columns then touch level-0 columns
+        cols = [[0, x, y] for x in range(6) for y in range(6) if (x, y) != (1, 1)]
+        cols += [[1, 2 + a, 2 + b] for a in (0, 1) for b in (0, 1) if (a, b) != (0, 0)]
+        cols += [[2, 4 + a, 4 + b] for a in (0, 1) for b in (0, 1)]
+        cols = np.array(cols)
+    elif bad == "order":
+        c["N"] = 9
+    elif bad == "index":
+        cols = cols.copy()
+        cols[0, 1] = 99
+    c["columns"] = cols
+    with pytest.raises(native.SemError) as ei:
+        sem_mesh_plan(c)
+    assert ei.value.code == code
+    msg = {"overlap": "overlap", "gap": "cover", "balance": "2:1", "order": "N must",
+           "index": "out of range"}[bad]
+    assert msg in str(ei.value)
