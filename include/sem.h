@@ -169,12 +169,26 @@ int sem_stage_update(const sem_mesh *mesh, double a, double b, double c,
 
 /* Fused stage: d_qout = a*d_qn + b*d_qs + c*R(d_qs), with R the full
  * right-hand side (scatter, element RHS, assembly, gather, finalize) evaluated
- * in one pass over the columns of every refinement level.  d_qout must not
- * alias d_qs or d_qn.  Uses the handle's workspace; concurrent calls on one
- * handle race. */
+ * in one launch over the columns of every refinement level, which finishes
+ * every node owned by a single column in place, followed by a small launch
+ * that finishes the nodes shared between columns from their per-column
+ * partial sums (fixed summation order: results are deterministic).
+ * d_qout must not alias d_qs or d_qn.  Uses the handle's partial buffer, so
+ * calls on one handle must not overlap.  Allocates nothing; two kernel nodes
+ * when captured in a HIP graph. */
 int sem_stage(const sem_mesh *mesh, double a, double b, double c,
               const double *d_qn, const double *d_qs, double *d_qout,
               int precision, void *stream);
+
+/* Work decomposition of sem_stage (chosen by the autotuner, or by hand):
+ * layers_per_chunk = stacked elements handled by one workgroup, one thread per
+ * unique node of the chunk ((N+1)^2 (layers_per_chunk N + 1) threads).
+ * 0 = default (the deepest chunk of at most 512 threads).  Supported: 1, 2, 4,
+ * 8 where the workgroup stays within 1024 threads and 64 KB of LDS.  Rebuilds
+ * the handle's fused tables and synchronises the device.  sem_stage_get_tune
+ * reports the current value. */
+int sem_stage_tune(sem_mesh *mesh, int layers_per_chunk);
+int sem_stage_get_tune(const sem_mesh *mesh, int *layers_per_chunk);
 
 /* Refinement flags (Section 4.1).  Criterion C at every node of every element
  * from element-local values: SEM_CRIT_SPEED |u| or SEM_CRIT_VORTZ dv/dx-du/dy.

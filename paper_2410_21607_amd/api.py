@@ -207,3 +207,13 @@ def amr_flag(mesh, q, criterion, thresholds, lvl_max, adapt_elem, adapt_col, str
                 int(criterion), thr.ctypes.data_as(native.c_dp) if thr.size else None,
                 int(lvl_max), _ptr(adapt_elem, torch.int8, mesh.info["n_elem"], "adapt_elem"),
                 _ptr(adapt_col, torch.int8, mesh.info["n_col"], "adapt_col"), _stream(stream))
+
+
+def sem_stage_tune(mesh, layers_per_chunk=0):
+    native.call("sem_stage_tune", mesh.handle, int(layers_per_chunk))
+
+
+def sem_stage_get_tune(mesh):
+    a = ctypes.c_int()
+    native.call("sem_stage_get_tune", mesh.handle, ctypes.byref(a))
+    return a.value

@@ -12,6 +12,7 @@ struct DevMesh {
     double f, g, gamma;
     const int32_t* gmap;      // n_col*(N+1)^2: h >= 0, or -(hh+1)
     const double *col_dx, *col_dy, *dz;
+    const double *col_sx, *col_sy, *sz;   // 2/dx, 2/dy per column, 2/dz per layer
     const int32_t *hang_ptr, *hang_src;
     const double* hang_w;
     const int32_t *hT_list, *hT_ptr, *hT_hh;

@@ -253,6 +253,8 @@ int build_host_mesh(const MeshInput& in, HostMesh& m, std::string& err) {
         m.col_dx[c] = wx; m.col_dy[c] = wy;
         m.col_x0[c] = -0.5 * in.Lx + in.ix[c] * wx;
         m.col_y0[c] = -0.5 * in.Ly + in.iy[c] * wy;
+        m.col_sx.push_back(2.0 / wx);
+        m.col_sy.push_back(2.0 / wy);
     }
     // ---- interior LGL positions must not meet the lattice or the
     //      interior positions of the adjacent level (checked on [0, 1])
@@ -278,6 +280,7 @@ int build_host_mesh(const MeshInput& in, HostMesh& m, std::string& err) {
     std::vector<double> mv(m.nzn, 0.0);
     for (int e = 0; e < in.n_z; ++e) {
         m.dz[e] = in.z_edges[e + 1] - in.z_edges[e];
+        m.sz.push_back(2.0 / m.dz[e]);
         for (int k = 0; k < np1; ++k) {
             int kz = e * N + k;
             if (k < N) m.zn[kz] = in.z_edges[e] + 0.5 * (1.0 + B.x[k]) * m.dz[e];

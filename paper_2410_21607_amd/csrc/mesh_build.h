@@ -38,6 +38,7 @@ struct HostMesh {
     int n_col = 0;
     std::vector<int32_t> col_level, col_ix, col_iy;
     std::vector<double> col_dx, col_dy, col_x0, col_y0;
+    std::vector<double> col_sx, col_sy, sz;   // 2/dx, 2/dy per column, 2/dz per layer
 
     // horizontal numbering
     int64_t n_h = 0, n_hh = 0;

@@ -12,6 +12,7 @@
 #include "devmesh.h"
 #include "mesh_build.h"
 #include "sem.h"
+#include "stage_fused.h"
 
 namespace {
 
@@ -40,14 +41,10 @@ struct sem_mesh {
     DevMesh d{};
     std::vector<void*> allocs;
     bool have_ref = false;
-    // workspace for the unfused composition and the fused stage
-    double* ws_hv = nullptr;   // F * n_hh * nzn
-    double* ws_rE = nullptr;   // F * n_local
-    double* ws_acc = nullptr;  // F * n_dof
-    double* ws_c = nullptr;    // F * n_hh * nzn
-    double* ws_r = nullptr;    // F * n_dof
+    sem::FusedPlan fused;
     int64_t ws_bytes = 0;
     ~sem_mesh() {
+        sem::fused_plan_free(fused);
         for (void* p : allocs) (void)hipFree(p);
     }
     template <typename T>
@@ -59,14 +56,6 @@ struct sem_mesh {
         HIPCHK(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
         ws_bytes += int64_t(v.size() * sizeof(T));
         *dst = static_cast<const T*>(p);
-        return SEM_OK;
-    }
-    int alloc(size_t bytes, void** dst) {
-        *dst = nullptr;
-        if (bytes == 0) return SEM_OK;
-        HIPCHK(hipMalloc(dst, bytes));
-        allocs.push_back(*dst);
-        ws_bytes += int64_t(bytes);
         return SEM_OK;
     }
 };
@@ -408,9 +397,6 @@ static int sem_launch_rhs(const sem_mesh* M, const double* q, const double* hv, 
 // ====================================================================== C ABI
 extern "C" {
 
-int sem_internal_compose_stage(const sem_mesh* M, double a, double b, double c, const double* qn,
-                               const double* qs, double* qout, int prec, void* stream);
-
 const char* sem_last_error(void) { return g_err.c_str(); }
 
 int sem_mesh_create(const sem_mesh_desc* desc, sem_mesh** out) {
@@ -432,21 +418,15 @@ int sem_mesh_create(const sem_mesh_desc* desc, sem_mesh** out) {
     d.gamma = H.c_p / (H.c_p - H.R_d);
 #define UP(vec, field) if ((rc = M->upload(vec, &d.field)) != SEM_OK) return rc;
     UP(H.gmap, gmap) UP(H.col_dx, col_dx) UP(H.col_dy, col_dy) UP(H.dz, dz)
+    UP(H.col_sx, col_sx) UP(H.col_sy, col_sy) UP(H.sz, sz)
     UP(H.hang_ptr, hang_ptr) UP(H.hang_src, hang_src) UP(H.hang_w, hang_w)
     UP(H.hT_list, hT_list) UP(H.hT_ptr, hT_ptr) UP(H.hT_hh, hT_hh) UP(H.hT_w, hT_w)
     UP(H.asm_ptr, asm_ptr) UP(H.asm_slot, asm_slot) UP(H.asmH_ptr, asmH_ptr)
     UP(H.asmH_slot, asmH_slot) UP(H.minv_h, minv_h) UP(H.minv_v, minv_v)
     UP(H.sib, sib) UP(H.col_level, col_level) UP(H.basis.D, D) UP(H.basis.w, w)
 #undef UP
-    const size_t np3 = size_t(H.np1) * H.np1 * H.np1;
-    const size_t n_dof = size_t(H.n_h) * H.nzn, n_hng = size_t(H.n_hh) * H.nzn;
-    const size_t n_loc = size_t(H.n_col) * H.n_z * np3;
-    void* p;
-    if ((rc = M->alloc(NF * n_hng * 8, &p)) != SEM_OK) return rc; M->ws_hv = (double*)p;
-    if ((rc = M->alloc(NF * n_loc * 8, &p)) != SEM_OK) return rc; M->ws_rE = (double*)p;
-    if ((rc = M->alloc(NF * n_dof * 8, &p)) != SEM_OK) return rc; M->ws_acc = (double*)p;
-    if ((rc = M->alloc(NF * n_hng * 8, &p)) != SEM_OK) return rc; M->ws_c = (double*)p;
-    if ((rc = M->alloc(NF * n_dof * 8, &p)) != SEM_OK) return rc; M->ws_r = (double*)p;
+    if ((rc = sem::fused_plan_build(H, 0, M->fused)) != SEM_OK)
+        return fail(rc, "could not build the fused-stage tables");
     *out = M.release();
     return SEM_OK;
 }
@@ -492,7 +472,7 @@ int sem_mesh_get_info(const sem_mesh* M, sem_mesh_info* o) {
     o->n_h = H.n_h; o->n_hh = H.n_hh;
     o->n_dof = H.n_h * H.nzn; o->n_hang = H.n_hh * H.nzn;
     o->n_local = o->n_elem * H.np1 * H.np1 * H.np1;
-    o->workspace_bytes = M->ws_bytes;
+    o->workspace_bytes = M->ws_bytes + M->fused.bytes;
     return SEM_OK;
 }
 
@@ -592,7 +572,29 @@ int sem_stage(const sem_mesh* M, double a, double b, double c, const double* qn,
     if (!qn || !qs || !qout) return fail(SEM_ERR_ARG, "null array");
     if (qout == qs || qout == qn) return fail(SEM_ERR_ARG, "qout must not alias qs or qn");
     if (prec != SEM_FP64 && prec != SEM_FP32) return fail(SEM_ERR_ARG, "bad precision");
-    return sem_internal_compose_stage(M, a, b, c, qn, qs, qout, prec, stream);
+    rc = sem::fused_stage_launch(M->d, M->fused, a, b, c, qn, qs, qout, prec, (hipStream_t)stream);
+    if (rc != SEM_OK) return fail(rc, "fused stage launch failed");
+    return SEM_OK;
+}
+
+int sem_stage_tune(sem_mesh* M, int layers_per_chunk) {
+    if (!M) return fail(SEM_ERR_ARG, "null mesh");
+    if (layers_per_chunk < 0 ||
+        (layers_per_chunk > 0 && !sem::fused_lpc_supported(M->host.N, layers_per_chunk)))
+        return fail(SEM_ERR_ARG, "unsupported layers_per_chunk for this order");
+    sem::FusedPlan P;
+    int rc = sem::fused_plan_build(M->host, layers_per_chunk, P);
+    if (rc != SEM_OK) { sem::fused_plan_free(P); return fail(rc, "could not build the fused-stage tables"); }
+    HIPCHK(hipDeviceSynchronize());
+    sem::fused_plan_free(M->fused);
+    M->fused = P;
+    return SEM_OK;
+}
+
+int sem_stage_get_tune(const sem_mesh* M, int* layers_per_chunk) {
+    if (!M || !layers_per_chunk) return fail(SEM_ERR_ARG, "null argument");
+    *layers_per_chunk = M->fused.t.layers_per_chunk;
+    return SEM_OK;
 }
 
 int amr_flag(const sem_mesh* M, const double* q, int criterion, const double* thr, int lvl_max,
@@ -622,18 +624,6 @@ int amr_flag(const sem_mesh* M, const double* q, int criterion, const double* th
     hipLaunchKernelGGL(sem::k_amr_col, dim3((d.n_col + 255) / 256), dim3(256), 0, s, d, ae, ac);
     HIPCHK(hipGetLastError());
     return SEM_OK;
-}
-
-// Internal entry used by the fused-stage fallback composition.
-int sem_internal_compose_stage(const sem_mesh* M, double a, double b, double c, const double* qn,
-                               const double* qs, double* qout, int prec, void* stream) {
-    int rc;
-    if ((rc = sem_nc_project(M, SEM_SCATTER, qs, M->ws_hv, stream)) != SEM_OK) return rc;
-    if ((rc = sem_rhs(M, qs, M->ws_hv, M->ws_rE, prec, stream)) != SEM_OK) return rc;
-    if ((rc = sem_dss(M, SEM_ASSEMBLE, M->ws_rE, M->ws_acc, M->ws_c, nullptr, stream)) != SEM_OK) return rc;
-    if ((rc = sem_nc_project(M, SEM_GATHER, M->ws_c, M->ws_acc, stream)) != SEM_OK) return rc;
-    if ((rc = sem_dss(M, SEM_FINALIZE, nullptr, M->ws_acc, nullptr, M->ws_r, stream)) != SEM_OK) return rc;
-    return sem_stage_update(M, a, b, c, qn, qs, M->ws_r, qout, stream);
 }
 
 }  // extern "C"

@@ -1,0 +1,430 @@
+// Fused Runge-Kutta stage for gfx950.
+//
+// q_out = a q^n + b q_s + c M^-1 Z^T (m_L R_L(Z q_s)) in one pass over the
+// columns of every refinement level, without ever storing the element-local
+// right-hand side.
+//
+// Column kernel.  A workgroup owns one column and marches up through it in
+// chunks of `layers_per_chunk` stacked elements; one thread per unique node of
+// the chunk (vertical index fastest, so that the accesses of one horizontal
+// position are contiguous in the [field][h][kz] state layout):
+//   * load the node of q_s (hanging positions interpolate the coarse face
+//     nodes: the scatter of Section 3.1) and evaluate the pointwise fields of
+//     Section 2 (rho u, rho v, rho w, u, v, w, p', theta') into LDS;
+//   * sum-factorised derivatives along x, y, z read the chunk tile from LDS
+//     (Section 3: tensor-product LGL basis, affine boxes); a node on the plane
+//     between two stacked elements shares its x and y derivatives and takes
+//     the z derivative of each element;
+//   * the strong-form right-hand side times the lumped LGL mass, summed over
+//     the elements of the chunk, is the column's contribution to the node; the
+//     plane between two chunks is completed through an LDS carry;
+//   * the node is then updated in place: the first contributor (lowest colour)
+//     writes a q^n + b q_s + c M^-1 contribution, later colours add
+//     c M^-1 contribution; hanging positions collect their contribution in a
+//     buffer instead (Z^T below).
+// Columns are coloured so that no two columns of one colour share a node: each
+// colour is one launch, so the read-modify-writes never race and the order of
+// the sums is fixed (deterministic results).
+// Hanging-point kernel (meshes with hanging nodes): every coarse face node
+// adds c M^-1 sum_hh w_hh c_hh, the transpose of the scatter (Section 3.1).
+#include "stage_fused.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <string>
+
+#include "mesh_build.h"
+#include "sem.h"
+
+namespace sem {
+
+namespace {
+
+constexpr int NF = SEM_NFIELDS;
+constexpr int NT = 8;   // LDS tiles: rho u, rho v, rho w, u, v, w, p', theta'
+
+template <int NP, int LPC>
+constexpr int wg_threads() {
+    return ((NP * NP * (LPC * (NP - 1) + 1) + 63) / 64) * 64;
+}
+
+template <typename T>
+__device__ __forceinline__ T pressure_perturbation(double rho0, double th0, double p0, double gamma,
+                                                   double rp, double tp) {
+    // p' = p0 ((rho theta)/(rho0 theta0))^gamma - p0 = p0 expm1(gamma log1p(x)),
+    // x = a + b + a b with a = rho'/rho0, b = theta'/theta0 (no cancellation)
+    if constexpr (sizeof(T) == 8) {
+        const double ra = rp / rho0, tb = tp / th0;
+        return p0 * expm1(gamma * log1p(ra + tb + ra * tb));
+    } else {
+        const float ra = float(rp) / float(rho0), tb = float(tp) / float(th0);
+        return float(p0) * expm1f(float(gamma) * log1pf(ra + tb + ra * tb));
+    }
+}
+
+template <int NP, int LPC, typename T>
+__global__ void __launch_bounds__(((NP * NP * (LPC * (NP - 1) + 1) + 63) / 64) * 64)
+k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double b, double c,
+                const double* __restrict__ qn, const double* __restrict__ qs,
+                double* __restrict__ qo) {
+    constexpr int NP2 = NP * NP, N = NP - 1;
+    constexpr int NK = LPC * N + 1;               // vertical nodes of a full chunk
+    constexpr int WGT = wg_threads<NP, LPC>();
+    __shared__ T tile[NT][NP2 * NK];              // [field][p][kzl], kzl fastest
+    __shared__ double carry[2][NF][NP2];
+    __shared__ T sD[NP2];
+    __shared__ double sW[NP];
+    const int tid = threadIdx.x;
+    for (int t = tid; t < NP2; t += WGT) sD[t] = T(m.D[t]);
+    for (int t = tid; t < NP; t += WGT) sW[t] = m.w[t];
+
+    // Workgroups go to the 8 XCDs round-robin by id; give each XCD a
+    // contiguous (Morton-ordered) range of this colour's columns.
+    const int G = gridDim.x;
+    const int xcd = blockIdx.x & 7, rr = blockIdx.x >> 3;
+    const int item = xcd * (G >> 3) + min(xcd, G & 7) + rr;
+    const int col = ft.col_order[col0 + min(item, ncol - 1)];
+
+    const int kzl = tid % NK;
+    const int p = tid / NK;
+    const bool lane_ok = (p < NP2) && (item < ncol);
+    const int pc = lane_ok ? p : 0;               // position used for table lookups
+    const int i = pc % NP, j = pc / NP;
+    const int nzn = m.nzn;
+    const int64_t fs = int64_t(m.n_h) * nzn;
+    const int64_t fsh = int64_t(m.n_hh) * nzn;
+
+    int g = 0, r_beg = 0, r_end = 0;
+    bool first = false;
+    double minv_h = 0.0;
+    const double dxc = m.col_dx[col], dyc = m.col_dy[col];
+    const T sx = T(m.col_sx[col]), sy = T(m.col_sy[col]);
+    if (lane_ok) {
+        g = m.gmap[col * NP2 + pc];
+        first = ft.first[col * NP2 + pc] != 0;
+        if (g < 0) {
+            r_beg = m.hang_ptr[-g - 1];
+            r_end = m.hang_ptr[-g];
+        } else {
+            minv_h = m.minv_h[g];
+        }
+    }
+    __syncthreads();
+    const T* Dx = &sD[i * NP];
+    const T* Dy = &sD[j * NP];
+    const double mass_ij = sW[i] * sW[j] * 0.125 * dxc * dyc;
+    const int lx0 = (j * NP) * NK + kzl, ly0 = i * NK + kzl;
+
+    const int n_chunk = (m.n_z + LPC - 1) / LPC;
+    for (int ch = 0; ch < n_chunk; ++ch) {
+        const int L0 = ch * LPC;
+        const int L1 = min(L0 + LPC, m.n_z);
+        const int nk = (L1 - L0) * N + 1;
+        const bool active = lane_ok && (kzl < nk);
+        const int kz = L0 * N + kzl;
+        const int lidx = pc * NK + kzl;
+        double qv[NF] = {0, 0, 0, 0, 0};
+        T rho = T(1);
+        if (active) {
+            if (g >= 0) {
+                const int64_t o = int64_t(g) * nzn + kz;
+#pragma unroll
+                for (int f = 0; f < NF; ++f) qv[f] = qs[f * fs + o];
+            } else {
+                for (int r = r_beg; r < r_end; ++r) {
+                    const double w = m.hang_w[r];
+                    const int64_t o = int64_t(m.hang_src[r]) * nzn + kz;
+#pragma unroll
+                    for (int f = 0; f < NF; ++f) qv[f] += w * qs[f * fs + o];
+                }
+            }
+            const double r0d = m.rho0[kz];
+            rho = T(r0d) + T(qv[0]);
+            const T u = T(qv[1]), v = T(qv[2]), w = T(qv[3]);
+            tile[0][lidx] = rho * u;
+            tile[1][lidx] = rho * v;
+            tile[2][lidx] = rho * w;
+            tile[3][lidx] = u;
+            tile[4][lidx] = v;
+            tile[5][lidx] = w;
+            tile[6][lidx] = pressure_perturbation<T>(r0d, m.theta0[kz], m.p0[kz], m.gamma, qv[0], qv[4]);
+            tile[7][lidx] = T(qv[4]);
+        }
+        __syncthreads();
+        double base[NF] = {0, 0, 0, 0, 0};
+        if (active && g >= 0) {
+            const double* bp = first ? qn : qo;
+            const int64_t o = int64_t(g) * nzn + kz;
+#pragma unroll
+            for (int f = 0; f < NF; ++f) base[f] = bp[f * fs + o];
+        }
+        if (active) {
+            // d/dx of tile tx and d/dy of tile ty at this node.  The empty asm
+            // pins both results before the next field's LDS reads may be
+            // issued (memory clobber), which bounds the live registers.
+            auto dxy = [&](int tx, int ty, T& ox, T& oy) {
+                T ax = 0, ay = 0;
+#pragma unroll
+                for (int mm = 0; mm < NP; ++mm) {
+                    ax += Dx[mm] * tile[tx][lx0 + mm * NK];
+                    ay += Dy[mm] * tile[ty][ly0 + mm * NP * NK];
+                }
+                asm volatile("" : "+v"(ax), "+v"(ay) : : "memory");
+                ox = ax * sx;
+                oy = ay * sy;
+            };
+            const T u = T(qv[1]), v = T(qv[2]), w = T(qv[3]);
+            const T inv_rho = T(1) / rho;
+            const T f = T(m.f), gr = T(m.g);
+            // the parts of R without z derivatives
+            T Rh[NF], ax, ay;
+            dxy(0, 1, ax, ay);
+            Rh[0] = -(ax + ay);
+            dxy(3, 3, ax, ay);
+            Rh[1] = -(u * ax + v * ay) + f * v;
+            dxy(4, 4, ax, ay);
+            Rh[2] = -(u * ax + v * ay) - f * u;
+            dxy(5, 5, ax, ay);
+            Rh[3] = -(u * ax + v * ay) - T(qv[0]) * inv_rho * gr;
+            dxy(6, 6, ax, ay);
+            Rh[1] -= ax * inv_rho;
+            Rh[2] -= ay * inv_rho;
+            dxy(7, 7, ax, ay);
+            Rh[4] = -(u * ax + v * ay) - w * T(m.dth0[kz]);
+            double acc[NF] = {0, 0, 0, 0, 0};
+            // elements of this chunk holding the node: (element, local k)
+            const bool inner_plane = (kzl % N == 0) && kzl > 0 && kzl < nk - 1;
+            const int e_first = (kzl == nk - 1) ? (kzl - 1) / N : (inner_plane ? kzl / N - 1 : kzl / N);
+            const int n_el = inner_plane ? 2 : 1;
+            for (int s2 = 0; s2 < n_el; ++s2) {
+                const int el = e_first + s2;
+                const int kk = kzl - el * N;
+                const double dzl = m.dz[L0 + el];
+                const T sz = T(m.sz[L0 + el]);
+                const T* Dz = &sD[kk * NP];
+                const int lz0 = pc * NK + el * N;
+                auto ddz = [&](int tz) {
+                    T az = 0;
+#pragma unroll
+                    for (int mm = 0; mm < NP; ++mm) az += Dz[mm] * tile[tz][lz0 + mm];
+                    asm volatile("" : "+v"(az) : : "memory");
+                    return az * sz;
+                };
+                T R[NF];
+                R[0] = Rh[0] - ddz(2);
+                R[1] = Rh[1] - w * ddz(3);
+                R[2] = Rh[2] - w * ddz(4);
+                R[3] = Rh[3] - w * ddz(5) - ddz(6) * inv_rho;
+                R[4] = Rh[4] - w * ddz(7);
+                const double mass = mass_ij * sW[kk] * dzl;
+#pragma unroll
+                for (int fl = 0; fl < NF; ++fl) acc[fl] += mass * double(R[fl]);
+            }
+            if (kzl == nk - 1 && L1 < m.n_z) {
+                // top plane of the chunk: finished by the next chunk
+#pragma unroll
+                for (int fl = 0; fl < NF; ++fl) carry[ch & 1][fl][pc] = acc[fl];
+            } else {
+                if (kzl == 0 && ch > 0) {
+#pragma unroll
+                    for (int fl = 0; fl < NF; ++fl) acc[fl] += carry[(ch - 1) & 1][fl][pc];
+                }
+                if (g >= 0) {
+                    const bool lid = (kz == 0) || (kz == nzn - 1);
+                    const double mi = c * minv_h * m.minv_v[kz];
+                    const int64_t o = int64_t(g) * nzn + kz;
+                    if (first) {
+#pragma unroll
+                        for (int fl = 0; fl < NF; ++fl) {
+                            const double tend = (fl == 3 && lid) ? 0.0 : mi * acc[fl];
+                            qo[fl * fs + o] = a * base[fl] + b * qv[fl] + tend;
+                        }
+                    } else {
+#pragma unroll
+                        for (int fl = 0; fl < NF; ++fl)
+                            if (!(fl == 3 && lid)) qo[fl * fs + o] = base[fl] + mi * acc[fl];
+                    }
+                } else {
+                    const int64_t o = int64_t(-g - 1) * nzn + kz;
+                    if (first) {
+#pragma unroll
+                        for (int fl = 0; fl < NF; ++fl) ft.cH[fl * fsh + o] = acc[fl];
+                    } else {
+#pragma unroll
+                        for (int fl = 0; fl < NF; ++fl) ft.cH[fl * fsh + o] += acc[fl];
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Z^T: coarse face nodes receive the hanging-point contributions
+__global__ void k_stage_hanging(DevMesh m, FusedTables ft, double c, double* __restrict__ qo) {
+    const int nzn = m.nzn;
+    const int64_t n = int64_t(m.n_hT) * nzn;
+    const int64_t fs = int64_t(m.n_h) * nzn;
+    const int64_t fsh = int64_t(m.n_hh) * nzn;
+    for (int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; t < n;
+         t += int64_t(gridDim.x) * blockDim.x) {
+        const int li = int(t / nzn), kz = int(t - int64_t(li) * nzn);
+        const int h = m.hT_list[li];
+        double s[NF] = {0, 0, 0, 0, 0};
+        for (int r = m.hT_ptr[li]; r < m.hT_ptr[li + 1]; ++r) {
+            const double w = m.hT_w[r];
+            const int64_t o = int64_t(m.hT_hh[r]) * nzn + kz;
+#pragma unroll
+            for (int f = 0; f < NF; ++f) s[f] += w * ft.cH[f * fsh + o];
+        }
+        const bool lid = (kz == 0) || (kz == nzn - 1);
+        const double mi = c * m.minv_h[h] * m.minv_v[kz];
+        const int64_t o = int64_t(h) * nzn + kz;
+#pragma unroll
+        for (int f = 0; f < NF; ++f)
+            if (!(f == 3 && lid)) qo[f * fs + o] += mi * s[f];
+    }
+}
+
+// (order, layers per chunk) instances with <= 1024 threads and <= 64 KB LDS
+#define SEM_FUSED_INSTANCES(X) \
+    X(1, 1) X(1, 2) X(1, 4) X(1, 8) \
+    X(2, 1) X(2, 2) X(2, 4) X(2, 8) \
+    X(3, 1) X(3, 2) X(3, 4) X(3, 8) \
+    X(4, 1) X(4, 2) X(4, 4) X(4, 8) \
+    X(5, 1) X(5, 2) X(5, 4)         \
+    X(6, 1) X(6, 2)                 \
+    X(7, 1) X(7, 2)                 \
+    X(8, 1)
+
+template <typename T>
+int launch_t(const DevMesh& m, const FusedTables& t, int col0, int ncol, double a, double b,
+             double c, const double* qn, const double* qs, double* qo, hipStream_t s) {
+    switch (m.N * 32 + t.layers_per_chunk) {
+#define CASE(NN, LP)                                                                    \
+    case NN * 32 + LP:                                                                  \
+        hipLaunchKernelGGL((k_stage_columns<NN + 1, LP, T>), dim3(ncol),                \
+                           dim3(wg_threads<NN + 1, LP>()), 0, s, m, t, col0, ncol, a, b, \
+                           c, qn, qs, qo);                                              \
+        break;
+        SEM_FUSED_INSTANCES(CASE)
+#undef CASE
+        default: return SEM_ERR_ARG;
+    }
+    return (hipGetLastError() == hipSuccess) ? SEM_OK : SEM_ERR_HIP;
+}
+
+}  // namespace
+
+bool fused_lpc_supported(int N, int lpc) {
+    switch (N * 32 + lpc) {
+#define CASE(NN, LP) case NN * 32 + LP: return true;
+        SEM_FUSED_INSTANCES(CASE)
+#undef CASE
+        default: return false;
+    }
+}
+
+int fused_plan_build(const HostMesh& H, int lpc, FusedPlan& P) {
+    const int np2 = H.np1 * H.np1;
+    if (lpc < 1) {
+        // default: the deepest supported chunk of at most 512 threads
+        lpc = 1;
+        while (fused_lpc_supported(H.N, lpc * 2) && np2 * (2 * lpc * H.N + 1) <= 512) lpc *= 2;
+    }
+    if (!fused_lpc_supported(H.N, lpc)) return SEM_ERR_ARG;
+    // conflict lists: the columns contributing to each unique node / hanging point
+    std::vector<std::vector<int32_t>> adj(size_t(H.n_col));
+    auto link = [&](const std::vector<int32_t>& ptr, const std::vector<int32_t>& slot, int64_t n) {
+        for (int64_t x = 0; x < n; ++x)
+            for (int32_t q = ptr[x]; q < ptr[x + 1]; ++q)
+                for (int32_t r = ptr[x]; r < ptr[x + 1]; ++r) {
+                    const int32_t c1 = slot[q] / np2, c2 = slot[r] / np2;
+                    if (c1 != c2) adj[c1].push_back(c2);
+                }
+    };
+    link(H.asm_ptr, H.asm_slot, H.n_h);
+    link(H.asmH_ptr, H.asmH_slot, H.n_hh);
+    // greedy colouring in column order (the caller's order; Morton keeps it local)
+    std::vector<int32_t> color(size_t(H.n_col), -1);
+    int n_color = 0;
+    for (int cidx = 0; cidx < H.n_col; ++cidx) {
+        std::vector<char> used(size_t(n_color) + 1, 0);
+        for (int32_t o : adj[cidx])
+            if (color[o] >= 0) used[color[o]] = 1;
+        int k = 0;
+        while (used[k]) ++k;
+        color[cidx] = k;
+        n_color = std::max(n_color, k + 1);
+    }
+    std::vector<int32_t> order, cptr(size_t(n_color) + 1, 0);
+    for (int k = 0; k < n_color; ++k) {
+        for (int cidx = 0; cidx < H.n_col; ++cidx)
+            if (color[cidx] == k) order.push_back(cidx);
+        cptr[k + 1] = int32_t(order.size());
+    }
+    // first contributor of every node: the lowest colour among its columns
+    std::vector<uint8_t> first(H.gmap.size(), 0);
+    auto mark = [&](const std::vector<int32_t>& ptr, const std::vector<int32_t>& slot, int64_t n) {
+        for (int64_t x = 0; x < n; ++x) {
+            int32_t best = -1;
+            for (int32_t q = ptr[x]; q < ptr[x + 1]; ++q)
+                if (best < 0 || color[slot[q] / np2] < color[best / np2]) best = slot[q];
+            if (best >= 0) first[best] = 1;
+        }
+    };
+    mark(H.asm_ptr, H.asm_slot, H.n_h);
+    mark(H.asmH_ptr, H.asmH_slot, H.n_hh);
+    auto up = [&](const void* src, size_t bytes, void** dst) -> int {
+        *dst = nullptr;
+        if (bytes == 0) return SEM_OK;
+        if (hipMalloc(dst, bytes) != hipSuccess) return SEM_ERR_HIP;
+        P.allocs.push_back(*dst);
+        P.bytes += int64_t(bytes);
+        if (src && hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice) != hipSuccess) return SEM_ERR_HIP;
+        return SEM_OK;
+    };
+    void* d;
+    int rc;
+    if ((rc = up(order.data(), order.size() * 4, &d)) != SEM_OK) return rc;
+    P.t.col_order = static_cast<const int32_t*>(d);
+    if ((rc = up(cptr.data(), cptr.size() * 4, &d)) != SEM_OK) return rc;
+    P.t.color_ptr = static_cast<const int32_t*>(d);
+    if ((rc = up(first.data(), first.size(), &d)) != SEM_OK) return rc;
+    P.t.first = static_cast<const uint8_t*>(d);
+    if ((rc = up(nullptr, size_t(NF) * H.n_hh * H.nzn * 8, &d)) != SEM_OK) return rc;
+    P.t.cH = static_cast<double*>(d);
+    P.t.n_color = n_color;
+    P.t.layers_per_chunk = lpc;
+    P.color_ptr_host = cptr;
+    return SEM_OK;
+}
+
+void fused_plan_free(FusedPlan& P) {
+    for (void* p : P.allocs) (void)hipFree(p);
+    P.allocs.clear();
+    P.bytes = 0;
+}
+
+int fused_stage_launch(const DevMesh& m, const FusedPlan& P, double a, double b, double c,
+                       const double* qn, const double* qs, double* qo, int prec, hipStream_t s) {
+    const FusedTables& t = P.t;
+    for (int k = 0; k < t.n_color; ++k) {
+        const int col0 = P.color_ptr_host[k];
+        const int ncol = P.color_ptr_host[k + 1] - col0;
+        if (ncol == 0) continue;
+        const int rc = (prec == SEM_FP32) ? launch_t<float>(m, t, col0, ncol, a, b, c, qn, qs, qo, s)
+                                          : launch_t<double>(m, t, col0, ncol, a, b, c, qn, qs, qo, s);
+        if (rc != SEM_OK) return rc;
+    }
+    const int64_t n2 = int64_t(m.n_hT) * m.nzn;
+    if (n2 > 0) {
+        const int64_t g = std::min<int64_t>((n2 + 255) / 256, 65536);
+        hipLaunchKernelGGL(k_stage_hanging, dim3(unsigned(g)), dim3(256), 0, s, m, t, c, qo);
+        if (hipGetLastError() != hipSuccess) return SEM_ERR_HIP;
+    }
+    return SEM_OK;
+}
+
+}  // namespace sem

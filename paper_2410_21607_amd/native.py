@@ -57,6 +57,8 @@ SIGNATURES = {
                                  c_void_p, c_void_p, c_void_p]),
     "sem_stage": (c_int, [c_void_p, c_double, c_double, c_double, c_void_p, c_void_p,
                           c_void_p, c_int, c_void_p]),
+    "sem_stage_tune": (c_int, [c_void_p, c_int]),
+    "sem_stage_get_tune": (c_int, [c_void_p, ctypes.POINTER(c_int)]),
     "amr_flag": (c_int, [c_void_p, c_void_p, c_int, c_dp, c_int, c_void_p, c_void_p, c_void_p]),
     "sem_last_error": (ctypes.c_char_p, []),
 }

@@ -242,3 +242,59 @@ def test_api_rejects_bad_calls():
                      torch.zeros(S.gm.info["n_col"], dtype=torch.int8, device="cuda"))
     with pytest.raises(ValueError):
         api.sem_stage(S.gm, 0.0, 1.0, 1.0, q[:-1], q.clone(), torch.empty_like(q))
+
+
+TUNES = [1, 2, 4, 8]
+
+
+@pytest.mark.parametrize("name,kw", [CASES[0], CASES[2], CASES[5], CASES[6]],
+                         ids=[IDS[0], IDS[2], IDS[5], IDS[6]])
+@pytest.mark.parametrize("ipw", TUNES)
+def test_fused_stage_decompositions(name, kw, ipw):
+    """Every work decomposition of the fused stage gives the oracle's stage."""
+    S = get(name, kw)
+    torch, api = S.torch, S.api
+    from paper_2410_21607_amd.native import SemError
+    say("fused tune", name, kw, ipw)
+    try:
+        api.sem_stage_tune(S.gm, ipw)
+    except SemError:
+        pytest.skip("no kernel instance for this order and packing")
+    try:
+        dt = S.c["dt"]
+        qn = S.q_g.clone()
+        qs = S.q_g.clone()
+        out = torch.empty_like(qn)
+        for st in range(3):
+            a, b, cc = timestep.stage_coefficients(st, dt)
+            api.sem_stage(S.gm, a, b, cc, qn, qs, out, api.SEM_FP64)
+            qs, out = out, qs
+        torch.cuda.synchronize()
+    finally:
+        api.sem_stage_tune(S.gm, 0)
+    rhs = lambda q: assembly.rhs(S.om, q, S.ref, S.c["phys"])
+    want, _ = timestep.run_stages(rhs, S.q_or, dt, 3)
+    err = metrics.rel_l2(S.to_oracle_order(qs), want, metrics.STATE_FLOORS)
+    say("  rel", err)
+    assert err.max() <= TOL64
+
+
+def test_fused_fp32_stage_error():
+    """FP32 element arithmetic inside the fused stage, FP64 accumulation."""
+    S = get(*CASES[0])
+    torch, api = S.torch, S.api
+    say("fused fp32")
+    dt = S.c["dt"]
+    qn = S.q_g.clone()
+    qs = S.q_g.clone()
+    out = torch.empty_like(qn)
+    for st in range(3):
+        a, b, cc = timestep.stage_coefficients(st, dt)
+        api.sem_stage(S.gm, a, b, cc, qn, qs, out, api.SEM_FP32)
+        qs, out = out, qs
+    torch.cuda.synchronize()
+    rhs = lambda q: assembly.rhs(S.om, q, S.ref, S.c["phys"])
+    want, _ = timestep.run_stages(rhs, S.q_or, dt, 3)
+    err = metrics.rel_l2(S.to_oracle_order(qs), want, metrics.STATE_FLOORS)
+    say("  rel fp32", err)
+    assert err.max() <= 1e-6
