@@ -190,6 +190,14 @@ int sem_stage(const sem_mesh *mesh, double a, double b, double c,
 int sem_stage_tune(sem_mesh *mesh, int layers_per_chunk);
 int sem_stage_get_tune(const sem_mesh *mesh, int *layers_per_chunk);
 
+/* Autotuner: times every supported layers_per_chunk on this mesh (reps fused
+ * stages each, HIP events on `stream`, d_qout used as scratch), keeps the
+ * fastest with sem_stage_tune, and reports it (*best_lpc, *best_ms = mean
+ * stage time in ms; either may be NULL).  Synchronises the stream. */
+int sem_stage_autotune(sem_mesh *mesh, const double *d_qn, const double *d_qs,
+                       double *d_qout, int precision, int reps, int *best_lpc,
+                       float *best_ms, void *stream);
+
 /* Refinement flags (Section 4.1).  Criterion C at every node of every element
  * from element-local values: SEM_CRIT_SPEED |u| or SEM_CRIT_VORTZ dv/dx-du/dy.
  * h_thr[0..lvl_max-1] = threshold(1..lvl_max), non-decreasing (host memory).

@@ -217,3 +217,13 @@ def sem_stage_get_tune(mesh):
     a = ctypes.c_int()
     native.call("sem_stage_get_tune", mesh.handle, ctypes.byref(a))
     return a.value
+
+
+def sem_stage_autotune(mesh, qn, qs, qout, precision=SEM_FP64, reps=5, stream=None):
+    """Pick the fastest chunk depth on this mesh; returns (layers_per_chunk, ms)."""
+    n = NF * mesh.n_dof
+    lpc, ms = ctypes.c_int(), ctypes.c_float()
+    native.call("sem_stage_autotune", mesh.handle, _ptr(qn, torch.float64, n, "qn"),
+                _ptr(qs, torch.float64, n, "qs"), _ptr(qout, torch.float64, n, "qout"),
+                int(precision), int(reps), ctypes.byref(lpc), ctypes.byref(ms), _stream(stream))
+    return lpc.value, ms.value

@@ -22,6 +22,8 @@ struct DevMesh {
     const int32_t *sib, *col_level;
     const double *D, *w;      // LGL derivative matrix and weights
     const double *rho0, *theta0, *dth0, *p0;   // reference state per kz
+    const double *inv_rho0, *inv_theta0;       // their reciprocals per kz
+    double binom[11];   // binom[n] = C(gamma, n): Taylor coefficients of (1+x)^gamma
 };
 
 }  // namespace sem

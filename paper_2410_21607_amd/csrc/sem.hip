@@ -416,6 +416,16 @@ int sem_mesh_create(const sem_mesh_desc* desc, sem_mesh** out) {
     d.n_h = int(H.n_h); d.n_hh = int(H.n_hh); d.n_hT = int(H.hT_list.size());
     d.f = H.f; d.g = H.g;
     d.gamma = H.c_p / (H.c_p - H.R_d);
+    {
+        // C(gamma, n) by the product rule in extended precision
+        long double cgam = (long double)H.c_p / ((long double)H.c_p - (long double)H.R_d);
+        long double cn = 1.0L;
+        d.binom[0] = 1.0;
+        for (int n = 1; n <= 10; ++n) {
+            cn *= (cgam - (long double)(n - 1)) / (long double)n;
+            d.binom[n] = (double)cn;
+        }
+    }
 #define UP(vec, field) if ((rc = M->upload(vec, &d.field)) != SEM_OK) return rc;
     UP(H.gmap, gmap) UP(H.col_dx, col_dx) UP(H.col_dy, col_dy) UP(H.dz, dz)
     UP(H.col_sx, col_sx) UP(H.col_sy, col_sy) UP(H.sz, sz)
@@ -490,25 +500,26 @@ int sem_mesh_set_reference(sem_mesh* M, const double* rho0, const double* theta0
     if (!M || !rho0 || !theta0 || !dth0) return fail(SEM_ERR_ARG, "null argument");
     const sem::HostMesh& H = M->host;
     std::vector<double> r(rho0, rho0 + H.nzn), t(theta0, theta0 + H.nzn), dt(dth0, dth0 + H.nzn),
-        p0(H.nzn);
+        p0(H.nzn), ir(H.nzn), it(H.nzn);
     const double gam = H.c_p / (H.c_p - H.R_d);
     for (int k = 0; k < H.nzn; ++k) {
         if (!(r[k] > 0) || !(t[k] > 0)) return fail(SEM_ERR_ARG, "reference state must be positive");
         p0[k] = H.p00 * std::pow(H.R_d * r[k] * t[k] / H.p00, gam);
+        ir[k] = 1.0 / r[k];
+        it[k] = 1.0 / t[k];
     }
-    if (M->have_ref) {
-        HIPCHK(hipMemcpy((void*)M->d.rho0, r.data(), H.nzn * 8, hipMemcpyHostToDevice));
-        HIPCHK(hipMemcpy((void*)M->d.theta0, t.data(), H.nzn * 8, hipMemcpyHostToDevice));
-        HIPCHK(hipMemcpy((void*)M->d.dth0, dt.data(), H.nzn * 8, hipMemcpyHostToDevice));
-        HIPCHK(hipMemcpy((void*)M->d.p0, p0.data(), H.nzn * 8, hipMemcpyHostToDevice));
-    } else {
-        int rc;
-        if ((rc = M->upload(r, &M->d.rho0)) != SEM_OK) return rc;
-        if ((rc = M->upload(t, &M->d.theta0)) != SEM_OK) return rc;
-        if ((rc = M->upload(dt, &M->d.dth0)) != SEM_OK) return rc;
-        if ((rc = M->upload(p0, &M->d.p0)) != SEM_OK) return rc;
-        M->have_ref = true;
+    const std::vector<double>* src[6] = {&r, &t, &dt, &p0, &ir, &it};
+    const double** dst[6] = {&M->d.rho0, &M->d.theta0, &M->d.dth0, &M->d.p0, &M->d.inv_rho0,
+                             &M->d.inv_theta0};
+    for (int q = 0; q < 6; ++q) {
+        if (M->have_ref) {
+            HIPCHK(hipMemcpy((void*)*dst[q], src[q]->data(), H.nzn * 8, hipMemcpyHostToDevice));
+        } else {
+            int rc = M->upload(*src[q], dst[q]);
+            if (rc != SEM_OK) return rc;
+        }
     }
+    M->have_ref = true;
     return SEM_OK;
 }
 
@@ -588,6 +599,51 @@ int sem_stage_tune(sem_mesh* M, int layers_per_chunk) {
     HIPCHK(hipDeviceSynchronize());
     sem::fused_plan_free(M->fused);
     M->fused = P;
+    return SEM_OK;
+}
+
+int sem_stage_autotune(sem_mesh* M, const double* qn, const double* qs, double* qout, int prec,
+                       int reps, int* best_lpc, float* best_ms, void* stream) {
+    int rc = check_mesh(M);
+    if (rc != SEM_OK) return rc;
+    if (!qn || !qs || !qout) return fail(SEM_ERR_ARG, "null array");
+    if (qout == qs || qout == qn) return fail(SEM_ERR_ARG, "qout must not alias qs or qn");
+    if (prec != SEM_FP64 && prec != SEM_FP32) return fail(SEM_ERR_ARG, "bad precision");
+    if (reps < 1) reps = 5;
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    int best = -1;
+    float best_t = 0.0f;
+    for (int lpc = 1; lpc <= 16; lpc *= 2) {
+        if (!sem::fused_lpc_supported(M->host.N, lpc) || lpc > 2 * M->host.n_z) continue;
+        sem::FusedPlan P;
+        if (sem::fused_plan_build(M->host, lpc, P) != SEM_OK) { sem::fused_plan_free(P); continue; }
+        // warm-up, then timed repetitions (the stage coefficients do not
+        // change the work; qout is scratch here)
+        rc = sem::fused_stage_launch(M->d, P, 0.5, 0.5, 1e-3, qn, qs, qout, prec, s);
+        if (rc == SEM_OK) {
+            (void)hipEventRecord(e0, s);
+            for (int r = 0; r < reps && rc == SEM_OK; ++r)
+                rc = sem::fused_stage_launch(M->d, P, 0.5, 0.5, 1e-3, qn, qs, qout, prec, s);
+            (void)hipEventRecord(e1, s);
+        }
+        float ms = 0.0f;
+        if (rc == SEM_OK && hipEventSynchronize(e1) == hipSuccess &&
+            hipEventElapsedTime(&ms, e0, e1) == hipSuccess) {
+            ms /= float(reps);
+            if (best < 0 || ms < best_t) { best = lpc; best_t = ms; }
+        }
+        (void)hipStreamSynchronize(s);
+        sem::fused_plan_free(P);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (best < 0) return fail(SEM_ERR_HIP, "autotuning found no working configuration");
+    if ((rc = sem_stage_tune(M, best)) != SEM_OK) return rc;
+    if (best_lpc) *best_lpc = best;
+    if (best_ms) *best_ms = best_t;
     return SEM_OK;
 }
 

@@ -49,22 +49,34 @@ constexpr int wg_threads() {
     return ((NP * NP * (LPC * (NP - 1) + 1) + 63) / 64) * 64;
 }
 
+// (1+x)^gamma - 1 for the ideal-gas pressure ratio.  For |x| <= 1/64 the
+// Taylor polynomial sum_{n=1..10} C(gamma, n) x^n is used (the first neglected
+// term is below 2^-66 |gamma x|, far under one ulp); otherwise
+// expm1(gamma log1p(x)).
 template <typename T>
-__device__ __forceinline__ T pressure_perturbation(double rho0, double th0, double p0, double gamma,
-                                                   double rp, double tp) {
-    // p' = p0 ((rho theta)/(rho0 theta0))^gamma - p0 = p0 expm1(gamma log1p(x)),
-    // x = a + b + a b with a = rho'/rho0, b = theta'/theta0 (no cancellation)
-    if constexpr (sizeof(T) == 8) {
-        const double ra = rp / rho0, tb = tp / th0;
-        return p0 * expm1(gamma * log1p(ra + tb + ra * tb));
-    } else {
-        const float ra = float(rp) / float(rho0), tb = float(tp) / float(th0);
-        return float(p0) * expm1f(float(gamma) * log1pf(ra + tb + ra * tb));
+__device__ __forceinline__ T pow1p_minus1(const DevMesh& m, T x) {
+    if (fabs(x) <= T(1.0 / 64.0)) {
+        T s = T(m.binom[10]);
+#pragma unroll
+        for (int n = 9; n >= 1; --n) s = s * x + T(m.binom[n]);
+        return s * x;
     }
+    if constexpr (sizeof(T) == 8) return expm1(m.gamma * log1p(x));
+    else return expm1f(float(m.gamma) * log1pf(x));
 }
 
+// p' = p0 ((rho theta)/(rho0 theta0))^gamma - p0 with x = a + b + a b,
+// a = rho'/rho0, b = theta'/theta0 (no cancellation against p0)
+template <typename T>
+__device__ __forceinline__ T pressure_perturbation(const DevMesh& m, int kz, double rp, double tp) {
+    const T ra = T(rp * m.inv_rho0[kz]), tb = T(tp * m.inv_theta0[kz]);
+    return T(m.p0[kz]) * pow1p_minus1<T>(m, ra + tb + ra * tb);
+}
+
+// At least four waves per SIMD: two workgroups share a CU, so that one can
+// compute while the other waits on memory (a few registers spill).
 template <int NP, int LPC, typename T>
-__global__ void __launch_bounds__(((NP * NP * (LPC * (NP - 1) + 1) + 63) / 64) * 64)
+__global__ void __launch_bounds__(((NP * NP * (LPC * (NP - 1) + 1) + 63) / 64) * 64, 4)
 k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double b, double c,
                 const double* __restrict__ qn, const double* __restrict__ qs,
                 double* __restrict__ qo) {
@@ -86,8 +98,27 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
     const int item = xcd * (G >> 3) + min(xcd, G & 7) + rr;
     const int col = ft.col_order[col0 + min(item, ncol - 1)];
 
-    const int kzl = tid % NK;
-    const int p = tid / NK;
+    // Thread -> node of the chunk.  Nodes inside an element or on the chunk's
+    // bottom/top come first (RG per position); nodes on the planes between two
+    // stacked elements (LPC-1 per position, two z derivatives each) follow,
+    // so that they fill waves of their own instead of diverging every wave.
+    constexpr int RG = LPC * (N - 1) + 2;
+    int kzl, p;
+    if (tid < NP2 * RG) {
+        p = tid / RG;
+        const int r = tid - p * RG;
+        if (r == 0) kzl = 0;
+        else if (r == RG - 1) kzl = NK - 1;
+        else if constexpr (N > 1) kzl = ((r - 1) / (N - 1)) * N + (r - 1) % (N - 1) + 1;
+        else kzl = 0;
+    } else if constexpr (LPC > 1) {
+        const int t2 = tid - NP2 * RG;
+        p = t2 / (LPC - 1);
+        kzl = (t2 - p * (LPC - 1) + 1) * N;
+    } else {
+        p = NP2;
+        kzl = 0;
+    }
     const bool lane_ok = (p < NP2) && (item < ncol);
     const int pc = lane_ok ? p : 0;               // position used for table lookups
     const int i = pc % NP, j = pc / NP;
@@ -148,7 +179,7 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
             tile[3][lidx] = u;
             tile[4][lidx] = v;
             tile[5][lidx] = w;
-            tile[6][lidx] = pressure_perturbation<T>(r0d, m.theta0[kz], m.p0[kz], m.gamma, qv[0], qv[4]);
+            tile[6][lidx] = pressure_perturbation<T>(m, kz, qv[0], qv[4]);
             tile[7][lidx] = T(qv[4]);
         }
         __syncthreads();
