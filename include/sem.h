@@ -22,10 +22,14 @@
  *               horizontal node h in [0, n_h) and a vertical node
  *               kz in [0, nzn), nzn = n_z*N + 1 (kz = layer*N + k).
  *               n_dof = n_h * nzn.
- * State layout: double q[F][n_h][nzn] (field-major, kz fastest), device memory.
+ * State layout: double q[F][n_h][ldz] (field-major, kz fastest), device memory,
+ *               with the row stride ldz = nzn rounded up to a multiple of 16
+ *               (128 bytes), so that each vertical row starts on a cache line.
+ *               Entries kz >= nzn are padding: compute calls never read them;
+ *               only sem_stage_update (element-wise) writes them.
  * Hanging     : a hanging point hh in [0, n_hh) is a horizontal position on a
  *               fine column's face that is not a node of the coarser neighbour
- *               (Section 3.1); hanging values are double hv[F][n_hh][nzn].
+ *               (Section 3.1); hanging values are double hv[F][n_hh][ldz].
  * Elements    : e = c*n_z + layer for column c (in the order given at create)
  *               and layer in [0, n_z); local node l = i + (N+1)(j + (N+1)k)
  *               with i along x, j along y, k along z (Section 3, basis).
@@ -96,7 +100,7 @@ typedef struct {
 } sem_mesh_desc;
 
 typedef struct {
-    int32_t N, n_z, nzn, max_level;
+    int32_t N, n_z, nzn, ldz, max_level;
     int64_t n_col, n_elem, n_h, n_hh, n_dof, n_hang, n_local;
     int64_t workspace_bytes;   /* device memory held by the handle            */
 } sem_mesh_info;
@@ -115,7 +119,7 @@ int sem_mesh_destroy(sem_mesh *mesh);
  * numbering as sem_mesh_create and report sizes in *info; when the arrays are
  * non-NULL also fill h_hxy[2*n_h], h_hhxy[2*n_hh], h_z[nzn] (as in
  * sem_mesh_coords) and h_mass[n_dof], the assembled lumped mass M_G at each
- * unique node in state order.  Call once with NULL arrays to learn the sizes. */
+ * unique node, packed as [h][kz] (no padding).  Call once with NULL arrays to learn the sizes. */
 int sem_mesh_plan(const sem_mesh_desc *desc, sem_mesh_info *info, double *h_hxy,
                   double *h_hhxy, double *h_z, double *h_mass);
 int sem_mesh_get_info(const sem_mesh *mesh, sem_mesh_info *out);
@@ -135,9 +139,9 @@ int sem_mesh_set_reference(sem_mesh *mesh, const double *h_rho0,
                            const double *h_theta0, const double *h_dtheta0dz);
 
 /* Modified-DSS interpolation across nonconforming faces (Section 3.1).
- * SEM_SCATTER: d_dst = hv[F][n_hh][nzn] is overwritten with Z_h d_src, the
- *              values at hanging points interpolated from d_src = q[F][n_h][nzn].
- * SEM_GATHER : d_dst = acc[F][n_h][nzn] += Z_h^T d_src, d_src = c[F][n_hh][nzn]
+ * SEM_SCATTER: d_dst = hv[F][n_hh][ldz] is overwritten with Z_h d_src, the
+ *              values at hanging points interpolated from d_src = q[F][n_h][ldz].
+ * SEM_GATHER : d_dst = acc[F][n_h][ldz] += Z_h^T d_src, d_src = c[F][n_hh][ldz]
  *              holding contributions summed at hanging points.
  * A mesh without hanging points makes both a no-op. */
 int sem_nc_project(const sem_mesh *mesh, int dir, const double *d_src,
@@ -147,21 +151,21 @@ int sem_nc_project(const sem_mesh *mesh, int dir, const double *d_src,
  * collocated at the LGL nodes of every element, Section 3), multiplied by the
  * lumped LGL mass w_i w_j w_k |J_e|:
  *   d_rE[F][n_elem][(N+1)^3] = m_l * R_l.
- * Inputs: d_q = q[F][n_h][nzn], d_hv = hanging values from SEM_SCATTER (may
+ * Inputs: d_q = q[F][n_h][ldz], d_hv = hanging values from SEM_SCATTER (may
  * be NULL when n_hh = 0).  precision = SEM_FP64 or SEM_FP32. */
 int sem_rhs(const sem_mesh *mesh, const double *d_q, const double *d_hv,
             double *d_rE, int precision, void *stream);
 
 /* Direct stiffness summation (Section 3.1).
- * SEM_ASSEMBLE: d_acc[F][n_h][nzn] = sum of d_rE over the local copies of each
- *               unique node; d_c[F][n_hh][nzn] = the same at hanging points
+ * SEM_ASSEMBLE: d_acc[F][n_h][ldz] = sum of d_rE over the local copies of each
+ *               unique node; d_c[F][n_hh][ldz] = the same at hanging points
  *               (pass d_c to sem_nc_project(SEM_GATHER) to add Z_h^T c).
- * SEM_FINALIZE: d_r[F][n_h][nzn] = d_acc / M_G, then r_w = 0 on the lids.
+ * SEM_FINALIZE: d_r[F][n_h][ldz] = d_acc / M_G, then r_w = 0 on the lids.
  * Unused pointers for a phase may be NULL. */
 int sem_dss(const sem_mesh *mesh, int phase, const double *d_rE, double *d_acc,
             double *d_c, double *d_r, void *stream);
 
-/* Runge-Kutta stage combination (Section 5), element-wise over 5*n_dof values:
+/* Runge-Kutta stage combination (Section 5), element-wise over 5*n_h*ldz values:
  *   d_qout = a*d_qn + b*d_qs + c*d_r        (any pointers may alias). */
 int sem_stage_update(const sem_mesh *mesh, double a, double b, double c,
                      const double *d_qn, const double *d_qs, const double *d_r,

@@ -116,6 +116,39 @@ class Mesh:
         return self.info["n_hang"]
 
     @property
+    def ldz(self):
+        return self.info["ldz"]
+
+    @property
+    def n_state(self):
+        """Doubles of a state array q[5][n_h][ldz] (padded rows)."""
+        return NF * self.info["n_h"] * self.info["ldz"]
+
+    @property
+    def n_hstate(self):
+        """Doubles of a hanging-point array hv[5][n_hh][ldz]."""
+        return NF * self.info["n_hh"] * self.info["ldz"]
+
+    def unpack(self, packed, device="cuda"):
+        """Packed values (5, n_h*nzn) in [h][kz] order -> padded state tensor."""
+        i = self.info
+        a = torch.as_tensor(np.asarray(packed, dtype=np.float64)).reshape(NF, i["n_h"], i["nzn"])
+        out = torch.zeros(NF, i["n_h"], i["ldz"], dtype=torch.float64)
+        out[:, :, : i["nzn"]] = a
+        return out.reshape(-1).to(device)
+
+    def pack(self, state):
+        """Padded state tensor -> numpy (5, n_h*nzn) in [h][kz] order."""
+        i = self.info
+        a = state.detach().reshape(NF, i["n_h"], i["ldz"])[:, :, : i["nzn"]]
+        return a.cpu().numpy().reshape(NF, -1)
+
+    def pack_hang(self, hv):
+        i = self.info
+        a = hv.detach().reshape(NF, i["n_hh"], i["ldz"])[:, :, : i["nzn"]]
+        return a.cpu().numpy().reshape(NF, -1)
+
+    @property
     def n_local(self):
         return self.info["n_local"]
 
@@ -156,13 +189,13 @@ class Mesh:
         native.call("sem_mesh_set_reference", self.handle,
                     *[a.ctypes.data_as(native.c_dp) for a in arrs])
 
-    # workspace-free tensors of the right shapes
     def state(self, device="cuda"):
-        return torch.zeros(NF * self.n_dof, dtype=torch.float64, device=device)
+        """A zeroed state tensor (padding stays zero under every compute call)."""
+        return torch.zeros(self.n_state, dtype=torch.float64, device=device)
 
 
 def sem_nc_project(mesh, direction, src, dst, stream=None):
-    nd, nh = NF * mesh.n_dof, NF * mesh.n_hang
+    nd, nh = mesh.n_state, mesh.n_hstate
     if direction == SEM_SCATTER:
         s, d = _ptr(src, torch.float64, nd, "src"), _ptr(dst, torch.float64, nh, "dst")
     else:
@@ -171,21 +204,21 @@ def sem_nc_project(mesh, direction, src, dst, stream=None):
 
 
 def sem_rhs(mesh, q, hv, rE, precision=SEM_FP64, stream=None):
-    native.call("sem_rhs", mesh.handle, _ptr(q, torch.float64, NF * mesh.n_dof, "q"),
-                _ptr(hv, torch.float64, NF * mesh.n_hang, "hv") if mesh.n_hang else None,
+    native.call("sem_rhs", mesh.handle, _ptr(q, torch.float64, mesh.n_state, "q"),
+                _ptr(hv, torch.float64, mesh.n_hstate, "hv") if mesh.n_hang else None,
                 _ptr(rE, torch.float64, NF * mesh.n_local, "rE"), int(precision), _stream(stream))
 
 
 def sem_dss(mesh, phase, rE=None, acc=None, c=None, r=None, stream=None):
     native.call("sem_dss", mesh.handle, int(phase),
                 _ptr(rE, torch.float64, NF * mesh.n_local, "rE"),
-                _ptr(acc, torch.float64, NF * mesh.n_dof, "acc"),
-                _ptr(c, torch.float64, NF * mesh.n_hang, "c") if mesh.n_hang else None,
-                _ptr(r, torch.float64, NF * mesh.n_dof, "r"), _stream(stream))
+                _ptr(acc, torch.float64, mesh.n_state, "acc"),
+                _ptr(c, torch.float64, mesh.n_hstate, "c") if mesh.n_hang else None,
+                _ptr(r, torch.float64, mesh.n_state, "r"), _stream(stream))
 
 
 def sem_stage_update(mesh, a, b, c, qn, qs, r, qout, stream=None):
-    n = NF * mesh.n_dof
+    n = mesh.n_state
     native.call("sem_stage_update", mesh.handle, float(a), float(b), float(c),
                 _ptr(qn, torch.float64, n, "qn"), _ptr(qs, torch.float64, n, "qs"),
                 _ptr(r, torch.float64, n, "r"), _ptr(qout, torch.float64, n, "qout"),
@@ -193,7 +226,7 @@ def sem_stage_update(mesh, a, b, c, qn, qs, r, qout, stream=None):
 
 
 def sem_stage(mesh, a, b, c, qn, qs, qout, precision=SEM_FP64, stream=None):
-    n = NF * mesh.n_dof
+    n = mesh.n_state
     native.call("sem_stage", mesh.handle, float(a), float(b), float(c),
                 _ptr(qn, torch.float64, n, "qn"), _ptr(qs, torch.float64, n, "qs"),
                 _ptr(qout, torch.float64, n, "qout"), int(precision), _stream(stream))
@@ -203,7 +236,7 @@ def amr_flag(mesh, q, criterion, thresholds, lvl_max, adapt_elem, adapt_col, str
     thr = np.ascontiguousarray(np.asarray(thresholds, dtype=np.float64))
     if thr.size < lvl_max:
         raise ValueError("need one threshold per level")
-    native.call("amr_flag", mesh.handle, _ptr(q, torch.float64, NF * mesh.n_dof, "q"),
+    native.call("amr_flag", mesh.handle, _ptr(q, torch.float64, mesh.n_state, "q"),
                 int(criterion), thr.ctypes.data_as(native.c_dp) if thr.size else None,
                 int(lvl_max), _ptr(adapt_elem, torch.int8, mesh.info["n_elem"], "adapt_elem"),
                 _ptr(adapt_col, torch.int8, mesh.info["n_col"], "adapt_col"), _stream(stream))
@@ -221,7 +254,7 @@ def sem_stage_get_tune(mesh):
 
 def sem_stage_autotune(mesh, qn, qs, qout, precision=SEM_FP64, reps=5, stream=None):
     """Pick the fastest chunk depth on this mesh; returns (layers_per_chunk, ms)."""
-    n = NF * mesh.n_dof
+    n = mesh.n_state
     lpc, ms = ctypes.c_int(), ctypes.c_float()
     native.call("sem_stage_autotune", mesh.handle, _ptr(qn, torch.float64, n, "qn"),
                 _ptr(qs, torch.float64, n, "qs"), _ptr(qout, torch.float64, n, "qout"),

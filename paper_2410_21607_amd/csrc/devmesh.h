@@ -8,6 +8,7 @@ namespace sem {
 
 struct DevMesh {
     int N, n_z, nzn, n_col;
+    int ldz;                  // row stride of [field][h][kz] arrays: nzn rounded up to 16
     int n_h, n_hh, n_hT;
     double f, g, gamma;
     const int32_t* gmap;      // n_col*(N+1)^2: h >= 0, or -(hh+1)

@@ -190,6 +190,7 @@ int build_host_mesh(const MeshInput& in, HostMesh& m, std::string& err) {
         if (!(in.z_edges[k + 1] > in.z_edges[k])) { err = "z_edges must increase"; return SEM_ERR_ARG; }
     const int N = in.N, np1 = N + 1, np2 = np1 * np1;
     m.N = N; m.np1 = np1; m.n_z = in.n_z; m.nzn = in.n_z * N + 1;
+    m.ldz = (m.nzn + 15) / 16 * 16;
     m.nx0 = in.nx0; m.ny0 = in.ny0; m.periodic_x = in.periodic_x; m.periodic_y = in.periodic_y;
     m.Lx = in.Lx; m.Ly = in.Ly;
     m.f = in.f; m.g = in.g; m.R_d = in.R_d; m.c_p = in.c_p; m.p00 = in.p00;
@@ -372,7 +373,7 @@ int build_host_mesh(const MeshInput& in, HostMesh& m, std::string& err) {
         if (hid.count(kv.first)) { err = "a hanging point is also a conforming node"; return SEM_ERR_MESH; }
     m.n_h = int64_t(hid.size());
     m.n_hh = int64_t(hhid.size());
-    if (m.n_h * int64_t(m.nzn) >= (int64_t(1) << 31) || m.n_hh * int64_t(m.nzn) >= (int64_t(1) << 31) ||
+    if (m.n_h * int64_t(m.ldz) >= (int64_t(1) << 31) || m.n_hh * int64_t(m.ldz) >= (int64_t(1) << 31) ||
         int64_t(in.n_col) * in.n_z * np1 * np2 >= (int64_t(1) << 31)) {
         err = "mesh too large for 32-bit node indices"; return SEM_ERR_MESH;
     }

@@ -30,6 +30,7 @@ void lagrange_weights(const Basis1D& b, double s, double* out);
 struct HostMesh {
     // description
     int N = 0, np1 = 0, n_z = 0, nzn = 0, nx0 = 0, ny0 = 0, max_level = 0;
+    int ldz = 0;   // padded row stride (128-byte multiple) of [field][h][kz] arrays
     bool periodic_x = true, periodic_y = true;
     double Lx = 0, Ly = 0;
     double f = 0, g = 0, R_d = 0, c_p = 0, p00 = 0;

@@ -67,37 +67,38 @@ namespace sem {
 // interpolating hanging points through their rows
 __device__ __forceinline__ double node_value(const DevMesh& m, const double* __restrict__ q,
                                              int g, int f, int kz) {
-    const int64_t fs = int64_t(m.n_h) * m.nzn;
-    if (g >= 0) return q[f * fs + int64_t(g) * m.nzn + kz];
+    const int64_t fs = int64_t(m.n_h) * m.ldz;
+    if (g >= 0) return q[f * fs + int64_t(g) * m.ldz + kz];
     const int hh = -g - 1;
     double s = 0.0;
     for (int t = m.hang_ptr[hh]; t < m.hang_ptr[hh + 1]; ++t)
-        s += m.hang_w[t] * q[f * fs + int64_t(m.hang_src[t]) * m.nzn + kz];
+        s += m.hang_w[t] * q[f * fs + int64_t(m.hang_src[t]) * m.ldz + kz];
     return s;
 }
 
 __global__ void k_nc_scatter(DevMesh m, const double* __restrict__ src, double* __restrict__ dst) {
     const int64_t n = int64_t(m.n_hh) * m.nzn;
-    const int64_t fs = int64_t(m.n_h) * m.nzn;
+    const int64_t fs = int64_t(m.n_h) * m.ldz, fsh = int64_t(m.n_hh) * m.ldz;
     for (int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; t < n;
          t += int64_t(gridDim.x) * blockDim.x) {
         const int hh = int(t / m.nzn), kz = int(t % m.nzn);
         double s[NF] = {0, 0, 0, 0, 0};
         for (int r = m.hang_ptr[hh]; r < m.hang_ptr[hh + 1]; ++r) {
             const double w = m.hang_w[r];
-            const int64_t base = int64_t(m.hang_src[r]) * m.nzn + kz;
+            const int64_t base = int64_t(m.hang_src[r]) * m.ldz + kz;
 #pragma unroll
             for (int f = 0; f < NF; ++f) s[f] += w * src[f * fs + base];
         }
+        const int64_t o = int64_t(hh) * m.ldz + kz;
 #pragma unroll
-        for (int f = 0; f < NF; ++f) dst[f * n + t] = s[f];
+        for (int f = 0; f < NF; ++f) dst[f * fsh + o] = s[f];
     }
 }
 
 __global__ void k_nc_gather(DevMesh m, const double* __restrict__ src, double* __restrict__ dst) {
     const int64_t n = int64_t(m.n_hT) * m.nzn;
-    const int64_t fs = int64_t(m.n_h) * m.nzn;
-    const int64_t fsh = int64_t(m.n_hh) * m.nzn;
+    const int64_t fs = int64_t(m.n_h) * m.ldz;
+    const int64_t fsh = int64_t(m.n_hh) * m.ldz;
     for (int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; t < n;
          t += int64_t(gridDim.x) * blockDim.x) {
         const int li = int(t / m.nzn), kz = int(t % m.nzn);
@@ -105,11 +106,11 @@ __global__ void k_nc_gather(DevMesh m, const double* __restrict__ src, double* _
         double s[NF] = {0, 0, 0, 0, 0};
         for (int r = m.hT_ptr[li]; r < m.hT_ptr[li + 1]; ++r) {
             const double w = m.hT_w[r];
-            const int64_t base = int64_t(m.hT_hh[r]) * m.nzn + kz;
+            const int64_t base = int64_t(m.hT_hh[r]) * m.ldz + kz;
 #pragma unroll
             for (int f = 0; f < NF; ++f) s[f] += w * src[f * fsh + base];
         }
-        const int64_t o = int64_t(h) * m.nzn + kz;
+        const int64_t o = int64_t(h) * m.ldz + kz;
 #pragma unroll
         for (int f = 0; f < NF; ++f) dst[f * fs + o] += s[f];
     }
@@ -130,17 +131,17 @@ k_rhs(DevMesh m, const double* __restrict__ q, const double* __restrict__ hv,
     if (t < NP2) sD[t] = T(m.D[t]);
     const int i = t % NP, j = (t / NP) % NP, k = t / NP2;
     const int kz = layer * N + k;
-    const int64_t fs = int64_t(m.n_h) * m.nzn, fsh = int64_t(m.n_hh) * m.nzn;
+    const int64_t fs = int64_t(m.n_h) * m.ldz, fsh = int64_t(m.n_hh) * m.ldz;
     T rp = 0, u = 0, v = 0, w = 0, tp = 0, rho = 1, rho_p = 0;
     if (t < NP3) {
         const int g = m.gmap[c * NP2 + i + NP * j];
         double x[NF];
         if (g >= 0) {
 #pragma unroll
-            for (int f = 0; f < NF; ++f) x[f] = q[f * fs + int64_t(g) * m.nzn + kz];
+            for (int f = 0; f < NF; ++f) x[f] = q[f * fs + int64_t(g) * m.ldz + kz];
         } else {
 #pragma unroll
-            for (int f = 0; f < NF; ++f) x[f] = hv[f * fsh + int64_t(-g - 1) * m.nzn + kz];
+            for (int f = 0; f < NF; ++f) x[f] = hv[f * fsh + int64_t(-g - 1) * m.ldz + kz];
         }
         const double r0 = m.rho0[kz], th0 = m.theta0[kz];
         rp = T(x[0]); u = T(x[1]); v = T(x[2]); w = T(x[3]); tp = T(x[4]);
@@ -231,8 +232,9 @@ __global__ void k_assemble(DevMesh m, const double* __restrict__ rE, double* __r
         const int h = int(t / m.nzn), kz = int(t % m.nzn);
         double s[NF];
         sum_local(m, rE, m.asm_slot, m.asm_ptr[h], m.asm_ptr[h + 1], kz, s);
+        const int64_t o = int64_t(h) * m.ldz + kz, fs = int64_t(m.n_h) * m.ldz;
 #pragma unroll
-        for (int f = 0; f < NF; ++f) acc[f * n + t] = s[f];
+        for (int f = 0; f < NF; ++f) acc[f * fs + o] = s[f];
     }
 }
 
@@ -243,8 +245,9 @@ __global__ void k_assemble_hang(DevMesh m, const double* __restrict__ rE, double
         const int hh = int(t / m.nzn), kz = int(t % m.nzn);
         double s[NF];
         sum_local(m, rE, m.asmH_slot, m.asmH_ptr[hh], m.asmH_ptr[hh + 1], kz, s);
+        const int64_t o = int64_t(hh) * m.ldz + kz, fsh = int64_t(m.n_hh) * m.ldz;
 #pragma unroll
-        for (int f = 0; f < NF; ++f) cH[f * n + t] = s[f];
+        for (int f = 0; f < NF; ++f) cH[f * fsh + o] = s[f];
     }
 }
 
@@ -255,11 +258,12 @@ __global__ void k_finalize(DevMesh m, const double* __restrict__ acc, double* __
         const int h = int(t / m.nzn), kz = int(t % m.nzn);
         const double minv = m.minv_h[h] * m.minv_v[kz];
         const bool lid = (kz == 0) || (kz == m.nzn - 1);
+        const int64_t o = int64_t(h) * m.ldz + kz, fs = int64_t(m.n_h) * m.ldz;
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
-            double v = acc[f * n + t] * minv;
+            double v = acc[f * fs + o] * minv;
             if (f == 3 && lid) v = 0.0;
-            r[f * n + t] = v;
+            r[f * fs + o] = v;
         }
     }
 }
@@ -412,7 +416,7 @@ int sem_mesh_create(const sem_mesh_desc* desc, sem_mesh** out) {
     if (rc != SEM_OK) return fail(rc, err);
     const sem::HostMesh& H = M->host;
     DevMesh& d = M->d;
-    d.N = H.N; d.n_z = H.n_z; d.nzn = H.nzn; d.n_col = H.n_col;
+    d.N = H.N; d.n_z = H.n_z; d.nzn = H.nzn; d.ldz = H.ldz; d.n_col = H.n_col;
     d.n_h = int(H.n_h); d.n_hh = int(H.n_hh); d.n_hT = int(H.hT_list.size());
     d.f = H.f; d.g = H.g;
     d.gamma = H.c_p / (H.c_p - H.R_d);
@@ -452,7 +456,7 @@ int sem_mesh_plan(const sem_mesh_desc* desc, sem_mesh_info* o, double* hxy, doub
     std::string err;
     int rc = sem::build_host_mesh(in, H, err);
     if (rc != SEM_OK) return fail(rc, err);
-    o->N = H.N; o->n_z = H.n_z; o->nzn = H.nzn; o->max_level = H.max_level;
+    o->N = H.N; o->n_z = H.n_z; o->nzn = H.nzn; o->ldz = H.ldz; o->max_level = H.max_level;
     o->n_col = H.n_col; o->n_elem = int64_t(H.n_col) * H.n_z;
     o->n_h = H.n_h; o->n_hh = H.n_hh;
     o->n_dof = H.n_h * H.nzn; o->n_hang = H.n_hh * H.nzn;
@@ -477,7 +481,7 @@ int sem_mesh_destroy(sem_mesh* mesh) {
 int sem_mesh_get_info(const sem_mesh* M, sem_mesh_info* o) {
     if (!M || !o) return fail(SEM_ERR_ARG, "null argument");
     const sem::HostMesh& H = M->host;
-    o->N = H.N; o->n_z = H.n_z; o->nzn = H.nzn; o->max_level = H.max_level;
+    o->N = H.N; o->n_z = H.n_z; o->nzn = H.nzn; o->ldz = H.ldz; o->max_level = H.max_level;
     o->n_col = H.n_col; o->n_elem = int64_t(H.n_col) * H.n_z;
     o->n_h = H.n_h; o->n_hh = H.n_hh;
     o->n_dof = H.n_h * H.nzn; o->n_hang = H.n_hh * H.nzn;
@@ -569,7 +573,7 @@ int sem_stage_update(const sem_mesh* M, double a, double b, double c, const doub
                      const double* qs, const double* r, double* qout, void* stream) {
     if (!M) return fail(SEM_ERR_ARG, "null mesh");
     if (!qn || !qs || !r || !qout) return fail(SEM_ERR_ARG, "null array");
-    const int64_t n = int64_t(NF) * M->d.n_h * M->d.nzn;
+    const int64_t n = int64_t(NF) * M->d.n_h * M->d.ldz;
     hipLaunchKernelGGL(sem::k_update, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)stream, n, a, b, c,
                        qn, qs, r, qout);
     HIPCHK(hipGetLastError());

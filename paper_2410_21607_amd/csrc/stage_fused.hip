@@ -123,8 +123,8 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
     const int pc = lane_ok ? p : 0;               // position used for table lookups
     const int i = pc % NP, j = pc / NP;
     const int nzn = m.nzn;
-    const int64_t fs = int64_t(m.n_h) * nzn;
-    const int64_t fsh = int64_t(m.n_hh) * nzn;
+    const int64_t fs = int64_t(m.n_h) * m.ldz;
+    const int64_t fsh = int64_t(m.n_hh) * m.ldz;
 
     int g = 0, r_beg = 0, r_end = 0;
     bool first = false;
@@ -159,13 +159,13 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
         T rho = T(1);
         if (active) {
             if (g >= 0) {
-                const int64_t o = int64_t(g) * nzn + kz;
+                const int64_t o = int64_t(g) * m.ldz + kz;
 #pragma unroll
                 for (int f = 0; f < NF; ++f) qv[f] = qs[f * fs + o];
             } else {
                 for (int r = r_beg; r < r_end; ++r) {
                     const double w = m.hang_w[r];
-                    const int64_t o = int64_t(m.hang_src[r]) * nzn + kz;
+                    const int64_t o = int64_t(m.hang_src[r]) * m.ldz + kz;
 #pragma unroll
                     for (int f = 0; f < NF; ++f) qv[f] += w * qs[f * fs + o];
                 }
@@ -186,7 +186,7 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
         double base[NF] = {0, 0, 0, 0, 0};
         if (active && g >= 0) {
             const double* bp = first ? qn : qo;
-            const int64_t o = int64_t(g) * nzn + kz;
+            const int64_t o = int64_t(g) * m.ldz + kz;
 #pragma unroll
             for (int f = 0; f < NF; ++f) base[f] = bp[f * fs + o];
         }
@@ -264,7 +264,7 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
                 if (g >= 0) {
                     const bool lid = (kz == 0) || (kz == nzn - 1);
                     const double mi = c * minv_h * m.minv_v[kz];
-                    const int64_t o = int64_t(g) * nzn + kz;
+                    const int64_t o = int64_t(g) * m.ldz + kz;
                     if (first) {
 #pragma unroll
                         for (int fl = 0; fl < NF; ++fl) {
@@ -277,7 +277,7 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
                             if (!(fl == 3 && lid)) qo[fl * fs + o] = base[fl] + mi * acc[fl];
                     }
                 } else {
-                    const int64_t o = int64_t(-g - 1) * nzn + kz;
+                    const int64_t o = int64_t(-g - 1) * m.ldz + kz;
                     if (first) {
 #pragma unroll
                         for (int fl = 0; fl < NF; ++fl) ft.cH[fl * fsh + o] = acc[fl];
@@ -296,8 +296,8 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
 __global__ void k_stage_hanging(DevMesh m, FusedTables ft, double c, double* __restrict__ qo) {
     const int nzn = m.nzn;
     const int64_t n = int64_t(m.n_hT) * nzn;
-    const int64_t fs = int64_t(m.n_h) * nzn;
-    const int64_t fsh = int64_t(m.n_hh) * nzn;
+    const int64_t fs = int64_t(m.n_h) * m.ldz;
+    const int64_t fsh = int64_t(m.n_hh) * m.ldz;
     for (int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; t < n;
          t += int64_t(gridDim.x) * blockDim.x) {
         const int li = int(t / nzn), kz = int(t - int64_t(li) * nzn);
@@ -305,13 +305,13 @@ __global__ void k_stage_hanging(DevMesh m, FusedTables ft, double c, double* __r
         double s[NF] = {0, 0, 0, 0, 0};
         for (int r = m.hT_ptr[li]; r < m.hT_ptr[li + 1]; ++r) {
             const double w = m.hT_w[r];
-            const int64_t o = int64_t(m.hT_hh[r]) * nzn + kz;
+            const int64_t o = int64_t(m.hT_hh[r]) * m.ldz + kz;
 #pragma unroll
             for (int f = 0; f < NF; ++f) s[f] += w * ft.cH[f * fsh + o];
         }
         const bool lid = (kz == 0) || (kz == nzn - 1);
         const double mi = c * m.minv_h[h] * m.minv_v[kz];
-        const int64_t o = int64_t(h) * nzn + kz;
+        const int64_t o = int64_t(h) * m.ldz + kz;
 #pragma unroll
         for (int f = 0; f < NF; ++f)
             if (!(f == 3 && lid)) qo[f * fs + o] += mi * s[f];
@@ -424,7 +424,7 @@ int fused_plan_build(const HostMesh& H, int lpc, FusedPlan& P) {
     P.t.color_ptr = static_cast<const int32_t*>(d);
     if ((rc = up(first.data(), first.size(), &d)) != SEM_OK) return rc;
     P.t.first = static_cast<const uint8_t*>(d);
-    if ((rc = up(nullptr, size_t(NF) * H.n_hh * H.nzn * 8, &d)) != SEM_OK) return rc;
+    if ((rc = up(nullptr, size_t(NF) * H.n_hh * H.ldz * 8, &d)) != SEM_OK) return rc;
     P.t.cH = static_cast<double*>(d);
     P.t.n_color = n_color;
     P.t.layers_per_chunk = lpc;

@@ -35,7 +35,7 @@ class SemMeshDesc(ctypes.Structure):
 
 class SemMeshInfo(ctypes.Structure):
     _fields_ = [("N", ctypes.c_int32), ("n_z", ctypes.c_int32), ("nzn", ctypes.c_int32),
-                ("max_level", ctypes.c_int32), ("n_col", ctypes.c_int64),
+                ("ldz", ctypes.c_int32), ("max_level", ctypes.c_int32), ("n_col", ctypes.c_int64),
                 ("n_elem", ctypes.c_int64), ("n_h", ctypes.c_int64), ("n_hh", ctypes.c_int64),
                 ("n_dof", ctypes.c_int64), ("n_hang", ctypes.c_int64),
                 ("n_local", ctypes.c_int64), ("workspace_bytes", ctypes.c_int64)]

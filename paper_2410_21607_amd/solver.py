@@ -31,13 +31,14 @@ class Stepper:
         self.mesh = mesh
         self.dt = float(dt)
         self.precision = precision
-        n = 5 * mesh.n_dof
+        n = mesh.n_state
         if q0.numel() != n:
-            raise ValueError("initial state has the wrong size")
+            raise ValueError("initial state has the wrong size (expected the padded layout)")
+        # zero-filled so that the row padding stays zero (no call writes it)
         self.buf = [q0.detach().to(torch.float64).contiguous().clone(),
-                    torch.empty(n, dtype=torch.float64, device=q0.device)]
-        self.s1 = torch.empty(n, dtype=torch.float64, device=q0.device)
-        self.s2 = torch.empty(n, dtype=torch.float64, device=q0.device)
+                    torch.zeros(n, dtype=torch.float64, device=q0.device)]
+        self.s1 = torch.zeros(n, dtype=torch.float64, device=q0.device)
+        self.s2 = torch.zeros(n, dtype=torch.float64, device=q0.device)
         self.cur = 0
         self.steps = 0
         self.graphs = None

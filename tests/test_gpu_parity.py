@@ -51,12 +51,11 @@ class Setup:
         # the hydrostatic and gradient-wind cancellations
         q_g = cases.initial_state(c, self.gxyz)
         np.testing.assert_allclose(q_g, self.q_or[:, self.perm], rtol=1e-12, atol=1e-12)
-        self.q_g = torch.tensor(np.ascontiguousarray(self.q_or[:, self.perm]).reshape(-1),
-                                dtype=torch.float64, device="cuda")
+        self.q_g = self.gm.unpack(self.q_or[:, self.perm])
         self.ref = oracle_reference_local(c, self.om)
 
     def to_oracle_order(self, flat):
-        a = flat.detach().cpu().numpy().reshape(5, -1)
+        a = self.gm.pack(flat)
         out = np.empty_like(a)
         out[:, self.perm] = a
         return out
@@ -76,7 +75,7 @@ def test_nc_scatter(name, kw):
         pytest.skip("conforming mesh")
     torch, api = S.torch, S.api
     say("nc_scatter", name, kw)
-    hv = torch.zeros(5 * S.gm.n_hang, dtype=torch.float64, device="cuda")
+    hv = torch.zeros(S.gm.n_hstate, dtype=torch.float64, device="cuda")
     api.sem_nc_project(S.gm, api.SEM_SCATTER, S.q_g, hv)
     torch.cuda.synchronize()
     qL = assembly.scatter(S.om, S.q_or).reshape(5, -1)
@@ -84,7 +83,7 @@ def test_nc_scatter(name, kw):
     _, first = np.unique(_keys(oh, S.c), axis=0, return_index=True)
     hidx = np.nonzero(S.om.hanging)[0][first]
     perm = match(oh[first], S.gm.hang_xyz(), S.c)
-    got = hv.cpu().numpy().reshape(5, -1)
+    got = S.gm.pack_hang(hv)
     want = qL[:, hidx][:, perm]
     err = metrics.rel_l2(got, want, metrics.STATE_FLOORS)
     say("  rel", err)
@@ -104,7 +103,7 @@ def test_rhs_element_contributions(name, kw):
     S = get(name, kw)
     torch, api = S.torch, S.api
     say("sem_rhs", name, kw)
-    hv = torch.zeros(max(5 * S.gm.n_hang, 1), dtype=torch.float64, device="cuda")[: 5 * S.gm.n_hang]
+    hv = torch.zeros(S.gm.n_hstate, dtype=torch.float64, device="cuda")
     if S.gm.n_hang:
         api.sem_nc_project(S.gm, api.SEM_SCATTER, S.q_g, hv)
     rE = torch.zeros(5 * S.gm.n_local, dtype=torch.float64, device="cuda")
@@ -120,7 +119,7 @@ def test_rhs_element_contributions(name, kw):
 
 def _gpu_rhs(S, prec):
     torch, api = S.torch, S.api
-    n, nh, nl = 5 * S.gm.n_dof, 5 * S.gm.n_hang, 5 * S.gm.n_local
+    n, nh, nl = S.gm.n_state, S.gm.n_hstate, 5 * S.gm.n_local
     z = lambda k: torch.zeros(k, dtype=torch.float64, device="cuda")
     hv, rE, acc, cH, r = z(nh), z(nl), z(n), z(nh), z(n)
     if nh:
@@ -166,7 +165,7 @@ def test_stages_match_oracle(name, kw):
     say("stages", name, kw, nst)
     qn = S.q_g.clone()
     qs = S.q_g.clone()
-    out = torch.empty_like(qn)
+    out = torch.zeros_like(qn)
     for st in range(nst):
         a, b, cc = timestep.stage_coefficients(st % 3, dt)
         api.sem_stage(S.gm, a, b, cc, qn, qs, out, api.SEM_FP64)
@@ -185,10 +184,10 @@ def test_stage_update_elementwise():
     S = get(*CASES[0])
     torch, api = S.torch, S.api
     say("stage_update")
-    n = 5 * S.gm.n_dof
+    n = S.gm.n_state
     g = torch.Generator(device="cuda").manual_seed(5)
     qn, qs, r = (torch.rand(n, dtype=torch.float64, device="cuda", generator=g) for _ in range(3))
-    out = torch.empty_like(qn)
+    out = torch.zeros_like(qn)
     api.sem_stage_update(S.gm, 0.75, 0.25, 0.1, qn, qs, r, out)
     torch.cuda.synchronize()
     want = 0.75 * qn.cpu().numpy() + 0.25 * qs.cpu().numpy() + 0.1 * r.cpu().numpy()
@@ -235,13 +234,13 @@ def test_api_rejects_bad_calls():
     with pytest.raises(SemError):
         api.sem_stage(S.gm, 0.0, 1.0, 1.0, q, q, q, api.SEM_FP64)   # aliasing
     with pytest.raises(SemError):
-        api.sem_stage(S.gm, 0.0, 1.0, 1.0, q, q.clone(), torch.empty_like(q), 7)
+        api.sem_stage(S.gm, 0.0, 1.0, 1.0, q, q.clone(), torch.zeros_like(q), 7)
     with pytest.raises(SemError):
         api.amr_flag(S.gm, q, 0, [2.0, 1.0], 2,
                      torch.zeros(S.gm.info["n_elem"], dtype=torch.int8, device="cuda"),
                      torch.zeros(S.gm.info["n_col"], dtype=torch.int8, device="cuda"))
     with pytest.raises(ValueError):
-        api.sem_stage(S.gm, 0.0, 1.0, 1.0, q[:-1], q.clone(), torch.empty_like(q))
+        api.sem_stage(S.gm, 0.0, 1.0, 1.0, q[:-1], q.clone(), torch.zeros_like(q))
 
 
 TUNES = [1, 2, 4, 8]
@@ -264,7 +263,7 @@ def test_fused_stage_decompositions(name, kw, ipw):
         dt = S.c["dt"]
         qn = S.q_g.clone()
         qs = S.q_g.clone()
-        out = torch.empty_like(qn)
+        out = torch.zeros_like(qn)
         for st in range(3):
             a, b, cc = timestep.stage_coefficients(st, dt)
             api.sem_stage(S.gm, a, b, cc, qn, qs, out, api.SEM_FP64)
@@ -287,7 +286,7 @@ def test_fused_fp32_stage_error():
     dt = S.c["dt"]
     qn = S.q_g.clone()
     qs = S.q_g.clone()
-    out = torch.empty_like(qn)
+    out = torch.zeros_like(qn)
     for st in range(3):
         a, b, cc = timestep.stage_coefficients(st, dt)
         api.sem_stage(S.gm, a, b, cc, qn, qs, out, api.SEM_FP32)

@@ -31,13 +31,12 @@ def setup(name, **kw):
     om = oracle_mesh(c)
     perm = match(om.node_xyz, gm.node_xyz(), c)
     q_or = cases.initial_state(c, om.node_xyz)
-    q_g = torch.tensor(np.ascontiguousarray(q_or[:, perm]).reshape(-1), dtype=torch.float64,
-                       device="cuda")
+    q_g = gm.unpack(q_or[:, perm])
     return c, gm, om, perm, q_or, q_g
 
 
-def to_oracle(flat, perm):
-    a = flat.detach().cpu().numpy().reshape(5, -1)
+def to_oracle(flat, perm, gm):
+    a = gm.pack(flat)
     out = np.empty_like(a)
     out[:, perm] = a
     return out
@@ -54,7 +53,7 @@ def test_stepper_matches_oracle(name, kw):
     torch.cuda.synchronize()
     ref = oracle_reference_local(c, om)
     want, _ = timestep.run_stages(lambda q: assembly.rhs(om, q, ref, c["phys"]), q_or, c["dt"], 6)
-    err = metrics.rel_l2(to_oracle(st.q, perm), want, metrics.STATE_FLOORS)
+    err = metrics.rel_l2(to_oracle(st.q, perm, gm), want, metrics.STATE_FLOORS)
     say("  rel", err)
     assert err.max() <= 1e-12
 
@@ -84,7 +83,7 @@ def test_fused_stage_is_deterministic():
     say("determinism")
     outs = []
     for _ in range(3):
-        o = torch.empty_like(q_g)
+        o = torch.zeros_like(q_g)
         api.sem_stage(gm, 0.75, 0.25, 0.1, q_g, q_g, o, api.SEM_FP64)
         torch.cuda.synchronize()
         outs.append(o)
@@ -96,16 +95,16 @@ def test_autotune_then_parity():
     from paper_2410_21607_amd import api
     c, gm, om, perm, q_or, q_g = setup("vortex_8x8x4_n4")
     say("autotune")
-    scratch = torch.empty_like(q_g)
+    scratch = torch.zeros_like(q_g)
     lpc, ms = api.sem_stage_autotune(gm, q_g, q_g.clone(), scratch, api.SEM_FP64, reps=3)
     say("  chosen layers_per_chunk", lpc, "ms", ms)
     assert lpc in (1, 2, 4, 8) and ms > 0
     assert api.sem_stage_get_tune(gm) == lpc
-    out = torch.empty_like(q_g)
+    out = torch.zeros_like(q_g)
     a, b, cc = timestep.stage_coefficients(0, c["dt"])
     api.sem_stage(gm, a, b, cc, q_g, q_g, out, api.SEM_FP64)
     torch.cuda.synchronize()
     ref = oracle_reference_local(c, om)
     want, _ = timestep.run_stages(lambda q: assembly.rhs(om, q, ref, c["phys"]), q_or, c["dt"], 1)
-    err = metrics.rel_l2(to_oracle(out, perm), want, metrics.STATE_FLOORS)
+    err = metrics.rel_l2(to_oracle(out, perm, gm), want, metrics.STATE_FLOORS)
     assert err.max() <= 1e-12
