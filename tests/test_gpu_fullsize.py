@@ -1,0 +1,84 @@
+"""Full-size parity: the workloads at their real sizes, run in the launch
+configuration the benchmark times (autotuned chunk depth, HIP-graph replay
+of whole RK3 steps), against the FP64 oracle on every unique node."""
+
+import sys
+
+import numpy as np
+import pytest
+
+from harness import match, oracle_mesh, oracle_reference_local
+from oracle import assembly, metrics, timestep
+from synth import cases
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def run_case(name, n_stages, precision=0, graph=True):
+    import torch
+    from paper_2410_21607_amd import api
+    from paper_2410_21607_amd.solver import Stepper
+    c = cases.get(name)
+    say("fullsize", name, "stages", n_stages, "precision", precision)
+    gm = api.Mesh.from_case(c)
+    _, _, z = gm.coords()
+    bg = cases.reference_state(c, z)
+    gm.set_reference(bg["rho0"], bg["theta0"], bg["dtheta0dz"])
+    om = oracle_mesh(c)
+    perm = match(om.node_xyz, gm.node_xyz(), c)
+    q_or = cases.initial_state(c, om.node_xyz)
+    q_g = gm.unpack(q_or[:, perm])
+    scratch = torch.zeros_like(q_g)
+    lpc, ms = api.sem_stage_autotune(gm, q_g, q_g.clone(), scratch, precision, reps=3)
+    say("  autotuned layers_per_chunk", lpc, "ms/stage", ms)
+    if n_stages % 3 == 0:
+        st = Stepper(gm, q_g, c["dt"], precision, graph=graph)
+        st.step(n_stages // 3)
+        out = st.q
+    else:
+        qs, out = q_g.clone(), torch.zeros_like(q_g)
+        for s in range(n_stages):
+            a, b, cc = timestep.stage_coefficients(s % 3, c["dt"])
+            api.sem_stage(gm, a, b, cc, q_g, qs, out, precision)
+            qs, out = out, qs
+        out = qs
+    torch.cuda.synchronize()
+    ref = oracle_reference_local(c, om)
+    want, _ = timestep.run_stages(lambda q: assembly.rhs(om, q, ref, c["phys"]), q_or, c["dt"],
+                                  n_stages)
+    got = np.empty_like(want)
+    got[:, perm] = gm.pack(out)
+    err = metrics.rel_l2(got, want, metrics.STATE_FLOORS)
+    vmax_g = metrics.max_wind(om.node_xyz, got)
+    vmax_o = metrics.max_wind(om.node_xyz, want)
+    say("  rel", err, "vmax", vmax_g, vmax_o)
+    return err, abs(vmax_g - vmax_o) / vmax_o
+
+
+@pytest.mark.timeout(900)
+def test_bench_workload_fp64():
+    err, dv = run_case("vortex_64x64x16_n4", 3)
+    assert err.max() <= 1e-12 and dv <= 1e-13
+
+
+@pytest.mark.timeout(900)
+def test_bench_workload_fp32():
+    err, dv = run_case("vortex_64x64x16_n4", 3, precision=1)
+    assert err.max() <= 1e-6 and dv <= 1e-6
+
+
+@pytest.mark.timeout(900)
+def test_two_level_amr_n4():
+    err, dv = run_case("amr2_64x64x8_n4", 3)
+    assert err.max() <= 1e-12
+
+
+@pytest.mark.timeout(1200)
+def test_two_level_amr_n7():
+    err, dv = run_case("amr2_64x64x8_n7", 1, graph=False)
+    assert err.max() <= 1e-12
