@@ -20,6 +20,8 @@ Cyclones using Adaptive Mesh Refinement" (arXiv 2410.21607):
                 rule: scatter Z, gather Z^T, lumped mass (Section 3.1).
 * ``timestep``  explicit third-order Runge-Kutta stages (Section 5).
 * ``amr``       threshold refinement / coarsening flags (Section 4.1).
+* ``adapt``     one adaptation pass of the column quadtree (split, 2:1
+                balance, merge) and the transfer of the solution onto it.
 * ``mlp``       small multilayer perceptron used by the refinement forecaster.
 * ``metrics``   floor-scaled relative L2 error and maximum wind.
 
@@ -28,4 +30,4 @@ constant generator with the HIP path; the only shared module is ``synth``
 (seeded input generation), which holds none of the method's arithmetic.
 """
 
-from . import gll, mesh, euler, assembly, timestep, amr, metrics  # noqa: F401
+from . import gll, mesh, euler, assembly, timestep, amr, adapt, metrics  # noqa: F401
