@@ -213,6 +213,57 @@ int amr_flag(const sem_mesh *mesh, const double *d_q, int criterion,
              const double *h_thr, int lvl_max, int8_t *d_adapt_elem,
              int8_t *d_adapt_col, void *stream);
 
+/* One adaptation pass of the column layout (Section 4.1: a column is refined
+ * by splitting it into a 2 x 2 block of columns, four sibling columns are
+ * coarsened by merging them into their parent).  Host only, no GPU needed.
+ * Inputs: desc (only nx0, ny0, periodic_x/y and the column list are read; the
+ * list must tile the domain without overlap), h_adapt_col[n_col] in
+ * {-1, 0, +1} (for example amr_flag's d_adapt_col copied to the host) and
+ * lvl_max.  The pass:
+ *   1. splits every column flagged +1 whose level is below lvl_max;
+ *   2. restores 2:1 face+corner balance by splitting every column that
+ *      touches a column two or more levels finer, until none does (the
+ *      coarsest balanced layout containing step 1);
+ *   3. merges every family of four sibling columns all flagged -1 whose
+ *      parent would touch no column more than one level finer; every merge is
+ *      decided on the layout of step 2, so the result is order-independent.
+ * Output: *n_out = number of columns; when cap >= *n_out the columns are
+ * written to h_level/h_ix/h_iy[cap] in Morton order of the finest level
+ * present, else SEM_ERR_ARG is returned (call with cap = 0 and NULL arrays to
+ * learn the size).  Errors: SEM_ERR_ARG, SEM_ERR_MESH (invalid input layout). */
+int sem_adapt_columns(const sem_mesh_desc *desc, const int8_t *h_adapt_col, int lvl_max,
+                      int32_t cap, int32_t *h_level, int32_t *h_ix, int32_t *h_iy,
+                      int32_t *n_out);
+
+/* Solution transfer onto an adapted mesh.  The paper delegates it to its
+ * mesh library; the rule implemented here (both meshes must share order N,
+ * base grid, domain and vertical layers, and every column of `to` must be a
+ * column of `from`, a child of one, or the parent of four):
+ *   * a node of a column present in both meshes, or of a child of a split
+ *     column, takes the old field at its position: the old element
+ *     polynomial, exact for the interpolation of a split;
+ *   * a node belonging only to merged parents takes the lumped-mass weighted
+ *     average of the parents' discrete L2 projections of their four children
+ *     (the projection conserves each parent's sum of m q).
+ * The transfer is horizontal (the vertical is untouched), a sparse matrix T
+ * of n_h(to) rows over the n_h(from) horizontal nodes:
+ *   q_to[f][h][kz] = sum_r w[r] q_from[f][src[r]][kz],  kz < nzn,
+ * and zero in the row padding.
+ * sem_transfer_create builds T from two mesh handles and uploads it (the
+ * handle does not keep the meshes); sem_transfer_apply launches it on
+ * `stream` (d_q_from = q[F][n_h(from)][ldz], d_q_to = q[F][n_h(to)][ldz],
+ * not aliased; allocates nothing).  sem_transfer_plan is the host-only
+ * variant: it builds both meshes from their descriptions and returns T in CSR
+ * form, *nnz entries, h_ptr[n_h(to)+1], h_src[nnz], h_w[nnz] (any array
+ * may be NULL to learn nnz first). */
+typedef struct sem_transfer sem_transfer;
+int sem_transfer_create(const sem_mesh *from, const sem_mesh *to, sem_transfer **out);
+int sem_transfer_apply(const sem_transfer *t, const double *d_q_from, double *d_q_to,
+                       void *stream);
+int sem_transfer_destroy(sem_transfer *t);
+int sem_transfer_plan(const sem_mesh_desc *from, const sem_mesh_desc *to, int64_t *nnz,
+                      int32_t *h_ptr, int32_t *h_src, double *h_w);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char *sem_last_error(void);
 

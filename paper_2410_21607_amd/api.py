@@ -81,8 +81,12 @@ class Mesh:
 
     def __init__(self, N, nx0, ny0, columns, Lx, Ly, z_edges, periodic_x=True,
                  periodic_y=True, f=0.0, g=9.81, R_d=287.0, c_p=1004.0, p00=1.0e5):
+        self.params = dict(N=N, nx0=nx0, ny0=ny0, Lx=Lx, Ly=Ly, z_edges=z_edges,
+                           periodic_x=periodic_x, periodic_y=periodic_y, f=f, g=g, R_d=R_d,
+                           c_p=c_p, p00=p00)
         self._keep, d = _desc(N, nx0, ny0, columns, Lx, Ly, z_edges, periodic_x, periodic_y,
                               f, g, R_d, c_p, p00)
+        self._d = d
         cols = self._keep[0]
         h = ctypes.c_void_p()
         native.call("sem_mesh_create", ctypes.byref(d), ctypes.byref(h))
@@ -96,6 +100,11 @@ class Mesh:
     @classmethod
     def from_case(cls, case):
         return cls(*_case_args(case))
+
+    def with_columns(self, columns):
+        """A new mesh with the same order, domain, vertical layers and
+        physical constants over another column layout."""
+        return Mesh(columns=columns, **self.params)
 
     def __del__(self):
         h = getattr(self, "handle", None)
@@ -260,3 +269,76 @@ def sem_stage_autotune(mesh, qn, qs, qout, precision=SEM_FP64, reps=5, stream=No
                 _ptr(qs, torch.float64, n, "qs"), _ptr(qout, torch.float64, n, "qout"),
                 int(precision), int(reps), ctypes.byref(lpc), ctypes.byref(ms), _stream(stream))
     return lpc.value, ms.value
+
+
+def _desc_of(params, columns):
+    p = params
+    return _desc(p["N"], p["nx0"], p["ny0"], columns, p["Lx"], p["Ly"], p["z_edges"],
+                 p["periodic_x"], p["periodic_y"], p["f"], p["g"], p["R_d"], p["c_p"], p["p00"])
+
+
+def sem_adapt_columns(mesh_or_params, columns, adapt_col, lvl_max):
+    """One adaptation pass of a column layout (host only).  ``mesh_or_params``
+    is a Mesh or its ``params`` dict; ``adapt_col`` holds one flag per column
+    (numpy or a torch tensor).  Returns the new layout (n, 3) int32."""
+    params = mesh_or_params.params if isinstance(mesh_or_params, Mesh) else mesh_or_params
+    keep, d = _desc_of(params, columns)
+    if isinstance(adapt_col, torch.Tensor):
+        adapt_col = adapt_col.detach().cpu().numpy()
+    fl = np.ascontiguousarray(np.asarray(adapt_col, dtype=np.int8).reshape(-1))
+    if fl.size != keep[0].shape[0]:
+        raise ValueError("one flag per column")
+    n = ctypes.c_int32()
+    L = native.lib()
+    rc = L.sem_adapt_columns(ctypes.byref(d), fl.ctypes.data_as(ctypes.c_void_p), int(lvl_max), 0,
+                             None, None, None, ctypes.byref(n))
+    if rc != native.SEM_OK and n.value == 0:
+        raise native.SemError("sem_adapt_columns", rc, L.sem_last_error().decode())
+    lev, ix, iy = (np.zeros(n.value, np.int32) for _ in range(3))
+    i32 = lambda a: a.ctypes.data_as(native.c_i32p)
+    native.call("sem_adapt_columns", ctypes.byref(d), fl.ctypes.data_as(ctypes.c_void_p),
+                int(lvl_max), n.value, i32(lev), i32(ix), i32(iy), ctypes.byref(n))
+    return np.stack([lev, ix, iy], axis=1)
+
+
+def sem_transfer_plan(params, columns_from, columns_to):
+    """Host-only transfer rows (ptr, src, w) from one layout to another."""
+    ka, da = _desc_of(params, columns_from)
+    kb, db = _desc_of(params, columns_to)
+    nnz = ctypes.c_int64()
+    native.call("sem_transfer_plan", ctypes.byref(da), ctypes.byref(db), ctypes.byref(nnz),
+                None, None, None)
+    info = native.SemMeshInfo()
+    native.call("sem_mesh_plan", ctypes.byref(db), ctypes.byref(info), None, None, None, None)
+    ptr = np.zeros(info.n_h + 1, np.int32)
+    src = np.zeros(max(nnz.value, 1), np.int32)
+    w = np.zeros(max(nnz.value, 1))
+    native.call("sem_transfer_plan", ctypes.byref(da), ctypes.byref(db), ctypes.byref(nnz),
+                ptr.ctypes.data_as(native.c_i32p), src.ctypes.data_as(native.c_i32p),
+                w.ctypes.data_as(native.c_dp))
+    return ptr, src[: nnz.value], w[: nnz.value]
+
+
+class Transfer:
+    """Owns a ``sem_transfer`` handle from mesh ``src`` to mesh ``dst``."""
+
+    def __init__(self, src, dst):
+        h = ctypes.c_void_p()
+        native.call("sem_transfer_create", src.handle, dst.handle, ctypes.byref(h))
+        self.handle = h
+        self.n_from, self.n_to = src.n_state, dst.n_state
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            try:
+                native.lib().sem_transfer_destroy(h)
+            except Exception:
+                pass
+            self.handle = None
+
+
+def sem_transfer_apply(transfer, q_from, q_to, stream=None):
+    native.call("sem_transfer_apply", transfer.handle,
+                _ptr(q_from, torch.float64, transfer.n_from, "q_from"),
+                _ptr(q_to, torch.float64, transfer.n_to, "q_to"), _stream(stream))

@@ -4,11 +4,14 @@
 
 #include <cmath>
 #include <cstdio>
+#include <algorithm>
+#include <array>
 #include <cstring>
 #include <memory>
 #include <string>
 #include <vector>
 
+#include "adapt.h"
 #include "devmesh.h"
 #include "mesh_build.h"
 #include "sem.h"
@@ -57,6 +60,20 @@ struct sem_mesh {
         ws_bytes += int64_t(v.size() * sizeof(T));
         *dst = static_cast<const T*>(p);
         return SEM_OK;
+    }
+};
+
+struct sem_transfer {
+    int64_t n_from = 0, n_to = 0;   // horizontal nodes of the two meshes
+    int nzn = 0, ldz = 0;
+    int64_t nnz = 0;
+    int32_t* ptr = nullptr;
+    int32_t* src = nullptr;
+    double* w = nullptr;
+    ~sem_transfer() {
+        if (ptr) (void)hipFree(ptr);
+        if (src) (void)hipFree(src);
+        if (w) (void)hipFree(w);
     }
 };
 
@@ -352,6 +369,30 @@ __global__ void k_amr_col(DevMesh m, const int8_t* __restrict__ ae, int8_t* __re
         if (ok) out = -1;
     }
     ac[c] = out;
+}
+
+// Solution transfer between two meshes with the same vertical structure:
+// every row (new horizontal node) is a short weighted sum of old horizontal
+// nodes, applied to the whole vertical row of each field.  One wavefront per
+// row and field; kz fastest, so reads and writes are whole 128-byte lines.
+// The padding entries kz in [nzn, ldz) are written as zero.
+__global__ void __launch_bounds__(64)
+k_transfer(const int32_t* __restrict__ ptr, const int32_t* __restrict__ src,
+           const double* __restrict__ w, int64_t n_rows, int64_t n_h_from, int nzn, int ldz,
+           const double* __restrict__ qa, double* __restrict__ qb) {
+    for (int64_t t = blockIdx.x; t < n_rows * SEM_NFIELDS; t += gridDim.x) {
+        const int64_t h = t % n_rows;
+        const int f = int(t / n_rows);
+        const int r0 = ptr[h], r1 = ptr[h + 1];
+        const double* qf = qa + f * n_h_from * ldz;
+        double* out = qb + (f * n_rows + h) * ldz;
+        for (int kz = threadIdx.x; kz < ldz; kz += 64) {
+            double acc = 0.0;
+            if (kz < nzn)
+                for (int r = r0; r < r1; ++r) acc += w[r] * qf[int64_t(src[r]) * ldz + kz];
+            out[kz] = acc;
+        }
+    }
 }
 
 }  // namespace sem
@@ -683,6 +724,98 @@ int amr_flag(const sem_mesh* M, const double* q, int criterion, const double* th
     }
     hipLaunchKernelGGL(sem::k_amr_col, dim3((d.n_col + 255) / 256), dim3(256), 0, s, d, ae, ac);
     HIPCHK(hipGetLastError());
+    return SEM_OK;
+}
+
+// ------------------------------------------------------------ adaptation
+static sem::MeshInput input_of(const sem_mesh_desc* d) {
+    return sem::MeshInput{d->N, d->nx0, d->ny0, d->n_z, d->n_col, d->h_col_level, d->h_col_ix,
+                          d->h_col_iy, d->Lx, d->Ly, d->h_z_edges, d->periodic_x != 0,
+                          d->periodic_y != 0, d->f, d->g, d->R_d, d->c_p, d->p00};
+}
+
+int sem_adapt_columns(const sem_mesh_desc* desc, const int8_t* flags, int lvl_max, int32_t cap,
+                      int32_t* lev, int32_t* ix, int32_t* iy, int32_t* n_out) {
+    if (!desc || !flags || !n_out) return fail(SEM_ERR_ARG, "null argument");
+    if (cap < 0 || (cap > 0 && (!lev || !ix || !iy))) return fail(SEM_ERR_ARG, "bad output arrays");
+    std::vector<std::array<int32_t, 3>> out;
+    std::string err;
+    int rc = sem::adapt_layout(desc->nx0, desc->ny0, desc->periodic_x != 0, desc->periodic_y != 0,
+                               desc->n_col, desc->h_col_level, desc->h_col_ix, desc->h_col_iy, flags,
+                               lvl_max, out, err);
+    if (rc != SEM_OK) return fail(rc, err);
+    *n_out = int32_t(out.size());
+    if (int64_t(out.size()) > cap)
+        return fail(SEM_ERR_ARG, "output capacity " + std::to_string(cap) + " < " +
+                                     std::to_string(out.size()) + " columns");
+    for (size_t i = 0; i < out.size(); ++i) {
+        lev[i] = out[i][0];
+        ix[i] = out[i][1];
+        iy[i] = out[i][2];
+    }
+    return SEM_OK;
+}
+
+int sem_transfer_plan(const sem_mesh_desc* from, const sem_mesh_desc* to, int64_t* nnz,
+                      int32_t* ptr, int32_t* src, double* w) {
+    if (!from || !to || !nnz) return fail(SEM_ERR_ARG, "null argument");
+    sem::HostMesh A, B;
+    std::string err;
+    int rc = sem::build_host_mesh(input_of(from), A, err);
+    if (rc == SEM_OK) rc = sem::build_host_mesh(input_of(to), B, err);
+    if (rc != SEM_OK) return fail(rc, err);
+    sem::TransferRows T;
+    if ((rc = sem::build_transfer(A, B, T, err)) != SEM_OK) return fail(rc, err);
+    *nnz = int64_t(T.src.size());
+    if (ptr) std::memcpy(ptr, T.ptr.data(), T.ptr.size() * sizeof(int32_t));
+    if (src) std::memcpy(src, T.src.data(), T.src.size() * sizeof(int32_t));
+    if (w) std::memcpy(w, T.w.data(), T.w.size() * sizeof(double));
+    return SEM_OK;
+}
+
+int sem_transfer_create(const sem_mesh* from, const sem_mesh* to, sem_transfer** out) {
+    if (!from || !to || !out) return fail(SEM_ERR_ARG, "null argument");
+    *out = nullptr;
+    sem::TransferRows T;
+    std::string err;
+    int rc = sem::build_transfer(from->host, to->host, T, err);
+    if (rc != SEM_OK) return fail(rc, err);
+    std::unique_ptr<sem_transfer> X(new sem_transfer());
+    X->n_from = from->host.n_h;
+    X->n_to = to->host.n_h;
+    X->nzn = to->host.nzn;
+    X->ldz = to->host.ldz;
+    X->nnz = int64_t(T.src.size());
+    for (int32_t s : T.src)
+        if (s < 0 || s >= X->n_from) return fail(SEM_ERR_MESH, "transfer row source out of range");
+    HIPCHK(hipMalloc(&X->ptr, T.ptr.size() * sizeof(int32_t)));
+    HIPCHK(hipMemcpy(X->ptr, T.ptr.data(), T.ptr.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    if (X->nnz > 0) {
+        HIPCHK(hipMalloc(&X->src, T.src.size() * sizeof(int32_t)));
+        HIPCHK(hipMalloc(&X->w, T.w.size() * sizeof(double)));
+        HIPCHK(hipMemcpy(X->src, T.src.data(), T.src.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(X->w, T.w.data(), T.w.size() * sizeof(double), hipMemcpyHostToDevice));
+    }
+    *out = X.release();
+    return SEM_OK;
+}
+
+int sem_transfer_apply(const sem_transfer* X, const double* q_from, double* q_to, void* stream) {
+    if (!X) return fail(SEM_ERR_ARG, "null transfer");
+    if (!q_from || !q_to) return fail(SEM_ERR_ARG, "null array");
+    if (q_from == q_to) return fail(SEM_ERR_ARG, "q_to must not alias q_from");
+    if (X->n_to == 0) return SEM_OK;
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t work = X->n_to * SEM_NFIELDS;
+    const int grid = int(std::min<int64_t>(work, 1 << 20));
+    hipLaunchKernelGGL(sem::k_transfer, dim3(grid), dim3(64), 0, s, X->ptr, X->src, X->w, X->n_to,
+                       X->n_from, X->nzn, X->ldz, q_from, q_to);
+    HIPCHK(hipGetLastError());
+    return SEM_OK;
+}
+
+int sem_transfer_destroy(sem_transfer* X) {
+    delete X;
     return SEM_OK;
 }
 

@@ -62,6 +62,13 @@ SIGNATURES = {
     "sem_stage_autotune": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_int,
                                    ctypes.POINTER(c_int), ctypes.POINTER(ctypes.c_float), c_void_p]),
     "amr_flag": (c_int, [c_void_p, c_void_p, c_int, c_dp, c_int, c_void_p, c_void_p, c_void_p]),
+    "sem_adapt_columns": (c_int, [ctypes.POINTER(SemMeshDesc), c_void_p, c_int, ctypes.c_int32,
+                                  c_i32p, c_i32p, c_i32p, ctypes.POINTER(ctypes.c_int32)]),
+    "sem_transfer_create": (c_int, [c_void_p, c_void_p, ctypes.POINTER(c_void_p)]),
+    "sem_transfer_apply": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
+    "sem_transfer_destroy": (c_int, [c_void_p]),
+    "sem_transfer_plan": (c_int, [ctypes.POINTER(SemMeshDesc), ctypes.POINTER(SemMeshDesc),
+                                  ctypes.POINTER(ctypes.c_int64), c_i32p, c_i32p, c_dp]),
     "sem_last_error": (ctypes.c_char_p, []),
 }
 
