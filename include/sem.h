@@ -81,6 +81,13 @@ extern "C" {
 #define SEM_ASSEMBLE 0    /* sem_dss phases */
 #define SEM_FINALIZE 1
 
+#define SEM_NFEAT 16      /* forecaster features per element                */
+#define SEM_MLP_IN 16     /* forecaster network: 16 -> 64 -> 64 -> 3         */
+#define SEM_MLP_HIDDEN 64
+#define SEM_MLP_OUT 3
+#define SEM_MLP_NPARAM 5443 /* 64*16 + 64 + 64*64 + 64 + 3*64 + 3          */
+#define SEM_MLP_WORK 260  /* mlp_backward workspace floats per sample        */
+
 #define SEM_CRIT_SPEED 0  /* amr_flag criteria: |u| at every node           */
 #define SEM_CRIT_VORTZ 1  /* vertical vorticity dv/dx - du/dy (element-local)*/
 
@@ -263,6 +270,73 @@ int sem_transfer_apply(const sem_transfer *t, const double *d_q_from, double *d_
 int sem_transfer_destroy(sem_transfer *t);
 int sem_transfer_plan(const sem_mesh_desc *from, const sem_mesh_desc *to, int64_t *nnz,
                       int32_t *h_ptr, int32_t *h_src, double *h_w);
+
+/* ---------------------------------------------------------------------------
+ * Refinement forecaster.  The paper's criterion (Section 4.1) thresholds a
+ * field at the element's nodes at the moment of adaptation; its conclusions
+ * call for better criteria.  The forecaster predicts the decision several
+ * adaptation intervals ahead with a small network on per-element features,
+ * so that the mesh can be rebuilt less often; its flags are combined with
+ * the criterion's, which overrides every refinement the forecaster misses.
+ * ------------------------------------------------------------------------- */
+
+/* Per-element features, d_feat[n_elem][SEM_NFEAT] (float), each raw value
+ * multiplied by h_scale[i] (host, SEM_NFEAT floats).  Raw features, from
+ * element-local values and derivatives (LGL derivative matrix, as in the
+ * criterion), zeta = dv/dx - du/dy, u_h = (u, v):
+ *   0 level, 1 max|zeta|, 2 mean zeta over the element's nodes, 3 max|u_h|,
+ *   4 max|w|, 5 max theta', 6 min theta', 7 max|grad p'|, 8 max|grad theta'|,
+ *   9 max|div u|, 10 max rho' - min rho', 11 largest feature-1 value and
+ *   12 largest feature-3 value over the elements of the same layer in the
+ *   horizontal neighbour columns (columns sharing a unique node), 13 feature 3
+ *   minus its value for d_q_prev, 14 feature 1 minus its value for d_q_prev,
+ *   15 the criterion's element flag d_plain_elem[e] (from amr_flag).
+ * d_dem[n_elem] (int8) = the level the criterion asks for: the largest l in
+ * 1..lvl_max with C_max > threshold(l) (0 if none), C as in amr_flag.
+ * d_q, d_q_prev: states on this mesh (q[F][n_h][ldz]).  Uses the handle's
+ * feature scratch, so calls on one handle must not overlap. */
+int amr_features(const sem_mesh *mesh, const double *d_q, const double *d_q_prev,
+                 const int8_t *d_plain_elem, int criterion, const double *h_thr, int lvl_max,
+                 const float *h_scale, float *d_feat, int8_t *d_dem, void *stream);
+
+/* Forecast flags combined with the criterion's.  d_logits[n_elem][3] from
+ * mlp_forward; class = argmax (first maximum on ties) in {0 coarsen, 1 keep,
+ * 2 refine}, clamped so that level 0 never coarsens and lvl_max never
+ * refines.  Element flag: +1 if the forecast or d_plain_elem is +1, -1 if
+ * both are -1, else 0 -> d_adapt_elem[n_elem]; column flags d_adapt_col[n_col]
+ * by the column rule of amr_flag. */
+int amr_forecast_flags(const sem_mesh *mesh, const float *d_logits, const int8_t *d_plain_elem,
+                       int lvl_max, int8_t *d_adapt_elem, int8_t *d_adapt_col, void *stream);
+
+/* Training labels (host only): for every element (column c, layer) of the
+ * layout `at`, the class clip(D - level, -1, 1) + 1 in {0, 1, 2}, where D is
+ * the criterion's level (d_dem of amr_features) of the element of the same
+ * layer in the layout `later` that contains the column, or the largest over
+ * the later columns inside it.  h_dem_later[n_elem(later)], h_class[n_elem(at)]. */
+int sem_forecast_labels(const sem_mesh_desc *at, const sem_mesh_desc *later,
+                        const int8_t *h_dem_later, int8_t *h_class);
+
+/* Network 16 -> 64 -> 64 -> 3, tanh hidden activations, FP32.  d_params is
+ * one array of SEM_MLP_NPARAM floats: W1[64][16], b1[64], W2[64][64], b2[64],
+ * W3[3][64], b3[3] (z = W x + b per layer).
+ * mlp_forward : d_logits[n][3] for inputs d_x[n][16].
+ * mlp_backward: the gradient of the mean softmax cross-entropy over a batch of
+ *   n samples, d_grad[SEM_MLP_NPARAM], and the loss itself, *d_loss (device).
+ *   d_x[n_rows][16] and d_class[n_rows] (class in {0,1,2}) hold the data;
+ *   sample b is row d_idx[b], or row b when d_idx is NULL (then n <= n_rows).
+ *   Indices outside [0, n_rows) and classes outside {0,1,2} are clamped into
+ *   range (memory safety; the binding checks them).  d_work: n*SEM_MLP_WORK
+ *   floats of caller-owned scratch.  Sums over the batch run in a fixed order
+ *   (deterministic).
+ * mlp_adam_step: Adam with bias correction, step t >= 1:
+ *   m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,
+ *   p -= lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps). */
+int mlp_forward(const float *d_params, const float *d_x, int64_t n, float *d_logits, void *stream);
+int mlp_backward(const float *d_params, const float *d_x, int64_t n_rows, const int8_t *d_class,
+                 const int32_t *d_idx, int64_t n, float *d_work, float *d_grad, float *d_loss,
+                 void *stream);
+int mlp_adam_step(float *d_params, const float *d_grad, float *d_m, float *d_v, int t, float lr,
+                  float beta1, float beta2, float eps, void *stream);
 
 /* Message of the last failed call on this thread ("" if none). */
 const char *sem_last_error(void);

@@ -342,3 +342,78 @@ def sem_transfer_apply(transfer, q_from, q_to, stream=None):
     native.call("sem_transfer_apply", transfer.handle,
                 _ptr(q_from, torch.float64, transfer.n_from, "q_from"),
                 _ptr(q_to, torch.float64, transfer.n_to, "q_to"), _stream(stream))
+
+
+# ---------------------------------------------------------------- forecaster
+NFEAT = native.SEM_NFEAT
+MLP_NPARAM = native.SEM_MLP_NPARAM
+MLP_WORK = native.SEM_MLP_WORK
+
+
+def amr_features(mesh, q, q_prev, plain_elem, criterion, thresholds, lvl_max, scale, feat, dem,
+                 stream=None):
+    thr = np.ascontiguousarray(np.asarray(thresholds, dtype=np.float64))
+    if thr.size < lvl_max:
+        raise ValueError("need one threshold per level")
+    sc = np.ascontiguousarray(np.asarray(scale, dtype=np.float32))
+    if sc.size != NFEAT:
+        raise ValueError("one scale per feature")
+    ne = mesh.info["n_elem"]
+    native.call("amr_features", mesh.handle, _ptr(q, torch.float64, mesh.n_state, "q"),
+                _ptr(q_prev, torch.float64, mesh.n_state, "q_prev"),
+                _ptr(plain_elem, torch.int8, ne, "plain_elem"), int(criterion),
+                thr.ctypes.data_as(native.c_dp) if thr.size else None, int(lvl_max),
+                sc.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                _ptr(feat, torch.float32, ne * NFEAT, "feat"), _ptr(dem, torch.int8, ne, "dem"),
+                _stream(stream))
+
+
+def amr_forecast_flags(mesh, logits, plain_elem, lvl_max, adapt_elem, adapt_col, stream=None):
+    ne = mesh.info["n_elem"]
+    native.call("amr_forecast_flags", mesh.handle, _ptr(logits, torch.float32, 3 * ne, "logits"),
+                _ptr(plain_elem, torch.int8, ne, "plain_elem"), int(lvl_max),
+                _ptr(adapt_elem, torch.int8, ne, "adapt_elem"),
+                _ptr(adapt_col, torch.int8, mesh.info["n_col"], "adapt_col"), _stream(stream))
+
+
+def sem_forecast_labels(params, columns_at, columns_later, dem_later):
+    """Host-only training classes (n_elem(at),) int8 in {0, 1, 2}."""
+    ka, da = _desc_of(params, columns_at)
+    kb, db = _desc_of(params, columns_later)
+    nz = len(params["z_edges"]) - 1
+    dem = np.ascontiguousarray(np.asarray(dem_later, dtype=np.int8).reshape(-1))
+    if dem.size != kb[0].shape[0] * nz:
+        raise ValueError("one dem value per element of the later layout")
+    out = np.zeros(ka[0].shape[0] * nz, dtype=np.int8)
+    native.call("sem_forecast_labels", ctypes.byref(da), ctypes.byref(db),
+                dem.ctypes.data_as(ctypes.c_void_p), out.ctypes.data_as(ctypes.c_void_p))
+    return out
+
+
+def mlp_forward(params, x, logits, stream=None):
+    n = x.shape[0]
+    native.call("mlp_forward", _ptr(params, torch.float32, MLP_NPARAM, "params"),
+                _ptr(x, torch.float32, n * 16, "x"), int(n),
+                _ptr(logits, torch.float32, n * 3, "logits"), _stream(stream))
+
+
+def mlp_backward(params, x, cls, idx, work, grad, loss, stream=None):
+    """Gradient of the mean cross-entropy over the rows idx (or all rows)."""
+    rows = x.shape[0]
+    n = rows if idx is None else idx.numel()
+    if work.numel() < n * MLP_WORK:
+        raise ValueError("workspace too small")
+    native.call("mlp_backward", _ptr(params, torch.float32, MLP_NPARAM, "params"),
+                _ptr(x, torch.float32, rows * 16, "x"), int(rows),
+                _ptr(cls, torch.int8, rows, "cls"),
+                None if idx is None else _ptr(idx, torch.int32, n, "idx"), int(n),
+                _ptr(work, torch.float32, work.numel(), "work"),
+                _ptr(grad, torch.float32, MLP_NPARAM, "grad"), _ptr(loss, torch.float32, 1, "loss"),
+                _stream(stream))
+
+
+def mlp_adam_step(params, grad, m, v, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    native.call("mlp_adam_step", _ptr(params, torch.float32, MLP_NPARAM, "params"),
+                _ptr(grad, torch.float32, MLP_NPARAM, "grad"), _ptr(m, torch.float32, MLP_NPARAM, "m"),
+                _ptr(v, torch.float32, MLP_NPARAM, "v"), int(t), float(lr), float(beta1),
+                float(beta2), float(eps), _stream(stream))

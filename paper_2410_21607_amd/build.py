@@ -10,7 +10,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libsem.so")
 
-SOURCES = ["sem.hip", "stage_fused.hip", "mesh_build.cpp", "adapt.cpp"]
+SOURCES = ["sem.hip", "stage_fused.hip", "forecast.hip", "mlp.hip", "mesh_build.cpp", "adapt.cpp"]
 
 # Packed FP32 instructions are disabled for every HIP translation unit.
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -21,6 +21,7 @@ struct DevMesh {
     const int32_t *asm_ptr, *asm_slot, *asmH_ptr, *asmH_slot;
     const double *minv_h, *minv_v;
     const int32_t *sib, *col_level;
+    const int32_t *nbr_ptr, *nbr_col;   // horizontal neighbour columns (CSR)
     const double *D, *w;      // LGL derivative matrix and weights
     const double *rho0, *theta0, *dth0, *p0;   // reference state per kz
     const double *inv_rho0, *inv_theta0;       // their reciprocals per kz

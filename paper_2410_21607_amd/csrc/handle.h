@@ -1,0 +1,73 @@
+// Internal definitions shared by the HIP translation units of the library:
+// the mesh handle, the error channel behind sem_last_error, and HIPCHK.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "devmesh.h"
+#include "mesh_build.h"
+#include "sem.h"
+#include "stage_fused.h"
+
+namespace sem {
+
+// thread-local message of the last failed call on this thread
+std::string& last_error();
+
+inline int fail(int code, const std::string& msg) {
+    last_error() = msg;
+    return code;
+}
+
+}  // namespace sem
+
+#define HIPCHK(x)                                                                        \
+    do {                                                                                 \
+        hipError_t e_ = (x);                                                             \
+        if (e_ != hipSuccess)                                                            \
+            return sem::fail(SEM_ERR_HIP, std::string(#x) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+struct sem_mesh {
+    sem::HostMesh host;
+    sem::DevMesh d{};
+    std::vector<void*> allocs;
+    bool have_ref = false;
+    sem::FusedPlan fused;
+    double* feat_aux = nullptr;   // 2 doubles per element (amr_features)
+    int64_t ws_bytes = 0;
+    ~sem_mesh() {
+        sem::fused_plan_free(fused);
+        if (feat_aux) (void)hipFree(feat_aux);
+        for (void* p : allocs) (void)hipFree(p);
+    }
+    template <typename T>
+    int upload(const std::vector<T>& v, const T** dst) {
+        if (v.empty()) { *dst = nullptr; return SEM_OK; }
+        void* p = nullptr;
+        HIPCHK(hipMalloc(&p, v.size() * sizeof(T)));
+        allocs.push_back(p);
+        HIPCHK(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+        ws_bytes += int64_t(v.size() * sizeof(T));
+        *dst = static_cast<const T*>(p);
+        return SEM_OK;
+    }
+};
+
+struct sem_transfer {
+    int64_t n_from = 0, n_to = 0;   // horizontal nodes of the two meshes
+    int nzn = 0, ldz = 0;
+    int64_t nnz = 0;
+    int32_t* ptr = nullptr;
+    int32_t* src = nullptr;
+    double* w = nullptr;
+    ~sem_transfer() {
+        if (ptr) (void)hipFree(ptr);
+        if (src) (void)hipFree(src);
+        if (w) (void)hipFree(w);
+    }
+};
+

@@ -472,6 +472,34 @@ int build_host_mesh(const MeshInput& in, HostMesh& m, std::string& err) {
         }
         if (ok) for (int q = 0; q < 4; ++q) m.sib[size_t(c) * 4 + q] = ids[q];
     }
+    // horizontal neighbours through shared unique horizontal nodes
+    {
+        const int np2 = m.np1 * m.np1;
+        std::vector<int32_t> hp(size_t(m.n_h) + 1, 0), hc;
+        for (size_t s = 0; s < m.gmap.size(); ++s)
+            if (m.gmap[s] >= 0) ++hp[size_t(m.gmap[s]) + 1];
+        for (int64_t h = 0; h < m.n_h; ++h) hp[h + 1] += hp[h];
+        hc.assign(hp.back(), 0);
+        std::vector<int32_t> fill(hp.begin(), hp.end() - 1);
+        for (size_t s = 0; s < m.gmap.size(); ++s)
+            if (m.gmap[s] >= 0) hc[fill[m.gmap[s]]++] = int32_t(s / np2);
+        m.nbr_ptr.assign(size_t(in.n_col) + 1, 0);
+        m.nbr_col.clear();
+        std::vector<int32_t> list;
+        for (int c = 0; c < in.n_col; ++c) {
+            list.clear();
+            for (int pos = 0; pos < np2; ++pos) {
+                const int32_t g = m.gmap[size_t(c) * np2 + pos];
+                if (g < 0) continue;
+                for (int r = hp[g]; r < hp[g + 1]; ++r)
+                    if (hc[r] != c) list.push_back(hc[r]);
+            }
+            std::sort(list.begin(), list.end());
+            list.erase(std::unique(list.begin(), list.end()), list.end());
+            m.nbr_col.insert(m.nbr_col.end(), list.begin(), list.end());
+            m.nbr_ptr[size_t(c) + 1] = int32_t(m.nbr_col.size());
+        }
+    }
     return SEM_OK;
 }
 

@@ -57,6 +57,9 @@ struct HostMesh {
     std::vector<double> minv_h, minv_v;
     // sibling families (4 ids) per column, -1 when not a complete family
     std::vector<int32_t> sib;
+    // horizontal neighbours: columns sharing at least one unique horizontal
+    // node (across faces or corners), CSR over columns, ascending ids
+    std::vector<int32_t> nbr_ptr, nbr_col;
 };
 
 struct MeshInput {

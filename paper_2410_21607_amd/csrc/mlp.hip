@@ -1,0 +1,237 @@
+// Multilayer perceptron of the refinement forecaster (gfx950, FP32):
+// 16 -> 64 -> 64 -> 3 with tanh, softmax cross-entropy, Adam.
+//
+// Parameters are one flat float array: W1[64][16], b1[64], W2[64][64], b2[64],
+// W3[3][64], b3[3] (5443 floats, staged in LDS by every workgroup).
+//
+// Training step = three launches:
+//   k_mlp_samples : one thread per sample: forward pass, softmax, the
+//                   per-sample back-propagated errors of the three layers and
+//                   the sample's loss, written to the workspace;
+//   k_mlp_grad    : one thread per parameter: the batch sum of its gradient
+//                   in a fixed order (deterministic, accumulated in double);
+//   k_adam        : element-wise Adam update.
+#include <cmath>
+
+#include "handle.h"
+
+namespace sem {
+
+namespace {
+
+constexpr int NI = SEM_MLP_IN, NH = SEM_MLP_HIDDEN, NO = SEM_MLP_OUT;
+constexpr int OW1 = 0, OB1 = OW1 + NH * NI, OW2 = OB1 + NH, OB2 = OW2 + NH * NH, OW3 = OB2 + NH,
+              OB3 = OW3 + NO * NH, NP = OB3 + NO;
+static_assert(NP == SEM_MLP_NPARAM, "parameter count");
+// workspace per sample: h1, h2, d1, d2 (64 each), d3 (3), loss (1)
+constexpr int WH1 = 0, WH2 = WH1 + NH, WD1 = WH2 + NH, WD2 = WD1 + NH, WD3 = WD2 + NH,
+              WL = WD3 + NO, WN = WL + 1;
+static_assert(WN == SEM_MLP_WORK, "workspace per sample");
+
+__device__ __forceinline__ void stage_params(const float* __restrict__ p, float* sp) {
+    for (int r = threadIdx.x; r < NP; r += blockDim.x) sp[r] = p[r];
+    __syncthreads();
+}
+
+// hidden layers and logits of one sample
+__device__ __forceinline__ void forward_one(const float* sp, const float* __restrict__ xin,
+                                            float* h1, float* h2, float* z3) {
+    float x[NI];
+#pragma unroll
+    for (int i = 0; i < NI; ++i) x[i] = xin[i];
+#pragma unroll
+    for (int o = 0; o < NH; ++o) {
+        float s = sp[OB1 + o];
+#pragma unroll
+        for (int i = 0; i < NI; ++i) s = fmaf(sp[OW1 + o * NI + i], x[i], s);
+        h1[o] = tanhf(s);
+    }
+#pragma unroll
+    for (int o = 0; o < NH; ++o) {
+        float s = sp[OB2 + o];
+#pragma unroll
+        for (int h = 0; h < NH; ++h) s = fmaf(sp[OW2 + o * NH + h], h1[h], s);
+        h2[o] = tanhf(s);
+    }
+#pragma unroll
+    for (int o = 0; o < NO; ++o) {
+        float s = sp[OB3 + o];
+#pragma unroll
+        for (int h = 0; h < NH; ++h) s = fmaf(sp[OW3 + o * NH + h], h2[h], s);
+        z3[o] = s;
+    }
+}
+
+}  // namespace
+
+__global__ void __launch_bounds__(256)
+k_mlp_forward(const float* __restrict__ p, const float* __restrict__ x, int64_t n,
+              float* __restrict__ logits) {
+    __shared__ float sp[NP];
+    stage_params(p, sp);
+    for (int64_t b = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; b < n;
+         b += int64_t(gridDim.x) * blockDim.x) {
+        float h1[NH], h2[NH], z3[NO];
+        forward_one(sp, x + b * NI, h1, h2, z3);
+#pragma unroll
+        for (int o = 0; o < NO; ++o) logits[b * NO + o] = z3[o];
+    }
+}
+
+__global__ void __launch_bounds__(256)
+k_mlp_samples(const float* __restrict__ p, const float* __restrict__ x,
+              const int8_t* __restrict__ cls, const int32_t* __restrict__ idx, int64_t n,
+              int64_t n_rows, float* __restrict__ work) {
+    __shared__ float sp[NP];
+    stage_params(p, sp);
+    const float inv_n = 1.0f / float(n);
+    for (int64_t b = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; b < n;
+         b += int64_t(gridDim.x) * blockDim.x) {
+        const int64_t s = idx ? min(max(int64_t(idx[b]), int64_t(0)), n_rows - 1) : b;
+        float h1[NH], h2[NH], z3[NO];
+        forward_one(sp, x + s * NI, h1, h2, z3);
+        const int lab = min(max(int(cls[s]), 0), NO - 1);
+        // softmax and cross-entropy
+        float zm = fmaxf(z3[0], fmaxf(z3[1], z3[2]));
+        float ex[NO], se = 0.0f;
+#pragma unroll
+        for (int o = 0; o < NO; ++o) { ex[o] = expf(z3[o] - zm); se += ex[o]; }
+        float* wb = work + b * WN;
+        float d3[NO];
+#pragma unroll
+        for (int o = 0; o < NO; ++o) {
+            d3[o] = (ex[o] / se - (o == lab ? 1.0f : 0.0f)) * inv_n;
+            wb[WD3 + o] = d3[o];
+        }
+        wb[WL] = -(z3[lab] - zm - logf(se));
+        // layer 2 error: (W3^T d3) * (1 - h2^2)
+        float d2[NH];
+#pragma unroll
+        for (int h = 0; h < NH; ++h) {
+            float s2 = 0.0f;
+#pragma unroll
+            for (int o = 0; o < NO; ++o) s2 = fmaf(sp[OW3 + o * NH + h], d3[o], s2);
+            d2[h] = s2 * (1.0f - h2[h] * h2[h]);
+            wb[WH2 + h] = h2[h];
+            wb[WD2 + h] = d2[h];
+        }
+        // layer 1 error: (W2^T d2) * (1 - h1^2)
+#pragma unroll
+        for (int h = 0; h < NH; ++h) {
+            float s1 = 0.0f;
+#pragma unroll
+            for (int o = 0; o < NH; ++o) s1 = fmaf(sp[OW2 + o * NH + h], d2[o], s1);
+            wb[WH1 + h] = h1[h];
+            wb[WD1 + h] = s1 * (1.0f - h1[h] * h1[h]);
+        }
+    }
+}
+
+// gradient of every parameter (and, in the extra thread, the mean loss) as
+// a batch sum in sample order
+__global__ void __launch_bounds__(256)
+k_mlp_grad(const float* __restrict__ x, const int32_t* __restrict__ idx, int64_t n,
+           int64_t n_rows, const float* __restrict__ work, float* __restrict__ grad,
+           float* __restrict__ loss) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r > NP) return;
+    double s = 0.0;
+    if (r == NP) {
+        for (int64_t b = 0; b < n; ++b) s += work[b * WN + WL];
+        *loss = float(s / double(n));
+        return;
+    }
+    if (r < OB1) {                       // W1[o][i] = sum d1[o] x[i]
+        const int o = r / NI, i = r % NI;
+        for (int64_t b = 0; b < n; ++b) {
+            const int64_t sm = idx ? min(max(int64_t(idx[b]), int64_t(0)), n_rows - 1) : b;
+            s += double(work[b * WN + WD1 + o]) * double(x[sm * NI + i]);
+        }
+    } else if (r < OW2) {                // b1[o] = sum d1[o]
+        const int o = r - OB1;
+        for (int64_t b = 0; b < n; ++b) s += work[b * WN + WD1 + o];
+    } else if (r < OB2) {                // W2[o][h] = sum d2[o] h1[h]
+        const int o = (r - OW2) / NH, h = (r - OW2) % NH;
+        for (int64_t b = 0; b < n; ++b)
+            s += double(work[b * WN + WD2 + o]) * double(work[b * WN + WH1 + h]);
+    } else if (r < OW3) {                // b2[o] = sum d2[o]
+        const int o = r - OB2;
+        for (int64_t b = 0; b < n; ++b) s += work[b * WN + WD2 + o];
+    } else if (r < OB3) {                // W3[o][h] = sum d3[o] h2[h]
+        const int o = (r - OW3) / NH, h = (r - OW3) % NH;
+        for (int64_t b = 0; b < n; ++b)
+            s += double(work[b * WN + WD3 + o]) * double(work[b * WN + WH2 + h]);
+    } else {                             // b3[o] = sum d3[o]
+        const int o = r - OB3;
+        for (int64_t b = 0; b < n; ++b) s += work[b * WN + WD3 + o];
+    }
+    grad[r] = float(s);
+}
+
+__global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
+                       float* __restrict__ v, float lr, float b1, float b2, float eps, float c1,
+                       float c2) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= NP) return;
+    const float gr = g[r];
+    const float mr = b1 * m[r] + (1.0f - b1) * gr;
+    const float vr = b2 * v[r] + (1.0f - b2) * gr * gr;
+    m[r] = mr;
+    v[r] = vr;
+    p[r] -= lr * (mr / c1) / (sqrtf(vr / c2) + eps);
+}
+
+}  // namespace sem
+
+namespace {
+using sem::fail;
+int grid_of(int64_t n) {
+    int64_t g = (n + 255) / 256;
+    if (g < 1) g = 1;
+    if (g > 65536) g = 65536;
+    return int(g);
+}
+}  // namespace
+
+extern "C" {
+
+int mlp_forward(const float* p, const float* x, int64_t n, float* logits, void* stream) {
+    if (!p || !logits || (n > 0 && !x)) return fail(SEM_ERR_ARG, "null array");
+    if (n < 0) return fail(SEM_ERR_ARG, "negative sample count");
+    if (n == 0) return SEM_OK;
+    hipLaunchKernelGGL(sem::k_mlp_forward, dim3(grid_of(n)), dim3(256), 0, (hipStream_t)stream,
+                       p, x, n, logits);
+    HIPCHK(hipGetLastError());
+    return SEM_OK;
+}
+
+int mlp_backward(const float* p, const float* x, int64_t n_rows, const int8_t* cls,
+                 const int32_t* idx, int64_t n, float* work, float* grad, float* loss, void* stream) {
+    if (!p || !x || !cls || !work || !grad || !loss) return fail(SEM_ERR_ARG, "null array");
+    if (n < 1) return fail(SEM_ERR_ARG, "empty batch");
+    if (n_rows < 1 || (!idx && n > n_rows)) return fail(SEM_ERR_ARG, "batch larger than the data");
+    hipStream_t s = (hipStream_t)stream;
+    hipLaunchKernelGGL(sem::k_mlp_samples, dim3(grid_of(n)), dim3(256), 0, s, p, x, cls, idx, n,
+                       n_rows, work);
+    HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL(sem::k_mlp_grad, dim3((SEM_MLP_NPARAM + 1 + 255) / 256), dim3(256), 0, s, x,
+                       idx, n, n_rows, work, grad, loss);
+    HIPCHK(hipGetLastError());
+    return SEM_OK;
+}
+
+int mlp_adam_step(float* p, const float* g, float* m, float* v, int t, float lr, float beta1,
+                  float beta2, float eps, void* stream) {
+    if (!p || !g || !m || !v) return fail(SEM_ERR_ARG, "null array");
+    if (t < 1) return fail(SEM_ERR_ARG, "Adam step count starts at 1");
+    if (!(beta1 >= 0.0f && beta1 < 1.0f && beta2 >= 0.0f && beta2 < 1.0f && eps > 0.0f))
+        return fail(SEM_ERR_ARG, "bad Adam hyper-parameters");
+    const float c1 = float(1.0 - std::pow(double(beta1), t));
+    const float c2 = float(1.0 - std::pow(double(beta2), t));
+    hipLaunchKernelGGL(sem::k_adam, dim3((SEM_MLP_NPARAM + 255) / 256), dim3(256), 0,
+                       (hipStream_t)stream, p, g, m, v, lr, beta1, beta2, eps, c1, c2);
+    HIPCHK(hipGetLastError());
+    return SEM_OK;
+}
+
+}  // extern "C"

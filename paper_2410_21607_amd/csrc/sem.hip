@@ -12,86 +12,27 @@
 #include <vector>
 
 #include "adapt.h"
-#include "devmesh.h"
-#include "mesh_build.h"
-#include "sem.h"
-#include "stage_fused.h"
+#include "handle.h"
+#include "nodeval.h"
+
+namespace sem {
+std::string& last_error() {
+    thread_local std::string msg;
+    return msg;
+}
+}  // namespace sem
 
 namespace {
 
-thread_local std::string g_err;
-
-int fail(int code, const std::string& msg) {
-    g_err = msg;
-    return code;
-}
-
-#define HIPCHK(x)                                                                   \
-    do {                                                                            \
-        hipError_t e_ = (x);                                                        \
-        if (e_ != hipSuccess)                                                       \
-            return fail(SEM_ERR_HIP, std::string(#x) + ": " + hipGetErrorString(e_)); \
-    } while (0)
-
+using sem::fail;
 constexpr int NF = SEM_NFIELDS;
 
 }  // namespace
 
 using sem::DevMesh;
 
-struct sem_mesh {
-    sem::HostMesh host;
-    DevMesh d{};
-    std::vector<void*> allocs;
-    bool have_ref = false;
-    sem::FusedPlan fused;
-    int64_t ws_bytes = 0;
-    ~sem_mesh() {
-        sem::fused_plan_free(fused);
-        for (void* p : allocs) (void)hipFree(p);
-    }
-    template <typename T>
-    int upload(const std::vector<T>& v, const T** dst) {
-        if (v.empty()) { *dst = nullptr; return SEM_OK; }
-        void* p = nullptr;
-        HIPCHK(hipMalloc(&p, v.size() * sizeof(T)));
-        allocs.push_back(p);
-        HIPCHK(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
-        ws_bytes += int64_t(v.size() * sizeof(T));
-        *dst = static_cast<const T*>(p);
-        return SEM_OK;
-    }
-};
-
-struct sem_transfer {
-    int64_t n_from = 0, n_to = 0;   // horizontal nodes of the two meshes
-    int nzn = 0, ldz = 0;
-    int64_t nnz = 0;
-    int32_t* ptr = nullptr;
-    int32_t* src = nullptr;
-    double* w = nullptr;
-    ~sem_transfer() {
-        if (ptr) (void)hipFree(ptr);
-        if (src) (void)hipFree(src);
-        if (w) (void)hipFree(w);
-    }
-};
-
 // ====================================================================== kernels
 namespace sem {
-
-// value of field f at horizontal slot g (unique node or hanging point) and kz,
-// interpolating hanging points through their rows
-__device__ __forceinline__ double node_value(const DevMesh& m, const double* __restrict__ q,
-                                             int g, int f, int kz) {
-    const int64_t fs = int64_t(m.n_h) * m.ldz;
-    if (g >= 0) return q[f * fs + int64_t(g) * m.ldz + kz];
-    const int hh = -g - 1;
-    double s = 0.0;
-    for (int t = m.hang_ptr[hh]; t < m.hang_ptr[hh + 1]; ++t)
-        s += m.hang_w[t] * q[f * fs + int64_t(m.hang_src[t]) * m.ldz + kz];
-    return s;
-}
 
 __global__ void k_nc_scatter(DevMesh m, const double* __restrict__ src, double* __restrict__ dst) {
     const int64_t n = int64_t(m.n_hh) * m.nzn;
@@ -347,28 +288,7 @@ k_amr_elem(DevMesh m, const double* __restrict__ q, int criterion, Thr thr, int 
 __global__ void k_amr_col(DevMesh m, const int8_t* __restrict__ ae, int8_t* __restrict__ ac) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= m.n_col) return;
-    auto col_state = [&](int cc, bool& any_ref, bool& all_crs) {
-        any_ref = false; all_crs = true;
-        for (int z = 0; z < m.n_z; ++z) {
-            const int8_t a = ae[cc * m.n_z + z];
-            any_ref = any_ref || (a == 1);
-            all_crs = all_crs && (a == -1);
-        }
-    };
-    bool r, cr;
-    col_state(c, r, cr);
-    int8_t out = 0;
-    if (r) out = 1;
-    else if (cr && m.sib[4 * c] >= 0) {
-        bool ok = true;
-        for (int s = 0; s < 4; ++s) {
-            bool r2, c2;
-            col_state(m.sib[4 * c + s], r2, c2);
-            ok = ok && c2 && !r2;
-        }
-        if (ok) out = -1;
-    }
-    ac[c] = out;
+    ac[c] = column_rule(m, ae, c);
 }
 
 // Solution transfer between two meshes with the same vertical structure:
@@ -442,7 +362,7 @@ static int sem_launch_rhs(const sem_mesh* M, const double* q, const double* hv, 
 // ====================================================================== C ABI
 extern "C" {
 
-const char* sem_last_error(void) { return g_err.c_str(); }
+const char* sem_last_error(void) { return sem::last_error().c_str(); }
 
 int sem_mesh_create(const sem_mesh_desc* desc, sem_mesh** out) {
     if (!desc || !out) return fail(SEM_ERR_ARG, "null argument");
@@ -479,7 +399,10 @@ int sem_mesh_create(const sem_mesh_desc* desc, sem_mesh** out) {
     UP(H.asm_ptr, asm_ptr) UP(H.asm_slot, asm_slot) UP(H.asmH_ptr, asmH_ptr)
     UP(H.asmH_slot, asmH_slot) UP(H.minv_h, minv_h) UP(H.minv_v, minv_v)
     UP(H.sib, sib) UP(H.col_level, col_level) UP(H.basis.D, D) UP(H.basis.w, w)
+    UP(H.nbr_ptr, nbr_ptr) UP(H.nbr_col, nbr_col)
 #undef UP
+    HIPCHK(hipMalloc(&M->feat_aux, sizeof(double) * 2 * size_t(std::max<int64_t>(1, int64_t(H.n_col) * H.n_z))));
+    M->ws_bytes += int64_t(sizeof(double)) * 2 * int64_t(H.n_col) * H.n_z;
     if ((rc = sem::fused_plan_build(H, 0, M->fused)) != SEM_OK)
         return fail(rc, "could not build the fused-stage tables");
     *out = M.release();

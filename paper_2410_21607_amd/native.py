@@ -69,8 +69,23 @@ SIGNATURES = {
     "sem_transfer_destroy": (c_int, [c_void_p]),
     "sem_transfer_plan": (c_int, [ctypes.POINTER(SemMeshDesc), ctypes.POINTER(SemMeshDesc),
                                   ctypes.POINTER(ctypes.c_int64), c_i32p, c_i32p, c_dp]),
+    "amr_features": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_dp, c_int,
+                             ctypes.POINTER(ctypes.c_float), c_void_p, c_void_p, c_void_p]),
+    "amr_forecast_flags": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_void_p, c_void_p,
+                                   c_void_p]),
+    "sem_forecast_labels": (c_int, [ctypes.POINTER(SemMeshDesc), ctypes.POINTER(SemMeshDesc),
+                                    c_void_p, c_void_p]),
+    "mlp_forward": (c_int, [c_void_p, c_void_p, ctypes.c_int64, c_void_p, c_void_p]),
+    "mlp_backward": (c_int, [c_void_p, c_void_p, ctypes.c_int64, c_void_p, c_void_p,
+                             ctypes.c_int64, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "mlp_adam_step": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int, ctypes.c_float,
+                              ctypes.c_float, ctypes.c_float, ctypes.c_float, c_void_p]),
     "sem_last_error": (ctypes.c_char_p, []),
 }
+
+SEM_NFEAT = 16
+SEM_MLP_NPARAM = 5443
+SEM_MLP_WORK = 260
 
 _LIB = None
 

@@ -140,3 +140,24 @@ def test_transfer_rows_match_oracle(seed, N, periodic):
     want = adapt.transfer(oa, ob, q_or)[:, perm_b]
     err = np.max(np.abs(got - want))
     assert err <= 1e-13 * np.max(np.abs(want)), err
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_forecast_labels_match_oracle(seed):
+    """Training classes (integer work): bit-exact against the oracle on a
+    layout and its adapted successor, with random levels asked for."""
+    _lib()
+    from paper_2410_21607_amd import api
+    from oracle import forecast
+    rng = np.random.default_rng(90 + seed)
+    p = params(n_z=3)
+    at = random_layout(seed, 4, 4, 2)
+    later = api.sem_adapt_columns(p, at, family_flags(at, rng, 0.5, 0.3), 3)
+    dem = rng.integers(0, 4, size=len(later) * 3).astype(np.int8)
+    got = api.sem_forecast_labels(p, at, later, dem)
+    want = forecast.labels(at, later, dem, 3)
+    np.testing.assert_array_equal(got, want)
+    # and the other way round (a later layout coarser in places)
+    dem2 = rng.integers(0, 4, size=len(at) * 3).astype(np.int8)
+    np.testing.assert_array_equal(api.sem_forecast_labels(p, later, at, dem2),
+                                  forecast.labels(later, at, dem2, 3))
