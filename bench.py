@@ -164,6 +164,124 @@ def amr_throughput(device):
     return out
 
 
+def adaptive_run(case, device, forecaster=None, rebuild_every=1, recorder=None, adapt=True,
+                 columns=None):
+    """An AdaptiveRun of an AMR workload (``case["amr"]`` settings) from its
+    synthetic initial state on the given (default: the case's) layout."""
+    from paper_2410_21607_amd import api
+    from paper_2410_21607_amd.adaptive import AdaptiveRun
+    from synth import cases
+    c = dict(case)
+    if columns is not None:
+        c["columns"] = columns
+    mesh = api.Mesh.from_case(c)
+    _, _, z = mesh.coords()
+    bg = cases.reference_state(c, z)
+    ref = (bg["rho0"], bg["theta0"], bg["dtheta0dz"])
+    mesh.set_reference(*ref)
+    q0 = mesh.unpack(cases.initial_state(c, mesh.node_xyz()), device=device)
+    a = c["amr"]
+    return AdaptiveRun(mesh, q0, c["dt"], ref, a["criterion"], a["thresholds"], a["lvl_max"],
+                       a["interval"], forecaster=forecaster, rebuild_every=rebuild_every,
+                       on_boundary=recorder, adapt=adapt)
+
+
+def _summary(run, ref_vmax=None):
+    import numpy as np
+    v = np.array([b["vmax"] for b in run.log])
+    out = {"wall_s": run.wall(), "step_s": run.timings["step"], "rebuilds": run.n_rebuild,
+           "boundaries": run.n_boundary, "timings_s": dict(run.timings),
+           "mean_n_dof": float(np.mean([b["n_dof"] for b in run.log])) if run.log else 0.0,
+           "mean_split_flag_fraction": float(np.mean([b["split_frac"] for b in run.log]))
+           if run.log else 0.0,
+           "vmax_final": float(v[-1]) if v.size else None}
+    if ref_vmax is not None and v.size:
+        out["vmax_max_rel_dev_vs_uniform"] = float(np.max(np.abs(v - ref_vmax) / ref_vmax))
+    return out
+
+
+def forecaster_experiment(device, case_name="vortex3_64x64x8_n4", sim_seconds=405.0,
+                          train_seeds=(0, 1, 2, 3, 4), eval_seed=5, horizon=5, n_samples=200000,
+                          epochs=20):
+    """Plain-criterion AMR vs forecaster-driven AMR vs the uniform finest mesh
+    on a translating vortex: wall time and maximum-wind deviation."""
+    import numpy as np
+    import torch
+    from paper_2410_21607_amd import forecast
+    from synth import cases, columns as sc
+    base = cases.get(case_name)
+    n_steps = int(round(sim_seconds / base["dt"]))
+    n_steps -= n_steps % base["amr"]["interval"]
+    res = {"workload": case_name, "sim_seconds": n_steps * base["dt"], "steps": n_steps,
+           "dt": base["dt"], "interval_steps": base["amr"]["interval"], "horizon_intervals": horizon,
+           "thresholds": base["amr"]["thresholds"], "lvl_max": base["amr"]["lvl_max"],
+           "steering_wind": base["steer"]}
+    # 1. training data from plain-criterion runs
+    X, Y = [], []
+    t0 = time.perf_counter()
+    for sd in train_seeds:
+        rec = forecast.Recorder()
+        run = adaptive_run(cases.get(case_name, seed=sd), device, recorder=rec)
+        run.run(n_steps)
+        x, y = rec.samples(horizon)
+        X.append(x)
+        Y.append(y)
+        print(f"  training run seed {sd}: {len(y)} samples, {run.n_rebuild} rebuilds, "
+              f"{run.wall():.1f} s", file=sys.stderr, flush=True)
+        del run, rec
+        torch.cuda.empty_cache()
+    X, Y = np.concatenate(X), np.concatenate(Y)
+    res["samples_available"] = int(Y.size)
+    res["class_counts"] = np.bincount(Y, minlength=3).tolist()
+    Xs, Ys = forecast.balanced_subset(X, Y, n_samples, seed=0)
+    fc = forecast.Forecaster(seed=0, horizon=horizon)
+    t1 = time.perf_counter()
+    losses = fc.train(Xs, Ys, epochs=epochs, batch=1024, lr=1e-3, seed=0)
+    torch.cuda.synchronize()
+    res["training"] = {"samples": int(Ys.size), "epochs": epochs, "loss_first": losses[0],
+                       "loss_last": losses[-1], "train_s": time.perf_counter() - t1,
+                       "collect_s": t1 - t0,
+                       "accuracy_all_samples": float(np.mean(fc.predict(X) == Y))}
+    del X, Y, Xs, Ys
+    # 2. evaluation on an unseen seed
+    ev = cases.get(case_name, seed=eval_seed)
+    lm = ev["amr"]["lvl_max"]
+    fine = np.array([(lm, x, y) for x in range(ev["nx0"] << lm) for y in range(ev["ny0"] << lm)])
+    uni = adaptive_run(ev, device, adapt=False, columns=sc.morton_sort(fine, lm))
+    uni.run(n_steps)
+    ref_v = np.array([b["vmax"] for b in uni.log])
+    res["uniform_finest"] = _summary(uni)
+    del uni
+    torch.cuda.empty_cache()
+    plain = adaptive_run(ev, device)
+    plain.run(n_steps)
+    res["plain_amr"] = _summary(plain, ref_v)
+    del plain
+    torch.cuda.empty_cache()
+    # ablation: the same rebuild schedule without the network
+    sparse = adaptive_run(ev, device, rebuild_every=horizon)
+    sparse.run(n_steps)
+    res["plain_amr_sparse_rebuilds"] = _summary(sparse, ref_v)
+    del sparse
+    torch.cuda.empty_cache()
+    rec = forecast.Recorder()
+    fr = adaptive_run(ev, device, forecaster=fc, rebuild_every=horizon)
+    fr.run(n_steps)
+    res["forecaster_amr"] = _summary(fr, ref_v)
+    del fr
+    # held-out skill: the eval seed's plain run, features at t vs classes at t + horizon
+    chk = adaptive_run(ev, device, recorder=rec)
+    chk.run(n_steps)
+    Xe, Ye = rec.samples(horizon)
+    res["heldout_scores"] = forecast.class_scores(fc.predict(Xe), Ye) if Ye.size else None
+    p, f, u = res["plain_amr"], res["forecaster_amr"], res["uniform_finest"]
+    res["speedup_forecaster_over_plain"] = p["wall_s"] / f["wall_s"]
+    res["speedup_plain_amr_over_uniform"] = u["wall_s"] / p["wall_s"]
+    res["speedup_forecaster_amr_over_uniform"] = u["wall_s"] / f["wall_s"]
+    res["vmax_dev_difference"] = f["vmax_max_rel_dev_vs_uniform"] - p["vmax_max_rel_dev_vs_uniform"]
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -173,7 +291,14 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the FP32-variant and AMR measurements")
+                    help="skip the FP32-variant, AMR and forecaster measurements")
+    ap.add_argument("--forecaster", action="store_true",
+                    help="run the forecaster experiment even with --no-extras")
+    ap.add_argument("--forecaster-only", action="store_true",
+                    help="run only the forecaster experiment and print its JSON")
+    ap.add_argument("--fc-case", default="vortex3_64x64x8_n4")
+    ap.add_argument("--fc-seconds", type=float, default=405.0,
+                    help="simulated seconds of each forecaster-experiment run")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run plain device copies of the state size (counter calibration)")
     args = ap.parse_args()
@@ -191,6 +316,9 @@ def main():
     from synth import cases
 
     dev = torch.device("cuda:0")
+    if args.forecaster_only:
+        print(json.dumps(forecaster_experiment(dev, args.fc_case, args.fc_seconds)), flush=True)
+        return
     case = cases.get(WORKLOAD)
     mesh = api.Mesh.from_case(case)
     _, _, z = mesh.coords()
@@ -260,6 +388,8 @@ def main():
     if not args.no_extras:
         res["fp32_variant"] = fp32_variant(case, mesh, q0)
         res["amr_two_level"] = amr_throughput(dev)
+    if args.forecaster or not args.no_extras:
+        res["amr_forecaster"] = forecaster_experiment(dev, args.fc_case, args.fc_seconds)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(case)
     print(json.dumps(res), flush=True)

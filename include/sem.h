@@ -308,6 +308,14 @@ int amr_features(const sem_mesh *mesh, const double *d_q, const double *d_q_prev
 int amr_forecast_flags(const sem_mesh *mesh, const float *d_logits, const int8_t *d_plain_elem,
                        int lvl_max, int8_t *d_adapt_elem, int8_t *d_adapt_col, void *stream);
 
+/* Maximum horizontal wind (the paper's intensity measure, Section 5):
+ * *d_vmax (device) = max sqrt(u^2 + v^2) over the unique nodes whose
+ * horizontal position (as reported by sem_mesh_coords) lies in
+ * [x0, x1] x [y0, y1], every height; 0 if none.  Uses the handle's scratch,
+ * so calls on one handle must not overlap. */
+int sem_max_wind(const sem_mesh *mesh, const double *d_q, double x0, double x1, double y0,
+                 double y1, double *d_vmax, void *stream);
+
 /* Training labels (host only): for every element (column c, layer) of the
  * layout `at`, the class clip(D - level, -1, 1) + 1 in {0, 1, 2}, where D is
  * the criterion's level (d_dem of amr_features) of the element of the same

@@ -2,21 +2,26 @@
 evaluate the refinement criterion, adapt the column quadtree, move the
 solution, continue stepping).
 
-Every ``interval`` RK3 steps ``AdaptiveRun.adapt`` does, on the device unless
-noted:
+Every ``interval`` RK3 steps the run reaches a boundary.  There:
 
-1. ``amr_flag`` -> per-column flags (+1 split, -1 merge, 0 keep);
-2. optionally, a forecaster (a callable taking the run and the criterion's
-   element and column flags and returning combined column flags on the
-   device);
-3. ``sem_adapt_columns`` (host) -> the new layout (split, 2:1 balance,
-   merge);
-4. a new mesh handle over the new layout, its reference state (the vertical
-   structure is unchanged, so the same per-level arrays are reused), the
-   transfer rows, one ``sem_transfer_apply`` launch;
-5. a new ``Stepper`` (HIP graphs recaptured for the new mesh).
+1. ``amr_flag`` gives the criterion's element and column flags (+1 split,
+   -1 merge, 0 keep) and ``sem_max_wind`` the intensity diagnostic;
+2. an optional ``on_boundary(run, plain_elem)`` hook sees the state (data
+   collection for the forecaster);
+3. every ``rebuild_every``-th boundary the mesh may be rebuilt:
+   a. optionally a forecaster (a callable taking the run and the criterion's
+      flags and returning combined column flags on the device) replaces the
+      column flags;
+   b. ``sem_adapt_columns`` (host) gives the new layout (split, 2:1 balance,
+      merge);
+   c. a new mesh handle over it, its reference state (the vertical structure
+      is unchanged, so the same per-level arrays are reused), the transfer
+      rows and one ``sem_transfer_apply`` launch;
+   d. a new ``Stepper`` (HIP graphs recaptured for the new mesh).
 
-The wall time of each phase is accumulated in ``timings``.
+The state at the previous boundary is kept on the current mesh
+(``q_prev``) for the forecaster's rate-of-change features.  Wall time per
+phase is accumulated in ``timings``; per-boundary diagnostics in ``log``.
 """
 
 import time
@@ -31,9 +36,12 @@ from .solver import Stepper
 class AdaptiveRun:
     def __init__(self, mesh, q0, dt, reference, criterion, thresholds, lvl_max,
                  interval, precision=api.SEM_FP64, graph=True, layers_per_chunk=0,
-                 forecaster=None):
+                 forecaster=None, rebuild_every=1, on_boundary=None, wind_box=None,
+                 adapt=True):
         """mesh: api.Mesh; q0: padded state tensor on it; reference: tuple of
-        (rho0, theta0, dtheta0dz) per vertical node (already set on mesh)."""
+        (rho0, theta0, dtheta0dz) per vertical node (already set on mesh);
+        wind_box: (x0, x1, y0, y1) of the maximum-wind diagnostic (default:
+        the whole domain); adapt=False keeps the mesh fixed (diagnostics only)."""
         self.mesh = mesh
         self.dt = float(dt)
         self.reference = tuple(np.asarray(a, dtype=np.float64) for a in reference)
@@ -45,12 +53,21 @@ class AdaptiveRun:
         self.graph = bool(graph)
         self.lpc = int(layers_per_chunk)
         self.forecaster = forecaster
-        self.timings = dict(step=0.0, flag=0.0, layout=0.0, mesh=0.0, transfer=0.0, capture=0.0)
-        self.n_adapt = 0
+        self.rebuild_every = max(1, int(rebuild_every))
+        self.adapt_enabled = bool(adapt)
+        self.on_boundary = on_boundary
+        p = mesh.params
+        self.wind_box = wind_box or (-0.5 * p["Lx"], 0.5 * p["Lx"], -0.5 * p["Ly"], 0.5 * p["Ly"])
+        self.timings = dict(step=0.0, flag=0.0, forecast=0.0, layout=0.0, mesh=0.0,
+                            transfer=0.0, capture=0.0)
+        self.n_boundary = 0
         self.n_rebuild = 0
         self.steps = 0
         self.history = []          # (step, n_col, n_dof) after each rebuild
+        self.log = []              # per boundary: step, vmax, plain split fraction, n_elem
+        self._vmax = torch.zeros(1, dtype=torch.float64, device=q0.device)
         self._new_stepper(q0)
+        self.q_prev = self.q.clone()
 
     # ------------------------------------------------------------------ #
     def _new_stepper(self, q):
@@ -65,25 +82,46 @@ class AdaptiveRun:
     def q(self):
         return self.stepper.q
 
-    def flags(self):
-        """Per-column flags of the plain criterion (device int8) and, when a
-        forecaster is attached, the combined flags."""
+    def plain_flags(self):
+        """The criterion's element and column flags (device int8)."""
         m = self.mesh
         ae = torch.empty(m.info["n_elem"], dtype=torch.int8, device="cuda")
         ac = torch.empty(m.info["n_col"], dtype=torch.int8, device="cuda")
         api.amr_flag(m, self.q, self.criterion, self.thresholds, self.lvl_max, ae, ac)
-        if self.forecaster is not None:
-            ac = self.forecaster(self, ae, ac)
         return ae, ac
 
-    def adapt(self):
-        """One adaptation pass; returns True when the mesh changed."""
+    def vmax(self):
+        api.sem_max_wind(self.mesh, self.q, self.wind_box, self._vmax)
+        return float(self._vmax.item())
+
+    def boundary(self):
+        """Diagnostics, the hook, and (every rebuild_every-th time) a rebuild.
+        Returns True when the mesh changed."""
         t0 = time.perf_counter()
-        _, ac = self.flags()
-        flags = ac.cpu().numpy()
+        k = self.n_boundary
+        self.n_boundary += 1
+        ae, ac = self.plain_flags()
+        ae_h = ae.cpu().numpy()
+        self.log.append(dict(step=self.steps, vmax=self.vmax(),
+                             split_frac=float(np.mean(ae_h == 1)), n_elem=int(ae_h.size),
+                             n_dof=int(self.mesh.n_dof)))
+        self.timings["flag"] += time.perf_counter() - t0
+        if self.on_boundary is not None:
+            self.on_boundary(self, ae)
+        changed = False
+        if self.adapt_enabled and k % self.rebuild_every == 0:
+            if self.forecaster is not None:
+                t1 = time.perf_counter()
+                ac = self.forecaster(self, ae, ac)
+                torch.cuda.synchronize()
+                self.timings["forecast"] += time.perf_counter() - t1
+            changed = self._rebuild(ac.cpu().numpy())
+        if not changed:
+            self.q_prev = self.q.clone()
+        return changed
+
+    def _rebuild(self, flags):
         t1 = time.perf_counter()
-        self.timings["flag"] += t1 - t0
-        self.n_adapt += 1
         if not flags.any():
             return False
         cols = api.sem_adapt_columns(self.mesh, self.mesh.columns, flags, self.lvl_max)
@@ -104,14 +142,17 @@ class AdaptiveRun:
         self.timings["transfer"] += t4 - t3
         self.mesh = new
         self._new_stepper(q_new)
+        self.q_prev = self.q.clone()
         self.n_rebuild += 1
         self.history.append((self.steps, int(new.info["n_col"]), int(new.n_dof)))
         return True
 
-    def run(self, n_steps, adapt_first=False):
-        """Advance n_steps RK3 steps, adapting every ``interval`` steps."""
-        if adapt_first:
-            self.adapt()
+    # kept for callers that adapt by hand
+    def adapt(self):
+        return self.boundary()
+
+    def run(self, n_steps):
+        """Advance n_steps RK3 steps with a boundary every ``interval`` steps."""
         done = 0
         while done < n_steps:
             k = min(self.interval - (self.steps % self.interval), n_steps - done)
@@ -122,6 +163,8 @@ class AdaptiveRun:
             done += k
             self.steps += k
             if self.steps % self.interval == 0:
-                self.adapt()
+                self.boundary()
         return self.q
 
+    def wall(self):
+        return sum(self.timings.values())

@@ -376,6 +376,14 @@ def amr_forecast_flags(mesh, logits, plain_elem, lvl_max, adapt_elem, adapt_col,
                 _ptr(adapt_col, torch.int8, mesh.info["n_col"], "adapt_col"), _stream(stream))
 
 
+def sem_max_wind(mesh, q, box, out, stream=None):
+    """out (1-element float64 CUDA tensor) = max horizontal wind in box
+    (x0, x1, y0, y1)."""
+    x0, x1, y0, y1 = (float(b) for b in box)
+    native.call("sem_max_wind", mesh.handle, _ptr(q, torch.float64, mesh.n_state, "q"), x0, x1,
+                y0, y1, _ptr(out, torch.float64, 1, "out"), _stream(stream))
+
+
 def sem_forecast_labels(params, columns_at, columns_later, dem_later):
     """Host-only training classes (n_elem(at),) int8 in {0, 1, 2}."""
     ka, da = _desc_of(params, columns_at)

@@ -199,6 +199,44 @@ __global__ void k_forecast_col(DevMesh m, const int8_t* __restrict__ ae, int8_t*
     if (c < m.n_col) ac[c] = column_rule(m, ae, c);
 }
 
+// maximum horizontal wind sqrt(u^2 + v^2) over the unique nodes whose
+// horizontal position lies in [x0, x1] x [y0, y1]: per-block maxima, then one
+// block over the partial results (a maximum does not depend on order)
+constexpr int WIND_BLOCKS = 256;
+
+__global__ void __launch_bounds__(256)
+k_max_wind(DevMesh m, const double* __restrict__ q, const double* __restrict__ hxy, double x0,
+           double x1, double y0, double y1, double* __restrict__ part) {
+    __shared__ double red[4];
+    const int64_t n = int64_t(m.n_h) * m.nzn;
+    const int64_t fs = int64_t(m.n_h) * m.ldz;
+    double best = 0.0;
+    for (int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; t < n;
+         t += int64_t(gridDim.x) * blockDim.x) {
+        const int64_t h = t / m.nzn;
+        const int kz = int(t - h * m.nzn);
+        const double x = hxy[2 * h], y = hxy[2 * h + 1];
+        if (x < x0 || x > x1 || y < y0 || y > y1) continue;
+        const double u = q[fs + h * m.ldz + kz], v = q[2 * fs + h * m.ldz + kz];
+        best = fmax(best, sqrt(u * u + v * v));
+    }
+    for (int off = 32; off > 0; off >>= 1) best = fmax(best, __shfl_xor(best, off));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = best;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+}
+
+__global__ void __launch_bounds__(256)
+k_max_wind_final(const double* __restrict__ part, int n, double* __restrict__ out) {
+    __shared__ double red[4];
+    double best = 0.0;
+    for (int t = threadIdx.x; t < n; t += blockDim.x) best = fmax(best, part[t]);
+    for (int off = 32; off > 0; off >>= 1) best = fmax(best, __shfl_xor(best, off));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = best;
+    __syncthreads();
+    if (threadIdx.x == 0) *out = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+}
+
 }  // namespace sem
 
 namespace {
@@ -261,6 +299,21 @@ int amr_forecast_flags(const sem_mesh* M, const float* logits, const int8_t* pla
     hipLaunchKernelGGL(sem::k_forecast_elem, dim3(grid), dim3(256), 0, s, d, logits, plain, lvl_max, ae);
     HIPCHK(hipGetLastError());
     hipLaunchKernelGGL(sem::k_forecast_col, dim3((d.n_col + 255) / 256), dim3(256), 0, s, d, ae, ac);
+    HIPCHK(hipGetLastError());
+    return SEM_OK;
+}
+
+int sem_max_wind(const sem_mesh* M, const double* q, double x0, double x1, double y0, double y1,
+                 double* vmax, void* stream) {
+    if (!M) return fail(SEM_ERR_ARG, "null mesh");
+    if (!q || !vmax) return fail(SEM_ERR_ARG, "null array");
+    if (!(x0 <= x1 && y0 <= y1)) return fail(SEM_ERR_ARG, "empty box");
+    hipStream_t s = (hipStream_t)stream;
+    hipLaunchKernelGGL(sem::k_max_wind, dim3(sem::WIND_BLOCKS), dim3(256), 0, s, M->d, q, M->d_hxy,
+                       x0, x1, y0, y1, M->wind_part);
+    HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL(sem::k_max_wind_final, dim3(1), dim3(256), 0, s, M->wind_part,
+                       sem::WIND_BLOCKS, vmax);
     HIPCHK(hipGetLastError());
     return SEM_OK;
 }

@@ -38,10 +38,13 @@ struct sem_mesh {
     bool have_ref = false;
     sem::FusedPlan fused;
     double* feat_aux = nullptr;   // 2 doubles per element (amr_features)
+    double* wind_part = nullptr;  // 256 partial maxima (sem_max_wind)
+    const double* d_hxy = nullptr; // x, y of every unique horizontal node
     int64_t ws_bytes = 0;
     ~sem_mesh() {
         sem::fused_plan_free(fused);
         if (feat_aux) (void)hipFree(feat_aux);
+        if (wind_part) (void)hipFree(wind_part);
         for (void* p : allocs) (void)hipFree(p);
     }
     template <typename T>

@@ -401,6 +401,8 @@ int sem_mesh_create(const sem_mesh_desc* desc, sem_mesh** out) {
     UP(H.sib, sib) UP(H.col_level, col_level) UP(H.basis.D, D) UP(H.basis.w, w)
     UP(H.nbr_ptr, nbr_ptr) UP(H.nbr_col, nbr_col)
 #undef UP
+    if ((rc = M->upload(H.h_xy, &M->d_hxy)) != SEM_OK) return rc;
+    HIPCHK(hipMalloc(&M->wind_part, sizeof(double) * 256));
     HIPCHK(hipMalloc(&M->feat_aux, sizeof(double) * 2 * size_t(std::max<int64_t>(1, int64_t(H.n_col) * H.n_z))));
     M->ws_bytes += int64_t(sizeof(double)) * 2 * int64_t(H.n_col) * H.n_z;
     if ((rc = sem::fused_plan_build(H, 0, M->fused)) != SEM_OK)

@@ -73,6 +73,8 @@ SIGNATURES = {
                              ctypes.POINTER(ctypes.c_float), c_void_p, c_void_p, c_void_p]),
     "amr_forecast_flags": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_void_p, c_void_p,
                                    c_void_p]),
+    "sem_max_wind": (c_int, [c_void_p, c_void_p, c_double, c_double, c_double, c_double,
+                             c_void_p, c_void_p]),
     "sem_forecast_labels": (c_int, [ctypes.POINTER(SemMeshDesc), ctypes.POINTER(SemMeshDesc),
                                     c_void_p, c_void_p]),
     "mlp_forward": (c_int, [c_void_p, c_void_p, ctypes.c_int64, c_void_p, c_void_p]),

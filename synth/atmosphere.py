@@ -48,11 +48,19 @@ def rankine(r, v_max, r_max, tail=0.5):
     return np.where(r <= r_max, inner, outer)
 
 
+def smooth_profile(r, v_max, r_max):
+    """V = 2 V_max x / (1 + x^2), x = r / r_max: peak V_max at r_max, smooth
+    vorticity 4 V_max / (r_max (1 + x^2)^2) (no jump at r_max)."""
+    x = np.asarray(r, dtype=np.float64) / r_max
+    return 2.0 * v_max * x / (1.0 + x * x)
+
+
 class Vortex:
     """Tabulated radial integrals of the balanced vortex."""
 
-    def __init__(self, v_max, r_max, D2, R_out, z_top_v, f, n_tab=400001):
+    def __init__(self, v_max, r_max, D2, R_out, z_top_v, f, n_tab=400001, profile="rankine"):
         self.v_max, self.r_max, self.D2 = v_max, r_max, D2
+        self.profile = profile
         self.R_out, self.z_top_v, self.f = R_out, z_top_v, f
         # radial grid with r_max on a grid point
         n1 = max(2, int(round((n_tab - 1) * r_max / R_out)))
@@ -71,7 +79,8 @@ class Vortex:
         self.B = cb[-1] - cb
 
     def vt_surface(self, r):
-        return rankine(r, self.v_max, self.r_max) * np.exp(-(np.asarray(r) / self.D2) ** 6)
+        prof = smooth_profile if self.profile == "smooth" else rankine
+        return prof(r, self.v_max, self.r_max) * np.exp(-(np.asarray(r) / self.D2) ** 6)
 
     def zv(self, z):
         return np.maximum(0.0, 1.0 - np.asarray(z) / self.z_top_v)
@@ -92,9 +101,30 @@ class Vortex:
         return (rv(r + h) - rv(r - h)) / (2 * h) / r
 
 
-def initial_state(xyz, bg_fn, vortex, phys, noise_amp, noise_ztop, seed, Lx, Ly):
-    """(rho', u, v, w, theta') at points xyz (n, 3)."""
+def smooth_modes(xyz, Lx, Ly, seed, n_modes=6, k_max=4):
+    """A smooth periodic field in [-1, 1]: a normalised sum of n_modes
+    horizontal Fourier modes (wavenumbers 1..k_max per direction) with seeded
+    amplitudes and phases (PCG64), each with a seeded vertical half-sine."""
+    rng = np.random.default_rng(seed)
     x, y, z = xyz[:, 0], xyz[:, 1], xyz[:, 2]
+    H = max(float(np.max(z)), 1.0)
+    out = np.zeros_like(x)
+    tot = 0.0
+    for _ in range(n_modes):
+        kx, ky = rng.integers(1, k_max + 1, size=2)
+        ph = rng.uniform(0, 2 * np.pi, size=2)
+        a = rng.uniform(0.5, 1.0)
+        m = rng.integers(1, 3)
+        out += a * np.cos(2 * np.pi * kx * x / Lx + ph[0]) * np.cos(2 * np.pi * ky * y / Ly + ph[1]) \
+            * np.sin(m * np.pi * z / H)
+        tot += a
+    return out / tot
+
+
+def initial_state(xyz, bg_fn, vortex, phys, noise_amp, noise_ztop, seed, Lx, Ly,
+                  center=(0.0, 0.0), noise_kind="nodes"):
+    """(rho', u, v, w, theta') at points xyz (n, 3)."""
+    x, y, z = xyz[:, 0] - center[0], xyz[:, 1] - center[1], xyz[:, 2]
     g, R_d, c_p, p00 = phys["g"], phys["R_d"], phys["c_p"], phys["p00"]
     c_v = c_p - R_d
     bg = bg_fn(z)
@@ -118,9 +148,12 @@ def initial_state(xyz, bg_fn, vortex, phys, noise_amp, noise_ztop, seed, Lx, Ly)
     if noise_amp > 0.0:
         # perturb theta at fixed pressure: rho theta stays fixed, so the noise
         # is a buoyancy perturbation and not a pressure (acoustic) one
-        U = noise.uniform01(xyz, Lx, Ly, seed)
-        mask = z <= noise_ztop + 1e-6
-        dth = np.where(mask, noise_amp * (2.0 * U - 1.0), 0.0)
+        if noise_kind == "modes":
+            dth = noise_amp * smooth_modes(xyz, Lx, Ly, seed)
+        else:
+            U = noise.uniform01(xyz, Lx, Ly, seed)
+            mask = z <= noise_ztop + 1e-6
+            dth = np.where(mask, noise_amp * (2.0 * U - 1.0), 0.0)
         rho_new = rho * theta / (theta + dth)
         rho_p = rho_new - bg["rho0"]
         theta_p = theta_p + dth

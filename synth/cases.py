@@ -50,10 +50,12 @@ def _case(N, nx0, ny0, Lx, Ly, H, n_z, cols, f=5e-5, v_max=15.0, r_max=50e3,
 def _vorticity_refiner(case, thresholds):
     vx = vortex_of(case)
 
+    xc, yc = case["vortex"].get("center", (0.0, 0.0))
+
     def pred(x, y, level):
         if level >= len(thresholds):
             return np.zeros_like(x, dtype=bool)
-        return vx.vorticity_surface(np.sqrt(x * x + y * y)) > thresholds[level]
+        return vx.vorticity_surface(np.hypot(x - xc, y - yc)) > thresholds[level]
     return pred
 
 
@@ -103,6 +105,27 @@ def get(name, **over):
                 return 2
             return l
         c["columns"] = columns.refine_to_target(4, 4, tgt, 2, periodic)
+    elif name.startswith("vortex3_64x64x8_n4") or name.startswith("small_vortex3"):
+        # three-level AMR workload around a translating vortex: 40 m/s at
+        # 25 km, uniform steering wind, seeded theta noise; layout refined by
+        # the analytic surface vorticity at thresholds 2e-4 and 1e-3 s-1
+        small = name.startswith("small")
+        nb, nz = (16, 4) if small else (64, 8)
+        seed = int(over.pop("seed", 0))
+        c = _case(4, nb, nb, 400e3, 400e3, 20e3, nz, columns.uniform(nb, nb), v_max=40.0,
+                  r_max=25e3, noise_amp=0.1, seed=seed, dt=0.85 if small else 0.27,
+                  stages=10, name=name)
+        c["steer"] = (10.0, 0.0)
+        c["amr"] = dict(criterion=1, thresholds=[2e-4, 1e-3], lvl_max=2, interval=100)
+        # a smooth profile (no vorticity jump at r_max) and smooth seeded
+        # perturbations: an inviscid run stays free of grid-scale noise; the
+        # seed also moves the vortex centre by up to 10 km
+        c["vortex"]["profile"] = "smooth"
+        rs = np.random.default_rng(1000 + seed)
+        c["vortex"]["center"] = tuple(rs.uniform(-10e3, 10e3, size=2))
+        c["noise"] = dict(amp=0.3, z_top=1e30, seed=seed, kind="modes")
+        pred = _vorticity_refiner(c, c["amr"]["thresholds"])
+        c["columns"] = columns.refine_where(nb, nb, 400e3, 400e3, 2, pred)
     else:
         raise KeyError(name)
     for k, v in over.items():
@@ -114,7 +137,7 @@ def vortex_of(case):
     v = case["vortex"]
     L = min(case["Lx"], case["Ly"])
     return atmosphere.Vortex(v["v_max"], v["r_max"], L / 4.0, L / 2.0, v["z_top_v"],
-                             case["phys"]["f"])
+                             case["phys"]["f"], profile=v.get("profile", "rankine"))
 
 
 def reference_state(case, z):
@@ -129,6 +152,14 @@ def initial_state(case, xyz, vortex=None):
         vortex = vortex_of(case)
     nz = case["noise"]
     bg = lambda z: reference_state(case, z)
-    return atmosphere.initial_state(np.asarray(xyz, dtype=np.float64), bg, vortex,
-                                    case["phys"], nz["amp"], nz["z_top"], nz["seed"],
-                                    case["Lx"], case["Ly"])
+    q = atmosphere.initial_state(np.asarray(xyz, dtype=np.float64), bg, vortex,
+                                 case["phys"], nz["amp"], nz["z_top"], nz["seed"],
+                                 case["Lx"], case["Ly"],
+                                 center=case["vortex"].get("center", (0.0, 0.0)),
+                                 noise_kind=nz.get("kind", "nodes"))
+    su, sv = case.get("steer", (0.0, 0.0))
+    if su or sv:
+        # uniform steering wind over the vortex (the lids keep w = 0)
+        q[1] += su
+        q[2] += sv
+    return q
