@@ -74,7 +74,9 @@ __device__ __forceinline__ T pressure_perturbation(const DevMesh& m, int kz, dou
 }
 
 // At least four waves per SIMD: two workgroups share a CU, so that one can
-// compute while the other waits on memory (a few registers spill).
+// compute while the other waits on memory.  The update base is loaded only
+// when the node is finished (not held in registers across the derivatives),
+// which keeps the kernel within 128 registers without spilling.
 template <int NP, int LPC, typename T>
 __global__ void __launch_bounds__(((NP * NP * (LPC * (NP - 1) + 1) + 63) / 64) * 64, 4)
 k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double b, double c,
@@ -183,13 +185,6 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
             tile[7][lidx] = T(qv[4]);
         }
         __syncthreads();
-        double base[NF] = {0, 0, 0, 0, 0};
-        if (active && g >= 0) {
-            const double* bp = first ? qn : qo;
-            const int64_t o = int64_t(g) * m.ldz + kz;
-#pragma unroll
-            for (int f = 0; f < NF; ++f) base[f] = bp[f * fs + o];
-        }
         if (active) {
             // d/dx of tile tx and d/dy of tile ty at this node.  The empty asm
             // pins both results before the next field's LDS reads may be
@@ -265,6 +260,14 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
                     const bool lid = (kz == 0) || (kz == nzn - 1);
                     const double mi = c * minv_h * m.minv_v[kz];
                     const int64_t o = int64_t(g) * m.ldz + kz;
+                    // update base: q^n for the first contributor (not read
+                    // when a = 0), the partial q_out for later colours
+                    double base[NF] = {0, 0, 0, 0, 0};
+                    if (!first || a != 0.0) {
+                        const double* bp = first ? qn : qo;
+#pragma unroll
+                        for (int f = 0; f < NF; ++f) base[f] = bp[f * fs + o];
+                    }
                     if (first) {
 #pragma unroll
                         for (int fl = 0; fl < NF; ++fl) {
