@@ -40,10 +40,12 @@ def gather(mesh, RL, lid_field=3):
     return RG
 
 
-def rhs(mesh, qG, ref_local, phys):
-    """Global right-hand side: scatter, element RHS, gather (Sections 2-3)."""
+def rhs(mesh, qG, ref_local, phys, dtype=np.float64):
+    """Global right-hand side: scatter, element RHS, gather (Sections 2-3).
+    dtype=float32 evaluates the element right-hand side in float32 (the
+    reduced-precision variant); scatter and gather stay FP64."""
     from .euler import element_rhs
     qL = scatter(mesh, qG)
     RL = element_rhs(mesh, qL, ref_local["rho0"], ref_local["theta0"],
-                     ref_local["dtheta0dz"], phys)
+                     ref_local["dtheta0dz"], phys, dtype=dtype)
     return gather(mesh, RL)

@@ -50,25 +50,33 @@ def local_derivatives(D, f, dx, dy, dz):
 
     d/dx at (i,j,k) = (2/dx_e) sum_m D[i,m] f[m,j,k], likewise y (index j)
     and z (index k)."""
-    fx = np.einsum("im,ekjm->ekji", D, f) * (2.0 / dx)[:, None, None, None]
-    fy = np.einsum("jm,ekmi->ekji", D, f) * (2.0 / dy)[:, None, None, None]
-    fz = np.einsum("km,emji->ekji", D, f) * (2.0 / dz)[:, None, None, None]
+    two = f.dtype.type(2.0)
+    fx = np.einsum("im,ekjm->ekji", D, f) * (two / dx)[:, None, None, None]
+    fy = np.einsum("jm,ekmi->ekji", D, f) * (two / dy)[:, None, None, None]
+    fz = np.einsum("km,emji->ekji", D, f) * (two / dz)[:, None, None, None]
     return fx, fy, fz
 
 
-def element_rhs(mesh, qL, rho0, theta0, dtheta0dz, phys):
+def element_rhs(mesh, qL, rho0, theta0, dtheta0dz, phys, dtype=np.float64):
     """Pointwise strong-form right-hand side on every local node.
 
     qL : array (5, E, n, n, n) of local values (rho', u, v, w, theta').
     rho0, theta0, dtheta0dz : reference state at the local nodes, (E,n,n,n).
     phys : dict with f, g, R_d, c_p, p00.
-    Returns R_L of shape (5, E, n, n, n) (not mass weighted)."""
+    dtype : float64, or float32 for the reduced-precision variant: the
+            pointwise fields, the derivatives and the right-hand side are
+            float32 arrays (perturbations and reference rounded to float32;
+            p' is the exact difference rounded to float32, so no cancellation
+            enters); the caller's assembly stays FP64.
+    Returns R_L of shape (5, E, n, n, n) (not mass weighted, float64)."""
+    pp = pressure_perturbation(rho0, theta0, qL[0], qL[4],
+                               phys["R_d"], phys["c_p"], phys["p00"]).astype(dtype)
+    qL = np.asarray(qL).astype(dtype)
+    rho0, theta0, dtheta0dz = (np.asarray(a).astype(dtype) for a in (rho0, theta0, dtheta0dz))
     rho_p, u, v, w, th_p = qL
-    D = derivative_matrix(mesh.N)
-    dx, dy, dz = mesh.e_dx, mesh.e_dy, mesh.e_dz
+    D = derivative_matrix(mesh.N).astype(dtype)
+    dx, dy, dz = (np.asarray(a).astype(dtype) for a in (mesh.e_dx, mesh.e_dy, mesh.e_dz))
     rho = rho0 + rho_p
-    pp = pressure_perturbation(rho0, theta0, rho_p, th_p,
-                               phys["R_d"], phys["c_p"], phys["p00"])
     d = lambda f: local_derivatives(D, f, dx, dy, dz)
     mx, _, _ = d(rho * u)
     _, my, _ = d(rho * v)
@@ -78,11 +86,11 @@ def element_rhs(mesh, qL, rho0, theta0, dtheta0dz, phys):
     wx, wy, wz = d(w)
     px, py, pz = d(pp)
     tx, ty, tz = d(th_p)
-    f, g = phys["f"], phys["g"]
+    f, g = dtype(phys["f"]), dtype(phys["g"])
     R = np.empty_like(qL)
     R[0] = -(mx + my + mz)
     R[1] = -(u * ux + v * uy + w * uz) - px / rho + f * v
     R[2] = -(u * vx + v * vy + w * vz) - py / rho - f * u
     R[3] = -(u * wx + v * wy + w * wz) - pz / rho - (rho_p / rho) * g
     R[4] = -(u * tx + v * ty + w * tz) - w * dtheta0dz
-    return R
+    return R.astype(np.float64)

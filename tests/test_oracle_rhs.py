@@ -215,3 +215,26 @@ def test_column_rule():
     ef2[3] = 0       # one element of sibling 1 keeps -> nobody in the family coarsens
     out2 = amr.column_flags(ef2, cols, nz)
     assert list(out2) == [0, 0, 0, 0, 1]
+
+
+def test_fp32_mode_is_float32_arithmetic():
+    """The oracle's reduced-precision mode really rounds to float32: its
+    tendency differs from FP64 by float32 round-off amplified by the
+    derivatives (between 1e-9 and 1e-3 relative per field); the hydrostatic
+    rest stays at rest in both modes (every perturbation term vanishes)."""
+    import numpy as np
+    from harness import oracle_mesh, oracle_reference_local
+    from oracle import assembly, metrics
+    from synth import cases
+    c = cases.get("vortex_8x8x4_n4")
+    m = oracle_mesh(c)
+    ref = oracle_reference_local(c, m)
+    q = cases.initial_state(c, m.node_xyz)
+    r64 = assembly.rhs(m, q, ref, c["phys"])
+    r32 = assembly.rhs(m, q, ref, c["phys"], dtype=np.float32)
+    err = metrics.rel_l2(r32, r64, metrics.RHS_FLOORS)
+    assert np.all(err > 1e-9) and np.all(err < 1e-3), err
+    rest = np.zeros_like(q)
+    assert np.abs(assembly.rhs(m, rest, ref, c["phys"])).max() == 0.0
+    r = assembly.rhs(m, rest, ref, c["phys"], dtype=np.float32)
+    assert np.abs(r).max() < 1e-4
