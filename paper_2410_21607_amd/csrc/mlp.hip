@@ -8,8 +8,9 @@
 //   k_mlp_samples : one thread per sample: forward pass, softmax, the
 //                   per-sample back-propagated errors of the three layers and
 //                   the sample's loss, written to the workspace;
-//   k_mlp_grad    : one thread per parameter: the batch sum of its gradient
-//                   in a fixed order (deterministic, accumulated in double);
+//   k_mlp_grad    : the batch sum of every parameter's gradient, 16
+//                   interleaved batch segments per parameter combined in a
+//                   fixed order (deterministic, accumulated in double);
 //   k_adam        : element-wise Adam update.
 #include <cmath>
 
@@ -127,45 +128,55 @@ k_mlp_samples(const float* __restrict__ p, const float* __restrict__ x,
     }
 }
 
-// gradient of every parameter (and, in the extra thread, the mean loss) as
-// a batch sum in sample order
-__global__ void __launch_bounds__(256)
+// gradient of every parameter (and, in the last slot, the mean loss) as a
+// batch sum: a workgroup owns 64 consecutive slots and splits the batch into
+// 16 interleaved segments (b = seg, seg + 16, ...), each summed in sample
+// order in double; the 16 partial sums are then added in segment order, so
+// the result does not depend on scheduling.
+constexpr int GRAD_SLOTS = 64, GRAD_SEGS = 16;
+
+__global__ void __launch_bounds__(GRAD_SLOTS * GRAD_SEGS)
 k_mlp_grad(const float* __restrict__ x, const int32_t* __restrict__ idx, int64_t n,
            int64_t n_rows, const float* __restrict__ work, float* __restrict__ grad,
            float* __restrict__ loss) {
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r > NP) return;
+    __shared__ double part[GRAD_SEGS][GRAD_SLOTS];
+    const int q = threadIdx.x % GRAD_SLOTS, seg = threadIdx.x / GRAD_SLOTS;
+    const int r = blockIdx.x * GRAD_SLOTS + q;
     double s = 0.0;
-    if (r == NP) {
-        for (int64_t b = 0; b < n; ++b) s += work[b * WN + WL];
-        *loss = float(s / double(n));
-        return;
-    }
-    if (r < OB1) {                       // W1[o][i] = sum d1[o] x[i]
+    if (r == NP) {                       // mean loss
+        for (int64_t b = seg; b < n; b += GRAD_SEGS) s += work[b * WN + WL];
+    } else if (r < OB1) {                // W1[o][i] = sum d1[o] x[i]
         const int o = r / NI, i = r % NI;
-        for (int64_t b = 0; b < n; ++b) {
+        for (int64_t b = seg; b < n; b += GRAD_SEGS) {
             const int64_t sm = idx ? min(max(int64_t(idx[b]), int64_t(0)), n_rows - 1) : b;
             s += double(work[b * WN + WD1 + o]) * double(x[sm * NI + i]);
         }
     } else if (r < OW2) {                // b1[o] = sum d1[o]
         const int o = r - OB1;
-        for (int64_t b = 0; b < n; ++b) s += work[b * WN + WD1 + o];
+        for (int64_t b = seg; b < n; b += GRAD_SEGS) s += work[b * WN + WD1 + o];
     } else if (r < OB2) {                // W2[o][h] = sum d2[o] h1[h]
         const int o = (r - OW2) / NH, h = (r - OW2) % NH;
-        for (int64_t b = 0; b < n; ++b)
+        for (int64_t b = seg; b < n; b += GRAD_SEGS)
             s += double(work[b * WN + WD2 + o]) * double(work[b * WN + WH1 + h]);
     } else if (r < OW3) {                // b2[o] = sum d2[o]
         const int o = r - OB2;
-        for (int64_t b = 0; b < n; ++b) s += work[b * WN + WD2 + o];
+        for (int64_t b = seg; b < n; b += GRAD_SEGS) s += work[b * WN + WD2 + o];
     } else if (r < OB3) {                // W3[o][h] = sum d3[o] h2[h]
         const int o = (r - OW3) / NH, h = (r - OW3) % NH;
-        for (int64_t b = 0; b < n; ++b)
+        for (int64_t b = seg; b < n; b += GRAD_SEGS)
             s += double(work[b * WN + WD3 + o]) * double(work[b * WN + WH2 + h]);
-    } else {                             // b3[o] = sum d3[o]
+    } else if (r < NP) {                 // b3[o] = sum d3[o]
         const int o = r - OB3;
-        for (int64_t b = 0; b < n; ++b) s += work[b * WN + WD3 + o];
+        for (int64_t b = seg; b < n; b += GRAD_SEGS) s += work[b * WN + WD3 + o];
     }
-    grad[r] = float(s);
+    part[seg][q] = s;
+    __syncthreads();
+    if (seg == 0 && r <= NP) {
+        double t = 0.0;
+        for (int k = 0; k < GRAD_SEGS; ++k) t += part[k][q];
+        if (r == NP) *loss = float(t / double(n));
+        else grad[r] = float(t);
+    }
 }
 
 __global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
@@ -214,8 +225,8 @@ int mlp_backward(const float* p, const float* x, int64_t n_rows, const int8_t* c
     hipLaunchKernelGGL(sem::k_mlp_samples, dim3(grid_of(n)), dim3(256), 0, s, p, x, cls, idx, n,
                        n_rows, work);
     HIPCHK(hipGetLastError());
-    hipLaunchKernelGGL(sem::k_mlp_grad, dim3((SEM_MLP_NPARAM + 1 + 255) / 256), dim3(256), 0, s, x,
-                       idx, n, n_rows, work, grad, loss);
+    hipLaunchKernelGGL(sem::k_mlp_grad, dim3((SEM_MLP_NPARAM + 1 + sem::GRAD_SLOTS - 1) / sem::GRAD_SLOTS),
+                       dim3(sem::GRAD_SLOTS * sem::GRAD_SEGS), 0, s, x, idx, n, n_rows, work, grad, loss);
     HIPCHK(hipGetLastError());
     return SEM_OK;
 }

@@ -123,7 +123,10 @@ def test_mlp_forward_and_gradient_match_oracle(seed, n, use_idx):
     grad = torch.zeros(mlp.N_PARAM, dtype=torch.float32, device="cuda")
     loss = torch.zeros(1, dtype=torch.float32, device="cuda")
     api.mlp_backward(P, X, Y, I, work, grad, loss)
+    grad2 = torch.zeros_like(grad)
+    api.mlp_backward(P, X, Y, I, work, grad2, loss)
     torch.cuda.synchronize()
+    assert torch.equal(grad, grad2)          # fixed summation order
     L, g = mlp.gradient(p.astype(np.float64), xs.astype(np.float64), ys.astype(np.int64))
     gg = grad.cpu().numpy().astype(np.float64)
     rel = np.linalg.norm(gg - g) / np.linalg.norm(g)
