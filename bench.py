@@ -53,7 +53,7 @@ def cpu_baseline(case, n_stages=1):
     el = time.perf_counter() - t
     return {"value": om.n_dof * n_stages / el, "unit": "DOF-stage/s", "cores": 1,
             "kind": "oracle",
-            "sample": f"{n_stages} SSP-RK3 stage(s) of {WORKLOAD} (full mesh, {om.n_dof} unique "
+            "sample": f"{n_stages} SSP-RK3 stage(s) of {case['name']} (full mesh, {om.n_dof} unique "
                       f"nodes), single-threaded NumPy/SciPy, mesh setup not timed; {el:.1f} s"}
 
 
@@ -66,10 +66,10 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
+def measured_traffic(workload=WORKLOAD):
     """HBM bytes per stage from the committed rocprofv3 counter summary, or
     None when it is missing or was taken on a different kernel source."""
-    path = os.path.join(ROOT, "profiles", f"traffic_{WORKLOAD}.json")
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
@@ -288,6 +288,8 @@ def main():
     ap.add_argument("--steps", type=int, default=300, help="RK stages to time (rounded up to whole RK3 steps)")
     ap.add_argument("--warmup", type=int, default=30)
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
+    ap.add_argument("--workload", default=WORKLOAD,
+                    help="case timed for the main line (default: the 64x64x16 N=4 bench workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
@@ -319,7 +321,7 @@ def main():
     if args.forecaster_only:
         print(json.dumps(forecaster_experiment(dev, args.fc_case, args.fc_seconds)), flush=True)
         return
-    case = cases.get(WORKLOAD)
+    case = cases.get(args.workload)
     mesh = api.Mesh.from_case(case)
     _, _, z = mesh.coords()
     bg = cases.reference_state(case, z)
@@ -360,7 +362,7 @@ def main():
         for _ in range(5):
             torch.mul(src, 1.0, out=dst)
         torch.cuda.synchronize()
-    traffic = measured_traffic()
+    traffic = measured_traffic(args.workload)
     stages = 3 * n_steps
     res = {
         "metric": METRIC,
@@ -375,7 +377,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if prec == api.SEM_FP64 else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": WORKLOAD, "N": case["N"], "elements": int(mesh.info["n_elem"]),
+        "config": {"workload": args.workload, "N": case["N"], "elements": int(mesh.info["n_elem"]),
                    "n_dof": int(n_dof), "local_points": int(mesh.n_local),
                    "step": "one SSP-RK3 stage (timed as HIP-graph replays of whole RK3 steps)",
                    "graph": not args.no_graph, "layers_per_chunk": lpc, "finite": ok},
