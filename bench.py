@@ -354,6 +354,20 @@ def main():
     alg_step = sum(algorithmic_bytes(n_dof, s) for s in range(3))
     achieved = alg_step / durs.mean() / 1e9
     ok = bool(torch.isfinite(st.q).all().item())
+    # achievable streaming bandwidth for context: an elementwise kernel that
+    # reads and writes one state-sized array (HIP events, mean of 20)
+    src = torch.rand(mesh.n_state, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        torch.mul(src, 1.0, out=dst)
+    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    c0.record(stream)
+    for _ in range(20):
+        torch.mul(src, 1.0, out=dst)
+    c1.record(stream)
+    torch.cuda.synchronize()
+    copy_gbs = 2 * src.numel() * 8 * 20 / (c0.elapsed_time(c1) * 1e-3) / 1e9
+    del src, dst
     if args.copy_calibration:
         # an elementwise kernel reading and writing one state-sized array
         # (5 n_dof doubles each way): the reference for HBM counter scaling
@@ -385,6 +399,8 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic,
                      "kernel": "fused stage (column passes + hanging pass), per stage",
+                     "copy_kernel_GBps": copy_gbs,
+                     "frac_of_copy": achieved / copy_gbs,
                      "avg_kernel_ms": float(durs.mean() * 1e3 / 3)},
     }
     if not args.no_extras:
