@@ -282,6 +282,46 @@ def forecaster_experiment(device, case_name="vortex3_64x64x8_n4", sim_seconds=40
     return res
 
 
+def tstar_study(device, sim_seconds=150.0, max_level=3):
+    """Normalised time-to-solution T* = T / T(uniform level 0) of uniform
+    meshes at levels 0..max_level and of speed-refined AMR up to each level
+    (thresholds 7.5, 15, 22.5 m/s per level), same simulated time; maximum
+    wind of each AMR run against the uniform run at its finest level."""
+    import numpy as np
+    import torch
+    from synth import cases
+    out = {"workload": "tstar_64x64x8_n4", "sim_seconds": sim_seconds, "runs": {}}
+    vref, base = {}, None
+    for amr in (False, True):
+        for lv in range(0 if not amr else 1, max_level + 1):
+            c = cases.get("tstar_64x64x8_n4", level=lv, amr=amr)
+            n = int(round(sim_seconds / c["dt"]))
+            n -= n % c["amr"]["interval"]
+            run = adaptive_run(c, device, adapt=amr)
+            run.run(n)
+            torch.cuda.synchronize()
+            v = np.array([b["vmax"] for b in run.log])
+            key = ("amr" if amr else "uniform") + f"_L{lv}"
+            rec = {"dt": c["dt"], "steps": n, "wall_s": run.wall(), "rebuilds": run.n_rebuild,
+                   "mean_n_dof": float(np.mean([b["n_dof"] for b in run.log])),
+                   "n_col_start": int(len(c["columns"])), "vmax_final": float(v[-1])}
+            if not amr:
+                vref[lv] = v
+                if lv == 0:
+                    base = rec["wall_s"]
+            else:
+                rec["vmax_max_rel_dev_vs_uniform_same_level"] = float(np.max(np.abs(v - vref[lv]) / vref[lv]))
+            rec["T_star"] = rec["wall_s"] / base
+            out["runs"][key] = rec
+            print(f"  {key}: {rec['wall_s']:.2f} s, T* {rec['T_star']:.2f}", file=sys.stderr, flush=True)
+            del run
+            torch.cuda.empty_cache()
+    for lv in range(1, max_level + 1):
+        out[f"speedup_amr_over_uniform_L{lv}"] = out["runs"][f"uniform_L{lv}"]["wall_s"] / \
+            out["runs"][f"amr_L{lv}"]["wall_s"]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -298,6 +338,8 @@ def main():
                     help="run the forecaster experiment even with --no-extras")
     ap.add_argument("--forecaster-only", action="store_true",
                     help="run only the forecaster experiment and print its JSON")
+    ap.add_argument("--tstar-only", action="store_true",
+                    help="run only the time-to-solution study (uniform vs AMR by level) and print its JSON")
     ap.add_argument("--fc-case", default="vortex3_64x64x8_n4")
     ap.add_argument("--fc-seconds", type=float, default=405.0,
                     help="simulated seconds of each forecaster-experiment run")
@@ -318,6 +360,9 @@ def main():
     from synth import cases
 
     dev = torch.device("cuda:0")
+    if args.tstar_only:
+        print(json.dumps(tstar_study(dev)), flush=True)
+        return
     if args.forecaster_only:
         print(json.dumps(forecaster_experiment(dev, args.fc_case, args.fc_seconds)), flush=True)
         return

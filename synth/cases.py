@@ -126,6 +126,34 @@ def get(name, **over):
         c["noise"] = dict(amp=0.3, z_top=1e30, seed=seed, kind="modes")
         pred = _vorticity_refiner(c, c["amr"]["thresholds"])
         c["columns"] = columns.refine_where(nb, nb, 400e3, 400e3, 2, pred)
+    elif name.startswith("tstar_64x64x8_n4"):
+        # time-to-solution study: the smooth 40 m/s vortex at rest on the
+        # 400 km domain, refined by wind speed with the paper's thresholds
+        # (7.5 m/s per level); `level` picks the layout: uniform at that
+        # level, or the speed-refined layout up to that level (`amr`)
+        seed = int(over.pop("seed", 0))
+        level = int(over.pop("level", 0))
+        amr = bool(over.pop("amr", False))
+        c = _case(4, 64, 64, 400e3, 400e3, 20e3, 8, columns.uniform(64, 64), v_max=40.0,
+                  r_max=25e3, noise_amp=0.3, seed=seed, dt=0.43, stages=10, name=name)
+        c["vortex"]["profile"] = "smooth"
+        c["noise"] = dict(amp=0.3, z_top=1e30, seed=seed, kind="modes")
+        thr = [7.5, 15.0, 22.5, 30.0][:max(level, 1)]
+        c["amr"] = dict(criterion=0, thresholds=thr, lvl_max=level, interval=100)
+        # stable step of the finest level present (vertical spacing limits levels 0-1)
+        c["dt"] = {0: 0.43, 1: 0.43, 2: 0.27, 3: 0.135}[level]
+        if amr and level > 0:
+            vx = vortex_of(c)
+
+            def pred(x, y, l):
+                if l >= level:
+                    return np.zeros_like(x, dtype=bool)
+                return vx.vt_surface(np.hypot(x, y)) > thr[l]
+            c["columns"] = columns.refine_where(64, 64, 400e3, 400e3, level, pred)
+        elif level > 0:
+            n = 64 << level
+            cols = np.array([(level, x, y) for x in range(n) for y in range(n)])
+            c["columns"] = columns.morton_sort(cols, level)
     else:
         raise KeyError(name)
     for k, v in over.items():
