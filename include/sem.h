@@ -179,14 +179,19 @@ int sem_stage_update(const sem_mesh *mesh, double a, double b, double c,
                      double *d_qout, void *stream);
 
 /* Fused stage: d_qout = a*d_qn + b*d_qs + c*R(d_qs), with R the full
- * right-hand side (scatter, element RHS, assembly, gather, finalize) evaluated
- * in one launch over the columns of every refinement level, which finishes
- * every node owned by a single column in place, followed by a small launch
- * that finishes the nodes shared between columns from their per-column
- * partial sums (fixed summation order: results are deterministic).
- * d_qout must not alias d_qs or d_qn.  Uses the handle's partial buffer, so
- * calls on one handle must not overlap.  Allocates nothing; two kernel nodes
- * when captured in a HIP graph. */
+ * right-hand side (scatter, element RHS, assembly, gather, finalize, lid rule)
+ * evaluated without storing element-local data.  Columns are coloured so that
+ * columns of one colour share no node; one launch per colour covers the
+ * columns of every refinement level of that colour (a workgroup marches up
+ * one column in chunks of stacked elements).  The first colour touching a
+ * node writes a*q^n + b*q_s + c*M^-1*(its contribution); later colours add
+ * their contributions (plain read-modify-write; the launches order them, so
+ * results are deterministic and bit-identical from run to run).  Hanging
+ * points collect their contributions in the handle's buffer, which one more
+ * launch adds to the coarse face nodes (Z^T).  d_qout must not alias d_qs or
+ * d_qn.  Calls on one handle must not overlap.  Allocates nothing; the kernel
+ * nodes (colours + 1 on meshes with hanging points) can be captured in a HIP
+ * graph. */
 int sem_stage(const sem_mesh *mesh, double a, double b, double c,
               const double *d_qn, const double *d_qs, double *d_qout,
               int precision, void *stream);
