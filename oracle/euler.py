@@ -93,4 +93,57 @@ def element_rhs(mesh, qL, rho0, theta0, dtheta0dz, phys, dtype=np.float64):
     R[2] = -(u * vx + v * vy + w * vz) - py / rho - f * u
     R[3] = -(u * wx + v * wy + w * wz) - pz / rho - (rho_p / rho) * g
     R[4] = -(u * tx + v * ty + w * tz) - w * dtheta0dz
-    return R.astype(np.float64)
+    R = R.astype(np.float64)
+    if phys.get("Cs", 0.0) > 0.0 or phys.get("sponge_gamma", 0.0) > 0.0:
+        R += dissipation(mesh, np.asarray(qL, dtype=np.float64), phys)
+    return R
+
+
+def sponge_profile(z, z_top, gamma, depth):
+    """Rayleigh absorbing layer of the paper's model setup (Section 5):
+    R(z) = min(1, max(0, gamma sin^2(pi/2 (1 - (z_top - z)/depth)))) inside the
+    top layer z >= z_top - depth, zero below it (the printed formula is
+    garbled; below the layer its sine would not vanish)."""
+    z = np.asarray(z, dtype=np.float64)
+    arg = 0.5 * np.pi * (1.0 - (z_top - z) / depth)
+    r = np.minimum(1.0, np.maximum(0.0, gamma * np.sin(arg) ** 2))
+    return np.where(z >= z_top - depth, r, 0.0)
+
+
+def dissipation(mesh, qL, phys):
+    """Sub-grid and absorbing-layer tendencies (Section 5 model setup), FP64.
+
+    Smagorinsky-Lilly in the horizontal: the momentum equations gain the
+    horizontal divergence of 2 nu_t S, S = (grad u + grad u^T)/2 from the
+    element-local derivatives, nu_t = (C_s Delta)^2 sqrt(2 S:S) with Delta the
+    mean horizontal node spacing of the element, (dx + dy) / (2N):
+        R_u += d/dx(2 nu S_xx) + d/dy(2 nu S_xy)
+        R_v += d/dx(2 nu S_yx) + d/dy(2 nu S_yy)
+        R_w += d/dx(2 nu S_zx) + d/dy(2 nu S_zy)
+    (strong form inside each element, like every other term).  Rayleigh
+    layer: every perturbation field gains -R(z) q'.
+    phys keys: Cs (0 disables), sponge_gamma [1/s] (0 disables),
+    sponge_depth [m]; the layer sits under the domain top."""
+    D = derivative_matrix(mesh.N)
+    d = lambda f: local_derivatives(D, f, mesh.e_dx, mesh.e_dy, mesh.e_dz)
+    out = np.zeros_like(qL)
+    cs = phys.get("Cs", 0.0)
+    if cs > 0.0:
+        u, v, w = qL[1], qL[2], qL[3]
+        ux, uy, uz = d(u)
+        vx, vy, vz = d(v)
+        wx, wy, wz = d(w)
+        sxx, syy, szz = ux, vy, wz
+        sxy, sxz, syz = 0.5 * (uy + vx), 0.5 * (uz + wx), 0.5 * (vz + wy)
+        ss = sxx**2 + syy**2 + szz**2 + 2.0 * (sxy**2 + sxz**2 + syz**2)
+        delta = (mesh.e_dx + mesh.e_dy) / (2.0 * mesh.N)
+        nu = (cs * delta)[:, None, None, None] ** 2 * np.sqrt(2.0 * ss)
+        txx, txy, tyy, txz, tyz = (2.0 * nu * a for a in (sxx, sxy, syy, sxz, syz))
+        out[1] += d(txx)[0] + d(txy)[1]
+        out[2] += d(txy)[0] + d(tyy)[1]
+        out[3] += d(txz)[0] + d(tyz)[1]
+    gam = phys.get("sponge_gamma", 0.0)
+    if gam > 0.0:
+        rz = sponge_profile(mesh.zl, mesh.z_edges[-1], gam, phys.get("sponge_depth", 4000.0))
+        out -= rz[None] * qL
+    return out
