@@ -145,6 +145,24 @@ int sem_mesh_coords(const sem_mesh *mesh, double *h_hxy, double *h_hhxy, double 
 int sem_mesh_set_reference(sem_mesh *mesh, const double *h_rho0,
                            const double *h_theta0, const double *h_dtheta0dz);
 
+/* Optional dissipation of the paper's model setup (Section 5), added to the
+ * right-hand side of sem_rhs and sem_stage when enabled (all zero = off):
+ *   horizontal Smagorinsky-Lilly: the momentum equations gain the horizontal
+ *     divergence of 2 nu_t S, S = (grad u + grad u^T)/2 from element-local
+ *     derivatives, nu_t = (Cs Delta)^2 sqrt(2 S:S), Delta = (dx + dy)/(2N) the
+ *     element's mean horizontal node spacing:
+ *       R_u += d/dx(2 nu S_xx) + d/dy(2 nu S_xy)   (v: S_yx, S_yy; w: S_zx, S_zy)
+ *   Rayleigh absorbing layer under the domain top: every perturbation field
+ *     gains -R(z) q', R(z) = min(1, max(0, sponge_gamma sin^2(pi/2 (1 - (z_top
+ *     - z)/sponge_depth)))) for z >= z_top - sponge_depth, zero below.
+ * Both are evaluated in FP64 element by element (strong form, like the other
+ * terms) and assembled with the same direct stiffness summation.  In
+ * sem_stage they run as a pre-pass whose assembled tendency the column pass
+ * adds.  Enabling allocates the pre-pass buffers once (5 element-local and 2
+ * state arrays); compute calls never allocate.  Synchronises the device. */
+int sem_mesh_set_dissipation(sem_mesh *mesh, double Cs, double sponge_gamma,
+                             double sponge_depth);
+
 /* Modified-DSS interpolation across nonconforming faces (Section 3.1).
  * SEM_SCATTER: d_dst = hv[F][n_hh][ldz] is overwritten with Z_h d_src, the
  *              values at hanging points interpolated from d_src = q[F][n_h][ldz].

@@ -198,6 +198,12 @@ class Mesh:
         native.call("sem_mesh_set_reference", self.handle,
                     *[a.ctypes.data_as(native.c_dp) for a in arrs])
 
+    def set_dissipation(self, Cs=0.0, sponge_gamma=0.0, sponge_depth=4000.0):
+        """Enable (or, with zeros, disable) the horizontal Smagorinsky-Lilly
+        and absorbing-layer terms; see sem_mesh_set_dissipation."""
+        native.call("sem_mesh_set_dissipation", self.handle, float(Cs), float(sponge_gamma),
+                    float(sponge_depth))
+
     def state(self, device="cuda"):
         """A zeroed state tensor (padding stays zero under every compute call)."""
         return torch.zeros(self.n_state, dtype=torch.float64, device=device)

@@ -26,6 +26,12 @@ struct DevMesh {
     const double *rho0, *theta0, *dth0, *p0;   // reference state per kz
     const double *inv_rho0, *inv_theta0;       // their reciprocals per kz
     double binom[11];   // binom[n] = C(gamma, n): Taylor coefficients of (1+x)^gamma
+    // optional dissipation (sem_mesh_set_dissipation): Smagorinsky constant
+    // (0 = off), absorbing-layer rate per kz (null = off), and the assembled
+    // dissipation tendency per unique node that the fused stage adds (null = none)
+    double cs;
+    const double* sponge;
+    const double* rx;
 };
 
 }  // namespace sem

@@ -38,12 +38,17 @@ struct sem_mesh {
     bool have_ref = false;
     sem::FusedPlan fused;
     double* feat_aux = nullptr;   // 2 doubles per element (amr_features)
+    // dissipation pre-pass of the fused stage (allocated when enabled)
+    double *diss_rE = nullptr, *diss_acc = nullptr, *diss_c = nullptr, *diss_r = nullptr;
+    double* diss_sponge = nullptr;
     double* wind_part = nullptr;  // 256 partial maxima (sem_max_wind)
     const double* d_hxy = nullptr; // x, y of every unique horizontal node
     int64_t ws_bytes = 0;
     ~sem_mesh() {
         sem::fused_plan_free(fused);
         if (feat_aux) (void)hipFree(feat_aux);
+        for (double* p : {diss_rE, diss_acc, diss_c, diss_r, diss_sponge})
+            if (p) (void)hipFree(p);
         if (wind_part) (void)hipFree(wind_part);
         for (void* p : allocs) (void)hipFree(p);
     }

@@ -155,6 +155,106 @@ k_rhs(DevMesh m, const double* __restrict__ q, const double* __restrict__ hv,
     for (int fld = 0; fld < NF; ++fld) rE[fld * es + int64_t(e) * NP3 + t] = mass * double(R[fld]);
 }
 
+// Sub-grid and absorbing-layer tendencies of one element, times the lumped
+// mass (the paper's model setup, Section 5): horizontal Smagorinsky-Lilly,
+//   R_u += d/dx(2 nu S_xx) + d/dy(2 nu S_xy), and likewise for v (S_yx, S_yy)
+//   and w (S_zx, S_zy), nu = (C_s Delta)^2 sqrt(2 S:S), Delta = (dx+dy)/(2N),
+// with S from the element-local velocity derivatives; and the Rayleigh layer,
+// R_f -= R(kz) q'_f for every field.  accumulate = true adds to rE (the
+// unfused element right-hand side), false overwrites it.
+template <int NP>
+__global__ void __launch_bounds__(((NP * NP * NP + 63) / 64) * 64)
+k_dissip(DevMesh m, const double* __restrict__ q, const double* __restrict__ hv,
+         double* __restrict__ rE, bool accumulate) {
+    constexpr int NP2 = NP * NP, NP3 = NP2 * NP;
+    constexpr int N = NP - 1;
+    __shared__ double sv[3][NP3];       // u, v, w
+    __shared__ double st[5][NP3];       // 2 nu (S_xx, S_xy, S_yy, S_xz, S_yz)
+    __shared__ double sD[NP2];
+    const int e = blockIdx.x;
+    const int c = e / m.n_z, layer = e - c * m.n_z;
+    const int t = threadIdx.x;
+    if (t < NP2) sD[t] = m.D[t];
+    const int i = t % NP, j = (t / NP) % NP, k = t / NP2;
+    const int kz = layer * N + k;
+    const int64_t fs = int64_t(m.n_h) * m.ldz, fsh = int64_t(m.n_hh) * m.ldz;
+    double x[NF] = {0, 0, 0, 0, 0};
+    if (t < NP3) {
+        const int g = m.gmap[c * NP2 + i + NP * j];
+        if (g >= 0) {
+#pragma unroll
+            for (int f = 0; f < NF; ++f) x[f] = q[f * fs + int64_t(g) * m.ldz + kz];
+        } else {
+#pragma unroll
+            for (int f = 0; f < NF; ++f) x[f] = hv[f * fsh + int64_t(-g - 1) * m.ldz + kz];
+        }
+        sv[0][t] = x[1];
+        sv[1][t] = x[2];
+        sv[2][t] = x[3];
+    }
+    __syncthreads();
+    const double sx = 2.0 / m.col_dx[c], sy = 2.0 / m.col_dy[c], sz = 2.0 / m.dz[layer];
+    double R[NF] = {0, 0, 0, 0, 0};
+    const bool sgs = m.cs > 0.0;
+    if (sgs && t < NP3) {
+        double g3[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};   // g3[a][b] = d(u_a)/d(x_b)
+        for (int mm = 0; mm < NP; ++mm) {
+            const double dxm = sD[i * NP + mm], dym = sD[j * NP + mm], dzm = sD[k * NP + mm];
+            const int ox = mm + NP * (j + NP * k), oy = i + NP * (mm + NP * k), oz = i + NP * (j + NP * mm);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                g3[a][0] += dxm * sv[a][ox];
+                g3[a][1] += dym * sv[a][oy];
+                g3[a][2] += dzm * sv[a][oz];
+            }
+        }
+#pragma unroll
+        for (int a = 0; a < 3; ++a) { g3[a][0] *= sx; g3[a][1] *= sy; g3[a][2] *= sz; }
+        const double sxx = g3[0][0], syy = g3[1][1], szz = g3[2][2];
+        const double sxy = 0.5 * (g3[0][1] + g3[1][0]);
+        const double sxz = 0.5 * (g3[0][2] + g3[2][0]);
+        const double syz = 0.5 * (g3[1][2] + g3[2][1]);
+        const double ss = sxx * sxx + syy * syy + szz * szz + 2.0 * (sxy * sxy + sxz * sxz + syz * syz);
+        const double delta = (m.col_dx[c] + m.col_dy[c]) / (2.0 * N);
+        const double cd = m.cs * delta;
+        const double two_nu = 2.0 * cd * cd * sqrt(2.0 * ss);
+        st[0][t] = two_nu * sxx;
+        st[1][t] = two_nu * sxy;
+        st[2][t] = two_nu * syy;
+        st[3][t] = two_nu * sxz;
+        st[4][t] = two_nu * syz;
+    }
+    __syncthreads();
+    if (t >= NP3) return;
+    if (sgs) {
+        double dx_[5] = {0, 0, 0, 0, 0}, dy_[5] = {0, 0, 0, 0, 0};
+        for (int mm = 0; mm < NP; ++mm) {
+            const double dxm = sD[i * NP + mm], dym = sD[j * NP + mm];
+            const int ox = mm + NP * (j + NP * k), oy = i + NP * (mm + NP * k);
+#pragma unroll
+            for (int a = 0; a < 5; ++a) {
+                dx_[a] += dxm * st[a][ox];
+                dy_[a] += dym * st[a][oy];
+            }
+        }
+        R[1] = dx_[0] * sx + dy_[1] * sy;
+        R[2] = dx_[1] * sx + dy_[2] * sy;
+        R[3] = dx_[3] * sx + dy_[4] * sy;
+    }
+    if (m.sponge) {
+        const double rz = m.sponge[kz];
+#pragma unroll
+        for (int f = 0; f < NF; ++f) R[f] -= rz * x[f];
+    }
+    const double mass = m.w[i] * m.w[j] * m.w[k] * 0.125 * m.col_dx[c] * m.col_dy[c] * m.dz[layer];
+    const int64_t es = int64_t(m.n_col) * m.n_z * NP3;
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+        const int64_t o = f * es + int64_t(e) * NP3 + t;
+        rE[o] = (accumulate ? rE[o] : 0.0) + mass * R[f];
+    }
+}
+
 // sum of element contributions at the local copies of (slot-list, kz)
 __device__ __forceinline__ void sum_local(const DevMesh& m, const double* __restrict__ rE,
                                           const int* __restrict__ slots, int s0, int s1, int kz,
@@ -352,11 +452,63 @@ int check_mesh(const sem_mesh* M) {
 
 }  // namespace
 
+// m * (sub-grid + absorbing-layer tendency) of every element into rE
+// (added to what is there when accumulate is true)
+int launch_dissip(const sem_mesh* M, const double* q, const double* hv, double* rE, bool accumulate,
+                  hipStream_t s) {
+    const DevMesh& d = M->d;
+    const int nb = d.n_col * d.n_z;
+    switch (d.N) {
+#define CASE(NN)                                                                                  \
+    case NN:                                                                                      \
+        hipLaunchKernelGGL((sem::k_dissip<NN + 1>), dim3(nb),                                     \
+                           dim3((((NN + 1) * (NN + 1) * (NN + 1) + 63) / 64) * 64), 0, s, d, q, hv, \
+                           rE, accumulate);                                                       \
+        break;
+        CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
+#undef CASE
+        default: return fail(SEM_ERR_N, "unsupported N");
+    }
+    HIPCHK(hipGetLastError());
+    return SEM_OK;
+}
+
+bool dissipation_on(const sem_mesh* M) { return M->d.cs > 0.0 || M->d.sponge != nullptr; }
+
 static int sem_launch_rhs(const sem_mesh* M, const double* q, const double* hv, double* rE, int prec,
                    hipStream_t s) {
-    if (prec == SEM_FP64) return launch_rhs_t<double>(M, q, hv, rE, s);
-    if (prec == SEM_FP32) return launch_rhs_t<float>(M, q, hv, rE, s);
-    return fail(SEM_ERR_ARG, "precision must be SEM_FP64 or SEM_FP32");
+    int rc;
+    if (prec == SEM_FP64) rc = launch_rhs_t<double>(M, q, hv, rE, s);
+    else if (prec == SEM_FP32) rc = launch_rhs_t<float>(M, q, hv, rE, s);
+    else return fail(SEM_ERR_ARG, "precision must be SEM_FP64 or SEM_FP32");
+    if (rc == SEM_OK && dissipation_on(M)) rc = launch_dissip(M, q, hv, rE, true, s);
+    return rc;
+}
+
+// dissipation tendency of q per unique node (M^-1 Z^T m R_dissip, lid rule)
+// into the handle's buffer, read by the fused stage
+int dissip_prepass(const sem_mesh* M, const double* q, hipStream_t s) {
+    const DevMesh& d = M->d;
+    const double* hv = nullptr;
+    if (d.n_hh > 0) {
+        hipLaunchKernelGGL(sem::k_nc_scatter, dim3(grid_for(int64_t(d.n_hh) * d.nzn)), dim3(256), 0, s, d, q,
+                           M->diss_c);
+        hv = M->diss_c;
+    }
+    int rc = launch_dissip(M, q, hv, M->diss_rE, false, s);
+    if (rc != SEM_OK) return rc;
+    hipLaunchKernelGGL(sem::k_assemble, dim3(grid_for(int64_t(d.n_h) * d.nzn)), dim3(256), 0, s, d, M->diss_rE,
+                       M->diss_acc);
+    if (d.n_hh > 0) {
+        hipLaunchKernelGGL(sem::k_assemble_hang, dim3(grid_for(int64_t(d.n_hh) * d.nzn)), dim3(256), 0, s, d,
+                           M->diss_rE, M->diss_c);
+        hipLaunchKernelGGL(sem::k_nc_gather, dim3(grid_for(int64_t(d.n_hT) * d.nzn)), dim3(256), 0, s, d,
+                           M->diss_c, M->diss_acc);
+    }
+    hipLaunchKernelGGL(sem::k_finalize, dim3(grid_for(int64_t(d.n_h) * d.nzn)), dim3(256), 0, s, d, M->diss_acc,
+                       M->diss_r);
+    HIPCHK(hipGetLastError());
+    return SEM_OK;
 }
 
 // ====================================================================== C ABI
@@ -553,8 +705,52 @@ int sem_stage(const sem_mesh* M, double a, double b, double c, const double* qn,
     if (!qn || !qs || !qout) return fail(SEM_ERR_ARG, "null array");
     if (qout == qs || qout == qn) return fail(SEM_ERR_ARG, "qout must not alias qs or qn");
     if (prec != SEM_FP64 && prec != SEM_FP32) return fail(SEM_ERR_ARG, "bad precision");
+    if (dissipation_on(M) && (rc = dissip_prepass(M, qs, (hipStream_t)stream)) != SEM_OK) return rc;
     rc = sem::fused_stage_launch(M->d, M->fused, a, b, c, qn, qs, qout, prec, (hipStream_t)stream);
     if (rc != SEM_OK) return fail(rc, "fused stage launch failed");
+    return SEM_OK;
+}
+
+int sem_mesh_set_dissipation(sem_mesh* M, double cs, double sponge_gamma, double sponge_depth) {
+    if (!M) return fail(SEM_ERR_ARG, "null mesh");
+    if (!(cs >= 0.0) || !(sponge_gamma >= 0.0) || (sponge_gamma > 0.0 && !(sponge_depth > 0.0)))
+        return fail(SEM_ERR_ARG, "need Cs >= 0, sponge_gamma >= 0 and sponge_depth > 0");
+    const sem::HostMesh& H = M->host;
+    DevMesh& d = M->d;
+    HIPCHK(hipDeviceSynchronize());
+    if (cs == 0.0 && sponge_gamma == 0.0) {
+        d.cs = 0.0;
+        d.sponge = nullptr;
+        d.rx = nullptr;
+        return SEM_OK;
+    }
+    const int64_t nloc = int64_t(H.n_col) * H.n_z * H.np1 * H.np1 * H.np1;
+    const int64_t nst = int64_t(NF) * H.n_h * H.ldz, nhs = int64_t(NF) * H.n_hh * H.ldz;
+    if (!M->diss_rE) {
+        HIPCHK(hipMalloc(&M->diss_rE, sizeof(double) * NF * nloc));
+        HIPCHK(hipMalloc(&M->diss_acc, sizeof(double) * nst));
+        HIPCHK(hipMalloc(&M->diss_r, sizeof(double) * nst));
+        HIPCHK(hipMalloc(&M->diss_c, sizeof(double) * std::max<int64_t>(nhs, 1)));
+        HIPCHK(hipMalloc(&M->diss_sponge, sizeof(double) * H.nzn));
+        // the row padding of the tendency stays zero (finalize writes kz < nzn only)
+        HIPCHK(hipMemset(M->diss_r, 0, sizeof(double) * nst));
+        M->ws_bytes += int64_t(sizeof(double)) * (NF * nloc + 2 * nst + std::max<int64_t>(nhs, 1) + H.nzn);
+    }
+    // absorbing layer per vertical node: min(1, max(0, gamma sin^2(pi/2 (1 - (z_top - z)/depth))))
+    // inside z >= z_top - depth, zero below
+    std::vector<double> sp(H.nzn, 0.0);
+    const double ztop = H.z_edges.back();
+    for (int kz = 0; kz < H.nzn; ++kz) {
+        const double z = H.zn[kz];
+        if (sponge_gamma > 0.0 && z >= ztop - sponge_depth) {
+            const double sn = std::sin(0.5 * M_PI * (1.0 - (ztop - z) / sponge_depth));
+            sp[kz] = std::min(1.0, std::max(0.0, sponge_gamma * sn * sn));
+        }
+    }
+    HIPCHK(hipMemcpy(M->diss_sponge, sp.data(), sizeof(double) * H.nzn, hipMemcpyHostToDevice));
+    d.cs = cs;
+    d.sponge = sponge_gamma > 0.0 ? M->diss_sponge : nullptr;
+    d.rx = M->diss_r;
     return SEM_OK;
 }
 

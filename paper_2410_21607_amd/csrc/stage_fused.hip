@@ -269,10 +269,17 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
                         for (int f = 0; f < NF; ++f) base[f] = bp[f * fs + o];
                     }
                     if (first) {
+                        // the dissipation pre-pass (if any) is already assembled:
+                        // the first contributor adds it once
+                        double rx[NF] = {0, 0, 0, 0, 0};
+                        if (m.rx) {
+#pragma unroll
+                            for (int fl = 0; fl < NF; ++fl) rx[fl] = c * m.rx[fl * fs + o];
+                        }
 #pragma unroll
                         for (int fl = 0; fl < NF; ++fl) {
                             const double tend = (fl == 3 && lid) ? 0.0 : mi * acc[fl];
-                            qo[fl * fs + o] = a * base[fl] + b * qv[fl] + tend;
+                            qo[fl * fs + o] = a * base[fl] + b * qv[fl] + tend + rx[fl];
                         }
                     } else {
 #pragma unroll
