@@ -328,6 +328,9 @@ def main():
     ap.add_argument("--steps", type=int, default=300, help="RK stages to time (rounded up to whole RK3 steps)")
     ap.add_argument("--warmup", type=int, default=30)
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
+    ap.add_argument("--dissipation", default="",
+                    help="Cs,sponge_gamma,sponge_depth: time the stage with the sub-grid and "
+                         "absorbing-layer terms on (default off, the inviscid stage)")
     ap.add_argument("--workload", default=WORKLOAD,
                     help="case timed for the main line (default: the 64x64x16 N=4 bench workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -373,6 +376,8 @@ def main():
     mesh.set_reference(bg["rho0"], bg["theta0"], bg["dtheta0dz"])
     q0 = mesh.unpack(cases.initial_state(case, mesh.node_xyz()), device=dev)
     prec = api.SEM_FP64 if args.precision == "fp64" else api.SEM_FP32
+    if args.dissipation:
+        mesh.set_dissipation(*(float(x) for x in args.dissipation.split(",")))
     n_dof = mesh.n_dof
     scratch = torch.empty_like(q0)
     lpc, tune_ms = api.sem_stage_autotune(mesh, q0, q0.clone(), scratch, prec, reps=5)
@@ -439,7 +444,8 @@ def main():
         "config": {"workload": args.workload, "N": case["N"], "elements": int(mesh.info["n_elem"]),
                    "n_dof": int(n_dof), "local_points": int(mesh.n_local),
                    "step": "one SSP-RK3 stage (timed as HIP-graph replays of whole RK3 steps)",
-                   "graph": not args.no_graph, "layers_per_chunk": lpc, "finite": ok},
+                   "graph": not args.no_graph, "layers_per_chunk": lpc, "finite": ok,
+                   "dissipation": args.dissipation or "off"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic,

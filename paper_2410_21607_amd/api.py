@@ -102,9 +102,12 @@ class Mesh:
         return cls(*_case_args(case))
 
     def with_columns(self, columns):
-        """A new mesh with the same order, domain, vertical layers and
-        physical constants over another column layout."""
-        return Mesh(columns=columns, **self.params)
+        """A new mesh with the same order, domain, vertical layers, physical
+        constants and dissipation settings over another column layout."""
+        new = Mesh(columns=columns, **self.params)
+        if getattr(self, "dissipation", None):
+            new.set_dissipation(*self.dissipation)
+        return new
 
     def __del__(self):
         h = getattr(self, "handle", None)
@@ -203,6 +206,8 @@ class Mesh:
         and absorbing-layer terms; see sem_mesh_set_dissipation."""
         native.call("sem_mesh_set_dissipation", self.handle, float(Cs), float(sponge_gamma),
                     float(sponge_depth))
+        on = Cs > 0.0 or sponge_gamma > 0.0
+        self.dissipation = (float(Cs), float(sponge_gamma), float(sponge_depth)) if on else None
 
     def state(self, device="cuda"):
         """A zeroed state tensor (padding stays zero under every compute call)."""
