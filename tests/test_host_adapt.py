@@ -161,3 +161,27 @@ def test_forecast_labels_match_oracle(seed):
     dem2 = rng.integers(0, 4, size=len(at) * 3).astype(np.int8)
     np.testing.assert_array_equal(api.sem_forecast_labels(p, later, at, dem2),
                                   forecast.labels(later, at, dem2, 3))
+
+
+def test_transfer_plan_rejects_unrelated_layouts():
+    """A column more than one level away from every old column, or meshes
+    with different orders, are rejected before any work."""
+    _lib()
+    from paper_2410_21607_amd import api
+    p = params()
+    a = sc.uniform(4, 4)
+    b = np.array([(2, x, y) for x in range(16) for y in range(16)])   # two levels finer
+    with pytest.raises(native.SemError):
+        api.sem_transfer_plan(p, a, b)
+
+
+def test_forecast_labels_reject_mismatched_layouts():
+    _lib()
+    from paper_2410_21607_amd import api
+    p = params(n_z=2)
+    a = sc.uniform(4, 4)
+    with pytest.raises(ValueError):
+        api.sem_forecast_labels(p, a, a, np.zeros(3, np.int8))     # wrong dem size
+    q = dict(p, nx0=5)
+    with pytest.raises(native.SemError):
+        api.sem_forecast_labels(q, sc.uniform(5, 4), a, np.zeros(len(a) * 2, np.int8))
