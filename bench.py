@@ -201,7 +201,7 @@ def _summary(run, ref_vmax=None):
 
 
 def forecaster_experiment(device, case_name="vortex3_64x64x8_n4", sim_seconds=405.0,
-                          train_seeds=(0, 1, 2, 3, 4), eval_seed=5, horizon=5, n_samples=200000,
+                          train_seeds=(0, 1, 2, 3, 4), eval_seeds=(5, 6, 7), horizon=5, n_samples=200000,
                           epochs=20):
     """Plain-criterion AMR vs forecaster-driven AMR vs the uniform finest mesh
     on a translating vortex: wall time and maximum-wind deviation."""
@@ -243,42 +243,56 @@ def forecaster_experiment(device, case_name="vortex3_64x64x8_n4", sim_seconds=40
                        "collect_s": t1 - t0,
                        "accuracy_all_samples": float(np.mean(fc.predict(X) == Y))}
     del X, Y, Xs, Ys
-    # 2. evaluation on an unseen seed
-    ev = cases.get(case_name, seed=eval_seed)
-    lm = ev["amr"]["lvl_max"]
-    fine = np.array([(lm, x, y) for x in range(ev["nx0"] << lm) for y in range(ev["ny0"] << lm)])
-    uni = adaptive_run(ev, device, adapt=False, columns=sc.morton_sort(fine, lm))
-    uni.run(n_steps)
-    ref_v = np.array([b["vmax"] for b in uni.log])
-    res["uniform_finest"] = _summary(uni)
-    del uni
-    torch.cuda.empty_cache()
-    plain = adaptive_run(ev, device)
-    plain.run(n_steps)
-    res["plain_amr"] = _summary(plain, ref_v)
-    del plain
-    torch.cuda.empty_cache()
-    # ablation: the same rebuild schedule without the network
-    sparse = adaptive_run(ev, device, rebuild_every=horizon)
-    sparse.run(n_steps)
-    res["plain_amr_sparse_rebuilds"] = _summary(sparse, ref_v)
-    del sparse
-    torch.cuda.empty_cache()
-    rec = forecast.Recorder()
-    fr = adaptive_run(ev, device, forecaster=fc, rebuild_every=horizon)
-    fr.run(n_steps)
-    res["forecaster_amr"] = _summary(fr, ref_v)
-    del fr
-    # held-out skill: the eval seed's plain run, features at t vs classes at t + horizon
-    chk = adaptive_run(ev, device, recorder=rec)
-    chk.run(n_steps)
-    Xe, Ye = rec.samples(horizon)
-    res["heldout_scores"] = forecast.class_scores(fc.predict(Xe), Ye) if Ye.size else None
-    p, f, u = res["plain_amr"], res["forecaster_amr"], res["uniform_finest"]
-    res["speedup_forecaster_over_plain"] = p["wall_s"] / f["wall_s"]
-    res["speedup_plain_amr_over_uniform"] = u["wall_s"] / p["wall_s"]
-    res["speedup_forecaster_amr_over_uniform"] = u["wall_s"] / f["wall_s"]
-    res["vmax_dev_difference"] = f["vmax_max_rel_dev_vs_uniform"] - p["vmax_max_rel_dev_vs_uniform"]
+    # 2. evaluation on unseen seeds
+    per_seed = []
+    for k, es in enumerate(eval_seeds):
+        ev = cases.get(case_name, seed=es)
+        lm = ev["amr"]["lvl_max"]
+        fine = np.array([(lm, x, y) for x in range(ev["nx0"] << lm) for y in range(ev["ny0"] << lm)])
+        uni = adaptive_run(ev, device, adapt=False, columns=sc.morton_sort(fine, lm))
+        uni.run(n_steps)
+        ref_v = np.array([b["vmax"] for b in uni.log])
+        r = {"seed": es, "uniform_finest": _summary(uni)}
+        del uni
+        torch.cuda.empty_cache()
+        for key, kw in (("plain_amr", {}), ("plain_amr_sparse_rebuilds", {"rebuild_every": horizon}),
+                        ("forecaster_amr", {"forecaster": fc, "rebuild_every": horizon})):
+            run = adaptive_run(ev, device, **kw)
+            run.run(n_steps)
+            r[key] = _summary(run, ref_v)
+            del run
+            torch.cuda.empty_cache()
+        if k == 0:
+            # held-out skill: the seed's plain run, features at t vs classes at t + horizon
+            rec = forecast.Recorder()
+            chk = adaptive_run(ev, device, recorder=rec)
+            chk.run(n_steps)
+            Xe, Ye = rec.samples(horizon)
+            res["heldout_scores"] = forecast.class_scores(fc.predict(Xe), Ye) if Ye.size else None
+            del chk, rec
+        p, f, u = r["plain_amr"], r["forecaster_amr"], r["uniform_finest"]
+        r["speedup_forecaster_over_plain"] = p["wall_s"] / f["wall_s"]
+        r["speedup_plain_amr_over_uniform"] = u["wall_s"] / p["wall_s"]
+        r["speedup_forecaster_amr_over_uniform"] = u["wall_s"] / f["wall_s"]
+        per_seed.append(r)
+        print(f"  eval seed {es}: forecaster/plain {r['speedup_forecaster_over_plain']:.3f}", file=sys.stderr,
+              flush=True)
+    res["eval"] = per_seed
+    agg = lambda key, sub: [r[key][sub] for r in per_seed]
+    for key in ("plain_amr", "plain_amr_sparse_rebuilds", "forecaster_amr", "uniform_finest"):
+        res[key] = {"wall_s_mean": float(np.mean(agg(key, "wall_s"))),
+                    "rebuilds_mean": float(np.mean(agg(key, "rebuilds"))),
+                    "mean_n_dof": float(np.mean(agg(key, "mean_n_dof"))),
+                    "mean_split_flag_fraction": float(np.mean(agg(key, "mean_split_flag_fraction")))}
+        if key != "uniform_finest":
+            res[key]["vmax_max_rel_dev_vs_uniform"] = float(np.max(agg(key, "vmax_max_rel_dev_vs_uniform")))
+    for k2 in ("speedup_forecaster_over_plain", "speedup_plain_amr_over_uniform",
+               "speedup_forecaster_amr_over_uniform"):
+        v = [r[k2] for r in per_seed]
+        res[k2] = float(np.mean(v))
+        res[k2 + "_min"] = float(np.min(v))
+    res["vmax_dev_difference"] = res["forecaster_amr"]["vmax_max_rel_dev_vs_uniform"] - \
+        res["plain_amr"]["vmax_max_rel_dev_vs_uniform"]
     return res
 
 
