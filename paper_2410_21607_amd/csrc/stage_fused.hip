@@ -52,7 +52,16 @@ constexpr int wg_threads() {
 // (1+x)^gamma - 1 for the ideal-gas pressure ratio.  For |x| <= 1/64 the
 // Taylor polynomial sum_{n=1..10} C(gamma, n) x^n is used (the first neglected
 // term is below 2^-66 |gamma x|, far under one ulp); otherwise
-// expm1(gamma log1p(x)).
+// expm1(gamma log1p(x)).  That general branch is kept out of line: inlined,
+// the compiler hoists its polynomial constants out of the chunk loop, where
+// they hold about 30 registers for the whole kernel.
+__device__ __noinline__ double pow1p_minus1_far(double x, double gamma) {
+    return expm1(gamma * log1p(x));
+}
+__device__ __noinline__ float pow1p_minus1_far(float x, float gamma) {
+    return expm1f(gamma * log1pf(x));
+}
+
 template <typename T>
 __device__ __forceinline__ T pow1p_minus1(const DevMesh& m, T x) {
     if (fabs(x) <= T(1.0 / 64.0)) {
@@ -61,22 +70,14 @@ __device__ __forceinline__ T pow1p_minus1(const DevMesh& m, T x) {
         for (int n = 9; n >= 1; --n) s = s * x + T(m.binom[n]);
         return s * x;
     }
-    if constexpr (sizeof(T) == 8) return expm1(m.gamma * log1p(x));
-    else return expm1f(float(m.gamma) * log1pf(x));
-}
-
-// p' = p0 ((rho theta)/(rho0 theta0))^gamma - p0 with x = a + b + a b,
-// a = rho'/rho0, b = theta'/theta0 (no cancellation against p0)
-template <typename T>
-__device__ __forceinline__ T pressure_perturbation(const DevMesh& m, int kz, double rp, double tp) {
-    const T ra = T(rp * m.inv_rho0[kz]), tb = T(tp * m.inv_theta0[kz]);
-    return T(m.p0[kz]) * pow1p_minus1<T>(m, ra + tb + ra * tb);
+    return pow1p_minus1_far(x, T(m.gamma));
 }
 
 // At least four waves per SIMD: two workgroups share a CU, so that one can
-// compute while the other waits on memory.  The update base is loaded only
-// when the node is finished (not held in registers across the derivatives),
-// which keeps the kernel within 128 registers without spilling.
+// compute while the other waits on memory.  Within a workgroup the global
+// loads of a chunk are issued one phase early: while the derivatives of chunk
+// ch run, the update base of its nodes, the next chunk's q_s (direct nodes)
+// and the next chunk's slice of the per-level tables are already in flight.
 template <int NP, int LPC, typename T>
 __global__ void __launch_bounds__(((NP * NP * (LPC * (NP - 1) + 1) + 63) / 64) * 64, 4)
 k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double b, double c,
@@ -89,9 +90,36 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
     __shared__ double carry[2][NF][NP2];
     __shared__ T sD[NP2];
     __shared__ double sW[NP];
+    // the chunk's slice of the per-level tables, double-buffered: rho0,
+    // 1/rho0, 1/theta0, p0, dtheta0/dz, 1/M_v at its NK levels, then dz and
+    // 2/dz of its LPC layers
+    constexpr int SL = 6 * NK + 2 * LPC;
+    __shared__ double slice[2][SL];
     const int tid = threadIdx.x;
     for (int t = tid; t < NP2; t += WGT) sD[t] = T(m.D[t]);
     for (int t = tid; t < NP; t += WGT) sW[t] = m.w[t];
+    // this thread's slice entry: source table, offset, step per chunk, limit
+    const double* sl_src = nullptr;
+    int sl_off = 0, sl_step = 0, sl_lim = 0;
+    if (tid < 6 * NK) {
+        const int tab = tid / NK;
+        sl_src = tab == 0 ? m.rho0 : tab == 1 ? m.inv_rho0 : tab == 2 ? m.inv_theta0
+               : tab == 3 ? m.p0 : tab == 4 ? m.dth0 : m.minv_v;
+        sl_off = tid - tab * NK;
+        sl_step = LPC * (NP - 1);
+        sl_lim = m.nzn;
+    } else if (tid < SL) {
+        const int e = tid - 6 * NK;
+        sl_src = e < LPC ? m.dz : m.sz;
+        sl_off = e < LPC ? e : e - LPC;
+        sl_step = LPC;
+        sl_lim = m.n_z;
+    }
+    auto slice_value = [&](int ch2) {
+        const int k = sl_off + ch2 * sl_step;
+        return k < sl_lim ? sl_src[k] : 0.0;
+    };
+    if (tid < SL) slice[0][tid] = slice_value(0);
 
     // Workgroups go to the 8 XCDs round-robin by id; give each XCD a
     // contiguous (Morton-ordered) range of this colour's columns.
@@ -150,6 +178,7 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
     const int lx0 = (j * NP) * NK + kzl, ly0 = i * NK + kzl;
 
     const int n_chunk = (m.n_z + LPC - 1) / LPC;
+    double pf[NF] = {0, 0, 0, 0, 0};              // q_s of the next chunk (direct nodes)
     for (int ch = 0; ch < n_chunk; ++ch) {
         const int L0 = ch * LPC;
         const int L1 = min(L0 + LPC, m.n_z);
@@ -161,9 +190,14 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
         T rho = T(1);
         if (active) {
             if (g >= 0) {
-                const int64_t o = int64_t(g) * m.ldz + kz;
+                if (ch > 0) {
 #pragma unroll
-                for (int f = 0; f < NF; ++f) qv[f] = qs[f * fs + o];
+                    for (int f = 0; f < NF; ++f) qv[f] = pf[f];
+                } else {
+                    const int64_t o = int64_t(g) * m.ldz + kz;
+#pragma unroll
+                    for (int f = 0; f < NF; ++f) qv[f] = qs[f * fs + o];
+                }
             } else {
                 for (int r = r_beg; r < r_end; ++r) {
                     const double w = m.hang_w[r];
@@ -172,7 +206,7 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
                     for (int f = 0; f < NF; ++f) qv[f] += w * qs[f * fs + o];
                 }
             }
-            const double r0d = m.rho0[kz];
+            const double r0d = slice[ch & 1][kzl];
             rho = T(r0d) + T(qv[0]);
             const T u = T(qv[1]), v = T(qv[2]), w = T(qv[3]);
             tile[0][lidx] = rho * u;
@@ -181,10 +215,38 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
             tile[3][lidx] = u;
             tile[4][lidx] = v;
             tile[5][lidx] = w;
-            tile[6][lidx] = pressure_perturbation<T>(m, kz, qv[0], qv[4]);
+            {
+                // p' = p0 ((rho theta)/(rho0 theta0))^gamma - p0 with x = a + b + a b,
+                // a = rho'/rho0, b = theta'/theta0 (no cancellation against p0)
+                const double* sp = slice[ch & 1];
+                const T ra = T(qv[0] * sp[NK + kzl]), tb = T(qv[4] * sp[2 * NK + kzl]);
+                tile[6][lidx] = T(sp[3 * NK + kzl]) * pow1p_minus1<T>(m, ra + tb + ra * tb);
+            }
             tile[7][lidx] = T(qv[4]);
         }
         __syncthreads();
+        // update base of the nodes finished in this chunk (q^n for the first
+        // contributor, not read when a = 0; the partial q_out for later colours)
+        double base[NF] = {0, 0, 0, 0, 0};
+        if (active && g >= 0 && !(kzl == nk - 1 && L1 < m.n_z) && (!first || a != 0.0)) {
+            const double* bp = first ? qn : qo;
+            const int64_t o = int64_t(g) * m.ldz + kz;
+#pragma unroll
+            for (int f = 0; f < NF; ++f) base[f] = bp[f * fs + o];
+        }
+        const double* sb = slice[ch & 1];
+        double sl_next = 0.0;
+        if (tid < SL && ch + 1 < n_chunk) sl_next = slice_value(ch + 1);
+        // prefetch the next chunk's q_s
+        if (ch + 1 < n_chunk && lane_ok && g >= 0) {
+            const int L0n = L0 + LPC;
+            const int nkn = (min(L0n + LPC, m.n_z) - L0n) * N + 1;
+            if (kzl < nkn) {
+                const int64_t o = int64_t(g) * m.ldz + L0n * N + kzl;
+#pragma unroll
+                for (int f = 0; f < NF; ++f) pf[f] = qs[f * fs + o];
+            }
+        }
         if (active) {
             // d/dx of tile tx and d/dy of tile ty at this node.  The empty asm
             // pins both results before the next field's LDS reads may be
@@ -217,7 +279,7 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
             Rh[1] -= ax * inv_rho;
             Rh[2] -= ay * inv_rho;
             dxy(7, 7, ax, ay);
-            Rh[4] = -(u * ax + v * ay) - w * T(m.dth0[kz]);
+            Rh[4] = -(u * ax + v * ay) - w * T(sb[4 * NK + kzl]);
             double acc[NF] = {0, 0, 0, 0, 0};
             // elements of this chunk holding the node: (element, local k)
             const bool inner_plane = (kzl % N == 0) && kzl > 0 && kzl < nk - 1;
@@ -226,8 +288,8 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
             for (int s2 = 0; s2 < n_el; ++s2) {
                 const int el = e_first + s2;
                 const int kk = kzl - el * N;
-                const double dzl = m.dz[L0 + el];
-                const T sz = T(m.sz[L0 + el]);
+                const double dzl = sb[6 * NK + el];
+                const T sz = T(sb[6 * NK + LPC + el]);
                 const T* Dz = &sD[kk * NP];
                 const int lz0 = pc * NK + el * N;
                 auto ddz = [&](int tz) {
@@ -258,16 +320,8 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
                 }
                 if (g >= 0) {
                     const bool lid = (kz == 0) || (kz == nzn - 1);
-                    const double mi = c * minv_h * m.minv_v[kz];
+                    const double mi = c * minv_h * sb[5 * NK + kzl];
                     const int64_t o = int64_t(g) * m.ldz + kz;
-                    // update base: q^n for the first contributor (not read
-                    // when a = 0), the partial q_out for later colours
-                    double base[NF] = {0, 0, 0, 0, 0};
-                    if (!first || a != 0.0) {
-                        const double* bp = first ? qn : qo;
-#pragma unroll
-                        for (int f = 0; f < NF; ++f) base[f] = bp[f * fs + o];
-                    }
                     if (first) {
                         // the dissipation pre-pass (if any) is already assembled:
                         // the first contributor adds it once
@@ -298,6 +352,7 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
                 }
             }
         }
+        if (tid < SL && ch + 1 < n_chunk) slice[(ch + 1) & 1][tid] = sl_next;
         __syncthreads();
     }
 }
