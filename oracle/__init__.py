@@ -22,6 +22,9 @@ Cyclones using Adaptive Mesh Refinement" (arXiv 2410.21607):
 * ``amr``       threshold refinement / coarsening flags (Section 4.1).
 * ``adapt``     one adaptation pass of the column quadtree (split, 2:1
                 balance, merge) and the transfer of the solution onto it.
+* ``terrain``   terrain-following (mapped) hexahedra: discrete metrics, the
+                chain-rule derivatives, mapped lumped masses and the surface
+                boundary rule.
 * ``mlp``       small multilayer perceptron used by the refinement forecaster.
 * ``metrics``   floor-scaled relative L2 error and maximum wind.
 
@@ -30,4 +33,4 @@ constant generator with the HIP path; the only shared module is ``synth``
 (seeded input generation), which holds none of the method's arithmetic.
 """
 
-from . import gll, mesh, euler, assembly, timestep, amr, adapt, metrics  # noqa: F401
+from . import gll, mesh, euler, assembly, timestep, amr, adapt, metrics, terrain  # noqa: F401

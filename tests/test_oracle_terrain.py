@@ -1,0 +1,131 @@
+"""Pins of the oracle's terrain-following (mapped) elements.
+
+* flat terrain reduces to the box-element right-hand side of Section 3;
+* the chain rule differentiates fields linear in the physical coordinates
+  exactly, whatever the terrain (a wrong sign or index in the metric breaks it);
+* the mapped lumped masses integrate the domain under the terrain exactly for
+  a polynomial surface (LGL quadrature is exact at that degree);
+* a manufactured solution over smooth terrain converges spectrally in N;
+* on a plane slope the surface normal is exact and the bottom tendency is
+  tangent to the surface.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import assembly, terrain
+from oracle.mesh import OracleMesh
+from synth import cases, columns
+
+from test_oracle_rhs import exact_rhs, manufactured
+
+
+def build(c):
+    return OracleMesh(c["N"], c["nx0"], c["ny0"], c["Lx"], c["Ly"], c["z_edges"],
+                      c["columns"], c["periodic_x"], c["periodic_y"])
+
+
+def ref_global(c, m, zsG):
+    bg = cases.reference_state(c, terrain.node_heights(m, zsG))
+    return dict(rho0=bg["rho0"], theta0=bg["theta0"], dtheta0dz=bg["dtheta0dz"])
+
+
+def hills(c, amp=1500.0):
+    k = 2 * np.pi / c["Lx"]
+    return lambda x, y: 0.5 * amp * (1.0 + np.cos(k * x) * np.cos(k * y + 0.4))
+
+
+def test_flat_terrain_is_the_box_element_rhs():
+    c = cases.get("vortex_8x8x4_n4")
+    m = build(c)
+    q = cases.initial_state(c, m.node_xyz)
+    zs = np.zeros(m.n_dof)
+    bg = cases.reference_state(c, m.zl)
+    want = assembly.rhs(m, q, dict(rho0=bg["rho0"], theta0=bg["theta0"],
+                                   dtheta0dz=bg["dtheta0dz"]), c["phys"])
+    got = terrain.rhs(m, q, ref_global(c, m, zs), zs, c["phys"])
+    scale = np.abs(want).max(axis=1, keepdims=True)
+    assert np.all(np.abs(got - want) <= 1e-12 * scale)
+
+
+@pytest.mark.parametrize("N", [2, 4, 7])
+def test_linear_fields_differentiate_exactly(N):
+    c = cases.get("vortex_8x8x4_n4", N=N)
+    m = build(c)
+    zs = hills(c)(m.node_xyz[:, 0], m.node_xyz[:, 1])
+    zp = terrain.physical_z(m, zs)
+    _, Jinv, detJ = terrain.jacobian(m, zp)
+    assert np.all(detJ > 0)
+    a, b, cz = 3e-4, -7e-4, 2e-3
+    f = a * m.xl + b * m.yl + cz * zp
+    gx, gy, gz = terrain.gradient(m, Jinv, f)
+    for got, want in ((gx, a), (gy, b), (gz, cz)):
+        assert np.abs(got - want).max() <= 1e-11 * abs(cz)
+    # the height itself: grad z = (0, 0, 1) although z varies along x and y
+    zx, zy, zz = terrain.gradient(m, Jinv, zp)
+    assert np.abs(zx).max() < 1e-12 and np.abs(zy).max() < 1e-12
+    assert np.abs(zz - 1.0).max() < 1e-12
+
+
+@pytest.mark.parametrize("N", [2, 4])
+def test_mapped_masses_integrate_the_volume_under_polynomial_terrain(N):
+    c = cases.get("small_uniform", N=N)
+    c["periodic_x"] = c["periodic_y"] = False
+    m = build(c)
+    Lx, Ly = c["Lx"], c["Ly"]
+    A, B, C, Dxy, E = 900.0, 2e-3, -1e-3, 3e-8, 4e-8
+    zs_fn = lambda x, y: A + B * x + C * y + Dxy * x * y + E * x * x
+    zs = zs_fn(m.node_xyz[:, 0], m.node_xyz[:, 1])
+    _, _, detJ = terrain.jacobian(m, terrain.physical_z(m, zs))
+    mL, MG = terrain.lumped_mass(m, detJ)
+    H = c["z_edges"][-1] - c["z_edges"][0]
+    exact = H * Lx * Ly - (A * Lx * Ly + E * Lx**3 * Ly / 12.0)
+    assert abs(mL.sum() - exact) <= 1e-12 * exact
+    assert abs(MG.sum() - exact) <= 1e-12 * exact
+    assert np.all(MG > 0)
+
+
+def mms_error(N, nx, nz):
+    L, H = 100e3, 10e3
+    c = cases.get("vortex_8x8x4_n4")
+    c.update(N=N, nx0=nx, ny0=nx, Lx=L, Ly=L, z_edges=np.linspace(0, H, nz + 1),
+             columns=columns.uniform(nx, nx))
+    m = build(c)
+    zs = hills(c, amp=1200.0)(m.node_xyz[:, 0], m.node_xyz[:, 1])
+    F = manufactured(L, H)
+    xyz = m.node_xyz.copy()
+    xyz[:, 2] = terrain.node_heights(m, zs)
+    q = np.stack([Fi.val(*xyz.T) for Fi in F])
+    R = terrain.rhs(m, q, ref_global(c, m, zs), zs, c["phys"])
+    Rex = exact_rhs(c, xyz, F)
+    inner = ~(terrain.surface_nodes(m) | terrain.top_nodes(m))
+    scale = np.abs(Rex[:, inner]).max(axis=1)
+    return (np.abs(R[:, inner] - Rex[:, inner]).max(axis=1) / scale).max()
+
+
+def test_manufactured_solution_over_terrain_converges_spectrally():
+    e = [mms_error(N, 4, 2) for N in (2, 4, 6, 8)]
+    assert all(e[i + 1] < 0.2 * e[i] for i in range(3)), e
+    assert e[-1] < 1e-4 * e[0], e
+
+
+def test_plane_slope_normal_and_tangent_bottom_tendency():
+    c = cases.get("vortex_8x8x4_n4")
+    c["periodic_x"] = c["periodic_y"] = False
+    m = build(c)
+    s = 0.004
+    zs = s * (m.node_xyz[:, 0] + 0.5 * c["Lx"])
+    zp = terrain.physical_z(m, zs)
+    _, Jinv, detJ = terrain.jacobian(m, zp)
+    mL, MG = terrain.lumped_mass(m, detJ)
+    n, bot = terrain.surface_normal(m, zs, Jinv, mL, MG)
+    want = np.array([-s, 0.0, 1.0]) / np.sqrt(1 + s * s)
+    assert np.abs(n - want[:, None]).max() < 1e-13
+    xyz = m.node_xyz.copy()
+    xyz[:, 2] = terrain.node_heights(m, zs)
+    q = cases.initial_state(c, xyz)
+    R = terrain.rhs(m, q, ref_global(c, m, zs), zs, c["phys"])
+    normal = np.sum(R[1:4, bot] * n, axis=0)
+    assert np.abs(normal).max() <= 1e-13 * np.abs(R[1:4, bot]).max()
+    assert np.abs(R[1:4, bot]).max() > 0
+    assert np.all(R[3, terrain.top_nodes(m)] == 0.0)
