@@ -163,6 +163,33 @@ int sem_mesh_set_reference(sem_mesh *mesh, const double *h_rho0,
 int sem_mesh_set_dissipation(sem_mesh *mesh, double Cs, double sponge_gamma,
                              double sponge_depth);
 
+/* Terrain-following coordinates: the basis of Section 3 on mapped hexahedra
+ * (the mappings xi(x), eta(x), zeta(x) of that section are affine for the
+ * paper's box elements; here the vertical one follows the terrain).
+ *   h_zs[n_h]: surface height above the flat bottom z0 = z_edges[0] at every
+ *     unique horizontal node (sem_mesh_coords order), 0 <= zs < H - z0 with
+ *     H = z_edges[n_z].  A node at flat height zf moves to
+ *     z = zf + zs (H - zf) / (H - z0); columns keep their horizontal boxes.
+ *   h_rho0, h_theta0, h_dtheta0dz[n_dof], packed [h][kz]: the reference state
+ *     at every node's physical height (p0 is the equation of state of rho0,
+ *     theta0, as in sem_mesh_set_reference).
+ * sem_stage then takes every derivative by the chain rule with the discrete
+ * metric of the mapping (dzs/dx, dzs/dy from the element's nodal zs), uses the
+ * mapped lumped masses (their terrain factor cancels in the mass-weighted
+ * sum), keeps the rigid lid at the top, and at the terrain surface removes
+ * the component of the momentum tendency along the unit normal
+ * n ~ (-dzs/dx, -dzs/dy, 1), whose horizontal gradient is averaged over the
+ * columns sharing the node with the horizontal lumped masses.  Flat terrain
+ * (all zs = 0) reproduces the box-element stage.
+ * Limits: conforming meshes only (SEM_ERR_MESH when the mesh has hanging
+ * points); FP64 only; while terrain is set, sem_rhs, sem_dss, amr_flag,
+ * amr_features, the dissipation and SEM_FP32 stages return SEM_ERR_STATE.
+ * h_zs = NULL removes the terrain.  Arrays are copied; synchronises the
+ * device.  Errors: SEM_ERR_ARG (null mesh, zs out of range, non-positive
+ * reference), SEM_ERR_MESH, SEM_ERR_STATE (dissipation enabled), SEM_ERR_HIP. */
+int sem_mesh_set_terrain(sem_mesh *mesh, const double *h_zs, const double *h_rho0,
+                         const double *h_theta0, const double *h_dtheta0dz);
+
 /* Modified-DSS interpolation across nonconforming faces (Section 3.1).
  * SEM_SCATTER: d_dst = hv[F][n_hh][ldz] is overwritten with Z_h d_src, the
  *              values at hanging points interpolated from d_src = q[F][n_h][ldz].

@@ -96,6 +96,7 @@ class Mesh:
         self.info = {k: getattr(info, k) for k, _ in native.SemMeshInfo._fields_}
         self.columns = cols
         self.N = int(N)
+        self.terrain = None
 
     @classmethod
     def from_case(cls, case):
@@ -208,6 +209,38 @@ class Mesh:
                     float(sponge_depth))
         on = Cs > 0.0 or sponge_gamma > 0.0
         self.dissipation = (float(Cs), float(sponge_gamma), float(sponge_depth)) if on else None
+
+    def set_terrain(self, zs, rho0=None, theta0=None, dtheta0dz=None):
+        """Terrain-following coordinates (see sem_mesh_set_terrain): zs per
+        unique horizontal node (coords() order), the reference state per unique
+        node in state order [h][kz] at each node's physical height.  zs=None
+        removes the terrain."""
+        if zs is None:
+            native.call("sem_mesh_set_terrain", self.handle, None, None, None, None)
+            self.terrain = None
+            return
+        z = np.ascontiguousarray(np.asarray(zs, dtype=np.float64))
+        if z.size != self.info["n_h"]:
+            raise ValueError("zs needs one value per unique horizontal node")
+        arrs = [np.ascontiguousarray(np.asarray(a, dtype=np.float64)) for a in (rho0, theta0, dtheta0dz)]
+        for a in arrs:
+            if a.size != self.n_dof:
+                raise ValueError("terrain reference arrays need one value per unique node")
+        native.call("sem_mesh_set_terrain", self.handle, z.ctypes.data_as(native.c_dp),
+                    *[a.ctypes.data_as(native.c_dp) for a in arrs])
+        self.terrain = z.copy()
+
+    def node_heights(self):
+        """Physical height of every unique node in state order (flat heights
+        when no terrain is set)."""
+        xyz = self.node_xyz()
+        if self.terrain is None:
+            return xyz[:, 2]
+        _, _, zf = self.coords()
+        ze = np.asarray(self.params["z_edges"], dtype=np.float64)
+        z0, top = float(ze[0]), float(ze[-1])
+        zs = np.repeat(self.terrain, zf.size)
+        return xyz[:, 2] + zs * (top - xyz[:, 2]) / (top - z0)
 
     def state(self, device="cuda"):
         """A zeroed state tensor (padding stays zero under every compute call)."""

@@ -32,6 +32,16 @@ struct DevMesh {
     double cs;
     const double* sponge;
     const double* rx;
+    // terrain-following coordinates (sem_mesh_set_terrain; zs null = flat
+    // boxes): surface height per unique horizontal node, the unit surface
+    // normal [3][n_h], the reference state at every node's physical height
+    // [5][n_h][ldz] (rho0, 1/rho0, 1/theta0, p0, dtheta0/dz), the factor
+    // (H - zf)/(H - z0) per vertical node and 1/(H - z0)
+    const double* zs;
+    const double* nrm;
+    const double* ref_n;
+    const double* tfac;
+    double inv_depth;
 };
 
 }  // namespace sem

@@ -254,6 +254,7 @@ int amr_features(const sem_mesh* M, const double* q, const double* q_prev, const
                  int8_t* dem, void* stream) {
     if (!M) return fail(SEM_ERR_ARG, "null mesh");
     if (!M->have_ref) return fail(SEM_ERR_STATE, "sem_mesh_set_reference has not been called");
+    if (M->d.zs) return fail(SEM_ERR_STATE, "amr_features does not support terrain");
     if (!q || !q_prev || !plain || !feat || !dem || !scale) return fail(SEM_ERR_ARG, "null array");
     if (criterion != SEM_CRIT_SPEED && criterion != SEM_CRIT_VORTZ) return fail(SEM_ERR_ARG, "bad criterion");
     if (lvl_max < 0 || lvl_max > SEM_MAX_LEVEL) return fail(SEM_ERR_ARG, "lvl_max out of range");

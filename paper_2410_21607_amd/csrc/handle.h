@@ -42,6 +42,8 @@ struct sem_mesh {
     double *diss_rE = nullptr, *diss_acc = nullptr, *diss_c = nullptr, *diss_r = nullptr;
     double* diss_sponge = nullptr;
     double* wind_part = nullptr;  // 256 partial maxima (sem_max_wind)
+    double* terrain_buf = nullptr; // zs, normals, per-node reference, tfac (sem_mesh_set_terrain)
+    int64_t terrain_bytes = 0;
     const double* d_hxy = nullptr; // x, y of every unique horizontal node
     int64_t ws_bytes = 0;
     ~sem_mesh() {
@@ -50,6 +52,7 @@ struct sem_mesh {
         for (double* p : {diss_rE, diss_acc, diss_c, diss_r, diss_sponge})
             if (p) (void)hipFree(p);
         if (wind_part) (void)hipFree(wind_part);
+        if (terrain_buf) (void)hipFree(terrain_buf);
         for (void* p : allocs) (void)hipFree(p);
     }
     template <typename T>

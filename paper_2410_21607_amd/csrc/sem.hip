@@ -446,7 +446,15 @@ int launch_rhs_t(const sem_mesh* M, const double* q, const double* hv, double* r
 
 int check_mesh(const sem_mesh* M) {
     if (!M) return fail(SEM_ERR_ARG, "null mesh");
-    if (!M->have_ref) return fail(SEM_ERR_STATE, "sem_mesh_set_reference has not been called");
+    if (!M->have_ref && !M->d.zs)
+        return fail(SEM_ERR_STATE, "sem_mesh_set_reference has not been called");
+    return SEM_OK;
+}
+
+// calls that only know box elements
+int check_flat(const sem_mesh* M, const char* what) {
+    if (M && M->d.zs)
+        return fail(SEM_ERR_STATE, std::string(what) + " does not support terrain (use sem_stage)");
     return SEM_OK;
 }
 
@@ -645,6 +653,94 @@ int sem_mesh_set_reference(sem_mesh* M, const double* rho0, const double* theta0
     return SEM_OK;
 }
 
+int sem_mesh_set_terrain(sem_mesh* M, const double* zs, const double* rho0, const double* theta0,
+                         const double* dth0) {
+    if (!M) return fail(SEM_ERR_ARG, "null mesh");
+    const sem::HostMesh& H = M->host;
+    DevMesh& d = M->d;
+    HIPCHK(hipDeviceSynchronize());
+    if (!zs) {
+        d.zs = d.nrm = d.ref_n = d.tfac = nullptr;
+        return SEM_OK;
+    }
+    if (!rho0 || !theta0 || !dth0) return fail(SEM_ERR_ARG, "null reference array");
+    if (H.n_hh > 0) return fail(SEM_ERR_MESH, "terrain needs a conforming mesh (no hanging points)");
+    if (d.cs > 0.0 || d.sponge) return fail(SEM_ERR_STATE, "terrain and the dissipation cannot be combined");
+    const double z0 = H.z_edges.front(), top = H.z_edges.back(), depth = top - z0;
+    for (int64_t h = 0; h < H.n_h; ++h)
+        if (!(zs[h] >= 0.0) || !(zs[h] < depth))
+            return fail(SEM_ERR_ARG, "terrain heights must lie in [0, H - z0)");
+    const int np1 = H.np1, np2 = np1 * np1;
+    // unit surface normal per horizontal node: the element-local gradient of
+    // zs (LGL derivative of its nodal values, 2/dx and 2/dy) averaged over the
+    // columns sharing the node with the weights w_i w_j dx dy
+    std::vector<double> gx(H.n_h, 0.0), gy(H.n_h, 0.0), wt(H.n_h, 0.0);
+    const std::vector<double>& Dm = H.basis.D;
+    const std::vector<double>& w = H.basis.w;
+    for (int c = 0; c < H.n_col; ++c) {
+        const int32_t* gm = &H.gmap[size_t(c) * np2];
+        for (int j = 0; j < np1; ++j)
+            for (int i = 0; i < np1; ++i) {
+                double sx = 0.0, sy = 0.0;
+                for (int m = 0; m < np1; ++m) {
+                    sx += Dm[i * np1 + m] * zs[gm[j * np1 + m]];
+                    sy += Dm[j * np1 + m] * zs[gm[m * np1 + i]];
+                }
+                const int32_t h = gm[j * np1 + i];
+                const double wij = w[i] * w[j] * H.col_dx[c] * H.col_dy[c];
+                gx[h] += wij * sx * H.col_sx[c];
+                gy[h] += wij * sy * H.col_sy[c];
+                wt[h] += wij;
+            }
+    }
+    // one buffer: zs[n_h], nrm[3][n_h], ref_n[5][n_h][ldz], tfac[nzn]
+    const int64_t n_ref = 5 * H.n_h * int64_t(H.ldz);
+    const int64_t total = H.n_h + 3 * H.n_h + n_ref + H.nzn;
+    std::vector<double> buf(size_t(total), 0.0);
+    double* b_zs = buf.data();
+    double* b_n = b_zs + H.n_h;
+    double* b_ref = b_n + 3 * H.n_h;
+    double* b_tf = b_ref + n_ref;
+    const double gam = H.c_p / (H.c_p - H.R_d);
+    const int64_t fs = H.n_h * int64_t(H.ldz);
+    for (int64_t h = 0; h < H.n_h; ++h) {
+        b_zs[h] = zs[h];
+        const double nx = -gx[h] / wt[h], ny = -gy[h] / wt[h];
+        const double inv = 1.0 / std::sqrt(1.0 + nx * nx + ny * ny);
+        b_n[h] = nx * inv;
+        b_n[H.n_h + h] = ny * inv;
+        b_n[2 * H.n_h + h] = inv;
+        for (int k = 0; k < H.nzn; ++k) {
+            const int64_t src = h * H.nzn + k, o = h * H.ldz + k;
+            const double r = rho0[src], t = theta0[src];
+            if (!(r > 0.0) || !(t > 0.0)) return fail(SEM_ERR_ARG, "reference state must be positive");
+            b_ref[o] = r;
+            b_ref[fs + o] = 1.0 / r;
+            b_ref[2 * fs + o] = 1.0 / t;
+            b_ref[3 * fs + o] = H.p00 * std::pow(H.R_d * r * t / H.p00, gam);
+            b_ref[4 * fs + o] = dth0[src];
+        }
+    }
+    for (int k = 0; k < H.nzn; ++k) b_tf[k] = (top - H.zn[k]) / depth;
+    if (M->terrain_bytes != int64_t(sizeof(double)) * total) {
+        if (M->terrain_buf) {
+            (void)hipFree(M->terrain_buf);
+            M->ws_bytes -= M->terrain_bytes;
+            M->terrain_buf = nullptr;
+        }
+        HIPCHK(hipMalloc(&M->terrain_buf, sizeof(double) * total));
+        M->terrain_bytes = int64_t(sizeof(double)) * total;
+        M->ws_bytes += M->terrain_bytes;
+    }
+    HIPCHK(hipMemcpy(M->terrain_buf, buf.data(), sizeof(double) * total, hipMemcpyHostToDevice));
+    d.zs = M->terrain_buf;
+    d.nrm = d.zs + H.n_h;
+    d.ref_n = d.nrm + 3 * H.n_h;
+    d.tfac = d.ref_n + n_ref;
+    d.inv_depth = 1.0 / depth;
+    return SEM_OK;
+}
+
 int sem_nc_project(const sem_mesh* M, int dir, const double* src, double* dst, void* stream) {
     if (!M) return fail(SEM_ERR_ARG, "null mesh");
     if (dir != SEM_SCATTER && dir != SEM_GATHER) return fail(SEM_ERR_ARG, "bad direction");
@@ -663,6 +759,7 @@ int sem_nc_project(const sem_mesh* M, int dir, const double* src, double* dst, v
 int sem_rhs(const sem_mesh* M, const double* q, const double* hv, double* rE, int prec, void* stream) {
     int rc = check_mesh(M);
     if (rc != SEM_OK) return rc;
+    if ((rc = check_flat(M, "sem_rhs")) != SEM_OK) return rc;
     if (!q || !rE || (M->d.n_hh > 0 && !hv)) return fail(SEM_ERR_ARG, "null array");
     return sem_launch_rhs(M, q, hv, rE, prec, (hipStream_t)stream);
 }
@@ -670,6 +767,7 @@ int sem_rhs(const sem_mesh* M, const double* q, const double* hv, double* rE, in
 int sem_dss(const sem_mesh* M, int phase, const double* rE, double* acc, double* c, double* r,
             void* stream) {
     if (!M) return fail(SEM_ERR_ARG, "null mesh");
+    if (check_flat(M, "sem_dss") != SEM_OK) return SEM_ERR_STATE;
     const DevMesh& d = M->d;
     hipStream_t s = (hipStream_t)stream;
     if (phase == SEM_ASSEMBLE) {
@@ -705,6 +803,7 @@ int sem_stage(const sem_mesh* M, double a, double b, double c, const double* qn,
     if (!qn || !qs || !qout) return fail(SEM_ERR_ARG, "null array");
     if (qout == qs || qout == qn) return fail(SEM_ERR_ARG, "qout must not alias qs or qn");
     if (prec != SEM_FP64 && prec != SEM_FP32) return fail(SEM_ERR_ARG, "bad precision");
+    if (M->d.zs && prec != SEM_FP64) return fail(SEM_ERR_STATE, "terrain needs SEM_FP64");
     if (dissipation_on(M) && (rc = dissip_prepass(M, qs, (hipStream_t)stream)) != SEM_OK) return rc;
     rc = sem::fused_stage_launch(M->d, M->fused, a, b, c, qn, qs, qout, prec, (hipStream_t)stream);
     if (rc != SEM_OK) return fail(rc, "fused stage launch failed");
@@ -715,6 +814,8 @@ int sem_mesh_set_dissipation(sem_mesh* M, double cs, double sponge_gamma, double
     if (!M) return fail(SEM_ERR_ARG, "null mesh");
     if (!(cs >= 0.0) || !(sponge_gamma >= 0.0) || (sponge_gamma > 0.0 && !(sponge_depth > 0.0)))
         return fail(SEM_ERR_ARG, "need Cs >= 0, sponge_gamma >= 0 and sponge_depth > 0");
+    if (M->d.zs && (cs > 0.0 || sponge_gamma > 0.0))
+        return fail(SEM_ERR_STATE, "terrain and the dissipation cannot be combined");
     const sem::HostMesh& H = M->host;
     DevMesh& d = M->d;
     HIPCHK(hipDeviceSynchronize());
@@ -775,6 +876,7 @@ int sem_stage_autotune(sem_mesh* M, const double* qn, const double* qs, double* 
     if (!qn || !qs || !qout) return fail(SEM_ERR_ARG, "null array");
     if (qout == qs || qout == qn) return fail(SEM_ERR_ARG, "qout must not alias qs or qn");
     if (prec != SEM_FP64 && prec != SEM_FP32) return fail(SEM_ERR_ARG, "bad precision");
+    if (M->d.zs && prec != SEM_FP64) return fail(SEM_ERR_STATE, "terrain needs SEM_FP64");
     if (reps < 1) reps = 5;
     hipStream_t s = (hipStream_t)stream;
     hipEvent_t e0, e1;
@@ -822,6 +924,7 @@ int sem_stage_get_tune(const sem_mesh* M, int* layers_per_chunk) {
 int amr_flag(const sem_mesh* M, const double* q, int criterion, const double* thr, int lvl_max,
              int8_t* ae, int8_t* ac, void* stream) {
     if (!M) return fail(SEM_ERR_ARG, "null mesh");
+    if (check_flat(M, "amr_flag") != SEM_OK) return SEM_ERR_STATE;
     if (!q || !ae || !ac) return fail(SEM_ERR_ARG, "null array");
     if (criterion != SEM_CRIT_SPEED && criterion != SEM_CRIT_VORTZ) return fail(SEM_ERR_ARG, "bad criterion");
     if (lvl_max < 0 || lvl_max > SEM_MAX_LEVEL) return fail(SEM_ERR_ARG, "lvl_max out of range");

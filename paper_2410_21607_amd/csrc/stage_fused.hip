@@ -78,7 +78,16 @@ __device__ __forceinline__ T pow1p_minus1(const DevMesh& m, T x) {
 // loads of a chunk are issued one phase early: while the derivatives of chunk
 // ch run, the update base of its nodes, the next chunk's q_s (direct nodes)
 // and the next chunk's slice of the per-level tables are already in flight.
-template <int NP, int LPC, typename T>
+// TER: terrain-following coordinates (FP64 only).  The columns keep their
+// horizontal boxes; with g_s = 1/(1 - zs/(H - z0)) per position and
+// t_f = (H - zf)/(H - z0) per level, the chain rule of the mapping gives, with
+// d/dzf the box derivative 2/dz d/dzeta,
+//   d/dx = d/dx|box + a_x d/dzf,  d/dy = d/dy|box + a_y d/dzf,  d/dz = g_s d/dzf,
+//   a_x = -t_f g_s dzs/dx,  a_y = -t_f g_s dzs/dy,
+// so advection becomes the box horizontal part plus (u a_x + v a_y + w g_s) d/dzf.
+// The terrain factor of the lumped mass, 1/g_s, is the same in every element
+// sharing a node and cancels in the mass-weighted sum: the box masses serve.
+template <int NP, int LPC, typename T, bool TER>
 __global__ void __launch_bounds__(((NP * NP * (LPC * (NP - 1) + 1) + 63) / 64) * 64, 4)
 k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double b, double c,
                 const double* __restrict__ qn, const double* __restrict__ qs,
@@ -103,8 +112,11 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
     int sl_off = 0, sl_step = 0, sl_lim = 0;
     if (tid < 6 * NK) {
         const int tab = tid / NK;
-        sl_src = tab == 0 ? m.rho0 : tab == 1 ? m.inv_rho0 : tab == 2 ? m.inv_theta0
-               : tab == 3 ? m.p0 : tab == 4 ? m.dth0 : m.minv_v;
+        if constexpr (TER)   // reference per node instead; t_f in slot 0
+            sl_src = tab == 0 ? m.tfac : tab == 5 ? m.minv_v : nullptr;
+        else
+            sl_src = tab == 0 ? m.rho0 : tab == 1 ? m.inv_rho0 : tab == 2 ? m.inv_theta0
+                   : tab == 3 ? m.p0 : tab == 4 ? m.dth0 : m.minv_v;
         sl_off = tid - tab * NK;
         sl_step = LPC * (NP - 1);
         sl_lim = m.nzn;
@@ -117,7 +129,8 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
     }
     auto slice_value = [&](int ch2) {
         const int k = sl_off + ch2 * sl_step;
-        return k < sl_lim ? sl_src[k] : 0.0;
+        if constexpr (TER) return (sl_src && k < sl_lim) ? sl_src[k] : 0.0;
+        else return k < sl_lim ? sl_src[k] : 0.0;
     };
     if (tid < SL) slice[0][tid] = slice_value(0);
 
@@ -149,6 +162,13 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
         p = NP2;
         kzl = 0;
     }
+    __shared__ double s_zs[TER ? NP2 : 1];
+    if constexpr (TER) {
+        for (int t = tid; t < NP2; t += WGT) {
+            const int gz = m.gmap[col * NP2 + t];
+            s_zs[t] = gz >= 0 ? m.zs[gz] : 0.0;
+        }
+    }
     const bool lane_ok = (p < NP2) && (item < ncol);
     const int pc = lane_ok ? p : 0;               // position used for table lookups
     const int i = pc % NP, j = pc / NP;
@@ -176,6 +196,17 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
     const T* Dy = &sD[j * NP];
     const double mass_ij = sW[i] * sW[j] * 0.125 * dxc * dyc;
     const int lx0 = (j * NP) * NK + kzl, ly0 = i * NK + kzl;
+    // terrain: g_s and the box derivatives of zs at this position
+    double gs = 1.0, zsx = 0.0, zsy = 0.0;
+    if constexpr (TER) {
+        gs = 1.0 / (1.0 - s_zs[pc] * m.inv_depth);
+        for (int mm = 0; mm < NP; ++mm) {
+            zsx += double(sD[i * NP + mm]) * s_zs[j * NP + mm];
+            zsy += double(sD[j * NP + mm]) * s_zs[mm * NP + i];
+        }
+        zsx *= m.col_sx[col];
+        zsy *= m.col_sy[col];
+    }
 
     const int n_chunk = (m.n_z + LPC - 1) / LPC;
     double pf[NF] = {0, 0, 0, 0, 0};              // q_s of the next chunk (direct nodes)
@@ -206,7 +237,20 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
                     for (int f = 0; f < NF; ++f) qv[f] += w * qs[f * fs + o];
                 }
             }
-            const double r0d = slice[ch & 1][kzl];
+            double r0d, irho0, ith0, p0v;
+            if constexpr (TER) {
+                const int64_t o = int64_t(g) * m.ldz + kz;
+                r0d = m.ref_n[o];
+                irho0 = m.ref_n[fs + o];
+                ith0 = m.ref_n[2 * fs + o];
+                p0v = m.ref_n[3 * fs + o];
+            } else {
+                const double* sp = slice[ch & 1];
+                r0d = sp[kzl];
+                irho0 = sp[NK + kzl];
+                ith0 = sp[2 * NK + kzl];
+                p0v = sp[3 * NK + kzl];
+            }
             rho = T(r0d) + T(qv[0]);
             const T u = T(qv[1]), v = T(qv[2]), w = T(qv[3]);
             tile[0][lidx] = rho * u;
@@ -218,9 +262,8 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
             {
                 // p' = p0 ((rho theta)/(rho0 theta0))^gamma - p0 with x = a + b + a b,
                 // a = rho'/rho0, b = theta'/theta0 (no cancellation against p0)
-                const double* sp = slice[ch & 1];
-                const T ra = T(qv[0] * sp[NK + kzl]), tb = T(qv[4] * sp[2 * NK + kzl]);
-                tile[6][lidx] = T(sp[3 * NK + kzl]) * pow1p_minus1<T>(m, ra + tb + ra * tb);
+                const T ra = T(qv[0] * irho0), tb = T(qv[4] * ith0);
+                tile[6][lidx] = T(p0v) * pow1p_minus1<T>(m, ra + tb + ra * tb);
             }
             tile[7][lidx] = T(qv[4]);
         }
@@ -235,6 +278,10 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
             for (int f = 0; f < NF; ++f) base[f] = bp[f * fs + o];
         }
         const double* sb = slice[ch & 1];
+        double dth_n = 0.0;
+        if constexpr (TER) {
+            if (active) dth_n = m.ref_n[4 * fs + int64_t(g) * m.ldz + kz];
+        }
         double sl_next = 0.0;
         if (tid < SL && ch + 1 < n_chunk) sl_next = slice_value(ch + 1);
         // prefetch the next chunk's q_s
@@ -279,7 +326,16 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
             Rh[1] -= ax * inv_rho;
             Rh[2] -= ay * inv_rho;
             dxy(7, 7, ax, ay);
-            Rh[4] = -(u * ax + v * ay) - w * T(sb[4 * NK + kzl]);
+            if constexpr (TER) Rh[4] = -(u * ax + v * ay) - w * T(dth_n);
+            else Rh[4] = -(u * ax + v * ay) - w * T(sb[4 * NK + kzl]);
+            // terrain: a_x, a_y and the advecting vertical speed per node
+            T a_x = 0, a_y = 0, wt = w;
+            if constexpr (TER) {
+                const double tg = sb[kzl] * gs;
+                a_x = T(-tg * zsx);
+                a_y = T(-tg * zsy);
+                wt = u * a_x + v * a_y + w * T(gs);
+            }
             double acc[NF] = {0, 0, 0, 0, 0};
             // elements of this chunk holding the node: (element, local k)
             const bool inner_plane = (kzl % N == 0) && kzl > 0 && kzl < nk - 1;
@@ -300,11 +356,20 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
                     return az * sz;
                 };
                 T R[NF];
-                R[0] = Rh[0] - ddz(2);
-                R[1] = Rh[1] - w * ddz(3);
-                R[2] = Rh[2] - w * ddz(4);
-                R[3] = Rh[3] - w * ddz(5) - ddz(6) * inv_rho;
-                R[4] = Rh[4] - w * ddz(7);
+                if constexpr (TER) {
+                    const T pz = ddz(6) * inv_rho;
+                    R[0] = Rh[0] - (a_x * ddz(0) + a_y * ddz(1) + T(gs) * ddz(2));
+                    R[1] = Rh[1] - wt * ddz(3) - a_x * pz;
+                    R[2] = Rh[2] - wt * ddz(4) - a_y * pz;
+                    R[3] = Rh[3] - wt * ddz(5) - T(gs) * pz;
+                    R[4] = Rh[4] - wt * ddz(7);
+                } else {
+                    R[0] = Rh[0] - ddz(2);
+                    R[1] = Rh[1] - w * ddz(3);
+                    R[2] = Rh[2] - w * ddz(4);
+                    R[3] = Rh[3] - w * ddz(5) - ddz(6) * inv_rho;
+                    R[4] = Rh[4] - w * ddz(7);
+                }
                 const double mass = mass_ij * sW[kk] * dzl;
 #pragma unroll
                 for (int fl = 0; fl < NF; ++fl) acc[fl] += mass * double(R[fl]);
@@ -319,7 +384,19 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
                     for (int fl = 0; fl < NF; ++fl) acc[fl] += carry[(ch - 1) & 1][fl][pc];
                 }
                 if (g >= 0) {
-                    const bool lid = (kz == 0) || (kz == nzn - 1);
+                    bool lid = (kz == 0) || (kz == nzn - 1);
+                    if constexpr (TER) {
+                        // terrain surface: drop the momentum tendency along the
+                        // unit normal (the top stays a rigid lid)
+                        if (kz == 0) {
+                            const double n0 = m.nrm[g], n1 = m.nrm[m.n_h + g], n2 = m.nrm[2 * m.n_h + g];
+                            const double dn = acc[1] * n0 + acc[2] * n1 + acc[3] * n2;
+                            acc[1] -= dn * n0;
+                            acc[2] -= dn * n1;
+                            acc[3] -= dn * n2;
+                        }
+                        lid = (kz == nzn - 1);
+                    }
                     const double mi = c * minv_h * sb[5 * NK + kzl];
                     const int64_t o = int64_t(g) * m.ldz + kz;
                     if (first) {
@@ -394,13 +471,13 @@ __global__ void k_stage_hanging(DevMesh m, FusedTables ft, double c, double* __r
     X(7, 1) X(7, 2)                 \
     X(8, 1)
 
-template <typename T>
+template <typename T, bool TER>
 int launch_t(const DevMesh& m, const FusedTables& t, int col0, int ncol, double a, double b,
              double c, const double* qn, const double* qs, double* qo, hipStream_t s) {
     switch (m.N * 32 + t.layers_per_chunk) {
 #define CASE(NN, LP)                                                                    \
     case NN * 32 + LP:                                                                  \
-        hipLaunchKernelGGL((k_stage_columns<NN + 1, LP, T>), dim3(ncol),                \
+        hipLaunchKernelGGL((k_stage_columns<NN + 1, LP, T, TER>), dim3(ncol),           \
                            dim3(wg_threads<NN + 1, LP>()), 0, s, m, t, col0, ncol, a, b, \
                            c, qn, qs, qo);                                              \
         break;
@@ -510,8 +587,14 @@ int fused_stage_launch(const DevMesh& m, const FusedPlan& P, double a, double b,
         const int col0 = P.color_ptr_host[k];
         const int ncol = P.color_ptr_host[k + 1] - col0;
         if (ncol == 0) continue;
-        const int rc = (prec == SEM_FP32) ? launch_t<float>(m, t, col0, ncol, a, b, c, qn, qs, qo, s)
-                                          : launch_t<double>(m, t, col0, ncol, a, b, c, qn, qs, qo, s);
+        int rc;
+        if (m.zs) {
+            if (prec != SEM_FP64) return SEM_ERR_ARG;
+            rc = launch_t<double, true>(m, t, col0, ncol, a, b, c, qn, qs, qo, s);
+        } else {
+            rc = (prec == SEM_FP32) ? launch_t<float, false>(m, t, col0, ncol, a, b, c, qn, qs, qo, s)
+                                    : launch_t<double, false>(m, t, col0, ncol, a, b, c, qn, qs, qo, s);
+        }
         if (rc != SEM_OK) return rc;
     }
     const int64_t n2 = int64_t(m.n_hT) * m.nzn;

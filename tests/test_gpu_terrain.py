@@ -1,0 +1,198 @@
+"""GPU parity of the terrain-following fused stage (sem_stage after
+sem_mesh_set_terrain) against the oracle's mapped elements (oracle.terrain):
+
+* the right-hand side itself (a stage with a = b = 0, c = 1), on hills and on
+  a plane slope, N = 3 to 7, every supported chunk depth;
+* several SSP-RK3 stages;
+* flat terrain against the box-element stage;
+* the error paths (nonconforming mesh, heights out of range, FP32, calls that
+  only know box elements).
+
+Bar: floor-scaled relative L2 <= 1e-12 per field (FP64)."""
+
+import sys
+
+import numpy as np
+import pytest
+
+from harness import match, oracle_mesh
+from oracle import metrics, timestep
+from oracle import terrain as oterrain
+from synth import cases
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def hills(c, amp=1500.0):
+    kx, ky = 2 * np.pi / c["Lx"], 2 * np.pi / c["Ly"]
+    return lambda x, y: 0.5 * amp * (1.0 + np.cos(kx * x) * np.cos(ky * y + 0.4))
+
+
+def slope(c, s=0.004):
+    return lambda x, y: s * (x + 0.5 * c["Lx"]) + 0.001 * (y + 0.5 * c["Ly"])
+
+
+class Setup:
+    def __init__(self, name, kw, shape, periodic=True):
+        import torch
+        from paper_2410_21607_amd import api
+        self.torch, self.api = torch, api
+        c = cases.get(name, **dict(kw))
+        c["periodic_x"] = c["periodic_y"] = periodic
+        self.c = c
+        self.om = oracle_mesh(c)
+        self.gm = api.Mesh.from_case(c)
+        self.perm = match(self.om.node_xyz, self.gm.node_xyz(), c)
+        fn = hills(c) if shape == "hills" else slope(c)
+        self.zs = fn(self.om.node_xyz[:, 0], self.om.node_xyz[:, 1])
+        zp = oterrain.node_heights(self.om, self.zs)
+        bg = cases.reference_state(c, zp)
+        self.ref = dict(rho0=bg["rho0"], theta0=bg["theta0"], dtheta0dz=bg["dtheta0dz"])
+        xyz = self.om.node_xyz.copy()
+        xyz[:, 2] = zp
+        self.q_or = cases.initial_state(c, xyz)
+        nzn = self.gm.info["nzn"]
+        zs_nodes = self.zs[self.perm].reshape(-1, nzn)
+        assert np.all(zs_nodes == zs_nodes[:, :1])      # constant along every column
+        self.gm.set_terrain(zs_nodes[:, 0], *(self.ref[k][self.perm]
+                                             for k in ("rho0", "theta0", "dtheta0dz")))
+        # the binding's physical heights agree with the oracle's
+        np.testing.assert_allclose(self.gm.node_heights(), zp[self.perm], rtol=0, atol=1e-9)
+        self.q_g = self.gm.unpack(self.q_or[:, self.perm])
+
+    def to_oracle_order(self, flat):
+        a = self.gm.pack(flat)
+        out = np.empty_like(a)
+        out[:, self.perm] = a
+        return out
+
+    def oracle_rhs(self, q):
+        return oterrain.rhs(self.om, q, self.ref, self.zs, self.c["phys"])
+
+    def gpu_rhs(self):
+        out = self.torch.zeros_like(self.q_g)
+        self.api.sem_stage(self.gm, 0.0, 0.0, 1.0, self.q_g, self.q_g.clone(), out)
+        self.torch.cuda.synchronize()
+        return self.to_oracle_order(out)
+
+
+CASES = [("vortex_8x8x4_n4", {}, "hills", True),
+         ("small_uniform", {"N": 3}, "hills", True),
+         ("small_uniform", {"N": 7}, "slope", False),
+         ("vortex_8x8x4_n4", {"N": 5}, "slope", False),
+         ("small_uniform", {"N": 6}, "hills", False)]
+IDS = [f"{n}-{kw}-{s}-{'per' if p else 'wall'}" for n, kw, s, p in CASES]
+
+
+@pytest.mark.parametrize("name,kw,shape,periodic", CASES, ids=IDS)
+def test_terrain_rhs_matches_oracle_every_chunk_depth(name, kw, shape, periodic):
+    S = Setup(name, kw, shape, periodic)
+    want = S.oracle_rhs(S.q_or)
+    n_z = S.c["z_edges"].size - 1
+    tried = 0
+    for lpc in (1, 2, 4, 8):
+        if lpc > 2 * n_z:
+            continue
+        try:
+            S.api.sem_stage_tune(S.gm, lpc)
+        except Exception:
+            continue                               # no instance at this order
+        say("terrain rhs", name, kw, shape, "lpc", lpc)
+        err = metrics.rel_l2(S.gpu_rhs(), want, metrics.RHS_FLOORS)
+        say("  rel", err)
+        assert err.max() <= TOL64
+        tried += 1
+    assert tried >= 2
+
+
+@pytest.mark.parametrize("name,kw,shape,periodic", CASES[:3], ids=IDS[:3])
+def test_terrain_stages_match_oracle(name, kw, shape, periodic):
+    S = Setup(name, kw, shape, periodic)
+    torch, api = S.torch, S.api
+    nst, dt = 6, S.c["dt"]
+    say("terrain stages", name, kw, shape, nst)
+    qn, qs = S.q_g.clone(), S.q_g.clone()
+    out = torch.zeros_like(qn)
+    for st in range(nst):
+        a, b, cc = timestep.stage_coefficients(st % 3, dt)
+        api.sem_stage(S.gm, a, b, cc, qn, qs, out)
+        qs, out = out, qs
+        if st % 3 == 2:
+            qn.copy_(qs)
+    torch.cuda.synchronize()
+    want, _ = timestep.run_stages(S.oracle_rhs, S.q_or, dt, nst)
+    err = metrics.rel_l2(S.to_oracle_order(qs), want, metrics.STATE_FLOORS)
+    say("  rel", err)
+    assert err.max() <= TOL64
+
+
+def test_flat_terrain_matches_the_box_element_stage():
+    import torch
+    from paper_2410_21607_amd import api
+    c = cases.get("vortex_8x8x4_n4")
+    gm = api.Mesh.from_case(c)
+    _, _, z = gm.coords()
+    bg = cases.reference_state(c, z)
+    gm.set_reference(bg["rho0"], bg["theta0"], bg["dtheta0dz"])
+    q = gm.unpack(cases.initial_state(c, gm.node_xyz()))
+    box = torch.zeros_like(q)
+    api.sem_stage(gm, 0.0, 0.0, 1.0, q, q.clone(), box)
+    nzn = z.size
+    nodes = cases.reference_state(c, np.tile(z, gm.info["n_h"]))
+    gm.set_terrain(np.zeros(gm.info["n_h"]), nodes["rho0"], nodes["theta0"], nodes["dtheta0dz"])
+    ter = torch.zeros_like(q)
+    api.sem_stage(gm, 0.0, 0.0, 1.0, q, q.clone(), ter)
+    gm.set_terrain(None)
+    again = torch.zeros_like(q)
+    api.sem_stage(gm, 0.0, 0.0, 1.0, q, q.clone(), again)
+    torch.cuda.synchronize()
+    assert torch.equal(again, box)                 # removing the terrain restores the box path
+    b, t = gm.pack(box), gm.pack(ter)
+    scale = np.abs(b).max(axis=1, keepdims=True)
+    assert nzn > 0 and np.all(np.abs(t - b) <= 1e-13 * scale)
+
+
+def test_terrain_error_paths():
+    import torch
+    from paper_2410_21607_amd import api, native
+    amr = api.Mesh.from_case(cases.get("small_amr2"))
+    n = amr.n_dof
+    ones = np.ones(n)
+    with pytest.raises(native.SemError) as e:      # hanging points
+        amr.set_terrain(np.zeros(amr.info["n_h"]), ones, 300 * ones, 0 * ones)
+    assert e.value.code == -3
+    c = cases.get("small_uniform", N=3)
+    gm = api.Mesh.from_case(c)
+    nh, n = gm.info["n_h"], gm.n_dof
+    one, zero = np.ones(n), np.zeros(n)
+    for bad in (np.full(nh, -1.0), np.full(nh, 20e3), np.full(nh, np.nan)):
+        with pytest.raises(native.SemError) as e:  # heights outside [0, H - z0)
+            gm.set_terrain(bad, one, 300 * one, zero)
+        assert e.value.code == -1
+    with pytest.raises(native.SemError):           # non-positive reference
+        gm.set_terrain(np.zeros(nh), zero, 300 * one, zero)
+    gm.set_terrain(np.full(nh, 500.0), one, 300 * one, zero)
+    q = gm.state()
+    out = torch.zeros_like(q)
+    with pytest.raises(native.SemError) as e:
+        api.sem_stage(gm, 0.0, 0.0, 1.0, q, q.clone(), out, api.SEM_FP32)
+    assert e.value.code == -5
+    rE = torch.zeros(5 * gm.n_local, dtype=torch.float64, device="cuda")
+    with pytest.raises(native.SemError) as e:
+        api.sem_rhs(gm, q, None, rE)
+    assert e.value.code == -5
+    with pytest.raises(native.SemError) as e:
+        gm.set_dissipation(0.21, 0.0, 4000.0)
+    assert e.value.code == -5
+    ae = torch.zeros(gm.info["n_elem"], dtype=torch.int8, device="cuda")
+    ac = torch.zeros(gm.info["n_col"], dtype=torch.int8, device="cuda")
+    with pytest.raises(native.SemError) as e:
+        api.amr_flag(gm, q, 0, [7.5], 1, ae, ac)
+    assert e.value.code == -5
