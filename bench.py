@@ -164,6 +164,45 @@ def amr_throughput(device):
     return out
 
 
+def terrain_throughput(device, flat_ms=None, amp=2000.0, half_width=60e3, n_steps=20):
+    """The bench workload over a Gaussian mountain (terrain-following
+    coordinates): per-stage cost, and the roofline with the reference state
+    read per node (five FP64 arrays, 40 B per node on top of the state)."""
+    import numpy as np
+    import torch
+    from paper_2410_21607_amd import api
+    from synth import cases
+    case = cases.get(WORKLOAD)
+    mesh = api.Mesh.from_case(case)
+    hxy, _, zf = mesh.coords()
+    zs = amp * np.exp(-(hxy[:, 0] ** 2 + hxy[:, 1] ** 2) / half_width ** 2)
+    zp = np.tile(zf, zs.size)
+    ze = np.asarray(case["z_edges"], dtype=np.float64)
+    zp = zp + np.repeat(zs, zf.size) * (ze[-1] - zp) / (ze[-1] - ze[0])
+    bg = cases.reference_state(case, zp)
+    mesh.set_terrain(zs, bg["rho0"], bg["theta0"], bg["dtheta0dz"])
+    xyz = mesh.node_xyz()
+    xyz[:, 2] = zp
+    q0 = mesh.unpack(cases.initial_state(case, xyz), device=device)
+    t, q = timed_run(mesh, q0, case["dt"], api.SEM_FP64, n_steps)
+    per_node = sum(algorithmic_bytes(1, s) for s in range(3)) / 3.0 + 5 * 8
+    achieved = mesh.n_dof * per_node / t / 1e9
+    out = {"workload": WORKLOAD + " over a Gaussian mountain",
+           "mountain": {"height_m": amp, "half_width_m": half_width},
+           "n_dof": int(mesh.n_dof), "ms_per_stage": t * 1e3,
+           "dof_stage_per_s": mesh.n_dof / t,
+           "layers_per_chunk": api.sem_stage_get_tune(mesh),
+           "algorithmic_bytes_per_node_stage": per_node,
+           "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS},
+           "finite": bool(torch.isfinite(q).all().item())}
+    if flat_ms:
+        out["cost_ratio_over_flat"] = t * 1e3 / flat_ms
+    del mesh, q0, q
+    torch.cuda.empty_cache()
+    return out
+
+
 def adaptive_run(case, device, forecaster=None, rebuild_every=1, recorder=None, adapt=True,
                  columns=None):
     """An AdaptiveRun of an AMR workload (``case["amr"]`` settings) from its
@@ -355,6 +394,8 @@ def main():
                     help="run the forecaster experiment even with --no-extras")
     ap.add_argument("--forecaster-only", action="store_true",
                     help="run only the forecaster experiment and print its JSON")
+    ap.add_argument("--terrain-only", action="store_true",
+                    help="run only the terrain-following measurement and print its JSON")
     ap.add_argument("--tstar-only", action="store_true",
                     help="run only the time-to-solution study (uniform vs AMR by level) and print its JSON")
     ap.add_argument("--fc-case", default="vortex3_64x64x8_n4")
@@ -377,6 +418,9 @@ def main():
     from synth import cases
 
     dev = torch.device("cuda:0")
+    if args.terrain_only:
+        print(json.dumps(terrain_throughput(dev)), flush=True)
+        return
     if args.tstar_only:
         print(json.dumps(tstar_study(dev)), flush=True)
         return
@@ -471,6 +515,7 @@ def main():
     if not args.no_extras:
         res["fp32_variant"] = fp32_variant(case, mesh, q0)
         res["amr_two_level"] = amr_throughput(dev)
+        res["terrain"] = terrain_throughput(dev, flat_ms=res["ms_per_step"])
     if args.forecaster or not args.no_extras:
         res["amr_forecaster"] = forecaster_experiment(dev, args.fc_case, args.fc_seconds)
     if not args.no_cpu_baseline:

@@ -163,6 +163,7 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
         kzl = 0;
     }
     __shared__ double s_zs[TER ? NP2 : 1];
+    __shared__ double s_ter[TER ? 3 : 1][TER ? NP2 : 1];   // g_s, g_s dzs/dx, g_s dzs/dy
     if constexpr (TER) {
         for (int t = tid; t < NP2; t += WGT) {
             const int gz = m.gmap[col * NP2 + t];
@@ -196,16 +197,21 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
     const T* Dy = &sD[j * NP];
     const double mass_ij = sW[i] * sW[j] * 0.125 * dxc * dyc;
     const int lx0 = (j * NP) * NK + kzl, ly0 = i * NK + kzl;
-    // terrain: g_s and the box derivatives of zs at this position
-    double gs = 1.0, zsx = 0.0, zsy = 0.0;
+    // terrain: g_s and g_s times the box derivatives of zs per position (LDS)
     if constexpr (TER) {
-        gs = 1.0 / (1.0 - s_zs[pc] * m.inv_depth);
-        for (int mm = 0; mm < NP; ++mm) {
-            zsx += double(sD[i * NP + mm]) * s_zs[j * NP + mm];
-            zsy += double(sD[j * NP + mm]) * s_zs[mm * NP + i];
+        for (int t = tid; t < NP2; t += WGT) {
+            const int ti = t % NP, tj = t / NP;
+            double zx = 0.0, zy = 0.0;
+            for (int mm = 0; mm < NP; ++mm) {
+                zx += double(sD[ti * NP + mm]) * s_zs[tj * NP + mm];
+                zy += double(sD[tj * NP + mm]) * s_zs[mm * NP + ti];
+            }
+            const double gs = 1.0 / (1.0 - s_zs[t] * m.inv_depth);
+            s_ter[0][t] = gs;
+            s_ter[1][t] = gs * zx * m.col_sx[col];
+            s_ter[2][t] = gs * zy * m.col_sy[col];
         }
-        zsx *= m.col_sx[col];
-        zsy *= m.col_sy[col];
+        __syncthreads();
     }
 
     const int n_chunk = (m.n_z + LPC - 1) / LPC;
@@ -278,10 +284,6 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
             for (int f = 0; f < NF; ++f) base[f] = bp[f * fs + o];
         }
         const double* sb = slice[ch & 1];
-        double dth_n = 0.0;
-        if constexpr (TER) {
-            if (active) dth_n = m.ref_n[4 * fs + int64_t(g) * m.ldz + kz];
-        }
         double sl_next = 0.0;
         if (tid < SL && ch + 1 < n_chunk) sl_next = slice_value(ch + 1);
         // prefetch the next chunk's q_s
@@ -326,15 +328,16 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
             Rh[1] -= ax * inv_rho;
             Rh[2] -= ay * inv_rho;
             dxy(7, 7, ax, ay);
-            if constexpr (TER) Rh[4] = -(u * ax + v * ay) - w * T(dth_n);
+            if constexpr (TER) Rh[4] = -(u * ax + v * ay) - w * T(m.ref_n[4 * fs + int64_t(g) * m.ldz + kz]);
             else Rh[4] = -(u * ax + v * ay) - w * T(sb[4 * NK + kzl]);
             // terrain: a_x, a_y and the advecting vertical speed per node
-            T a_x = 0, a_y = 0, wt = w;
+            T a_x = 0, a_y = 0, wt = w, gs = 1;
             if constexpr (TER) {
-                const double tg = sb[kzl] * gs;
-                a_x = T(-tg * zsx);
-                a_y = T(-tg * zsy);
-                wt = u * a_x + v * a_y + w * T(gs);
+                const double tf = sb[kzl];
+                gs = T(s_ter[0][pc]);
+                a_x = T(-tf * s_ter[1][pc]);
+                a_y = T(-tf * s_ter[2][pc]);
+                wt = u * a_x + v * a_y + w * gs;
             }
             double acc[NF] = {0, 0, 0, 0, 0};
             // elements of this chunk holding the node: (element, local k)
@@ -358,10 +361,10 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
                 T R[NF];
                 if constexpr (TER) {
                     const T pz = ddz(6) * inv_rho;
-                    R[0] = Rh[0] - (a_x * ddz(0) + a_y * ddz(1) + T(gs) * ddz(2));
+                    R[0] = Rh[0] - (a_x * ddz(0) + a_y * ddz(1) + gs * ddz(2));
                     R[1] = Rh[1] - wt * ddz(3) - a_x * pz;
                     R[2] = Rh[2] - wt * ddz(4) - a_y * pz;
-                    R[3] = Rh[3] - wt * ddz(5) - T(gs) * pz;
+                    R[3] = Rh[3] - wt * ddz(5) - gs * pz;
                     R[4] = Rh[4] - wt * ddz(7);
                 } else {
                     R[0] = Rh[0] - ddz(2);
