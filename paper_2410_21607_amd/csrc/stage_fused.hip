@@ -227,7 +227,7 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
         T rho = T(1);
         if (active) {
             if (g >= 0) {
-                if (ch > 0) {
+                if (!TER && ch > 0) {
 #pragma unroll
                     for (int f = 0; f < NF; ++f) qv[f] = pf[f];
                 } else {
@@ -277,7 +277,7 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
         // update base of the nodes finished in this chunk (q^n for the first
         // contributor, not read when a = 0; the partial q_out for later colours)
         double base[NF] = {0, 0, 0, 0, 0};
-        if (active && g >= 0 && !(kzl == nk - 1 && L1 < m.n_z) && (!first || a != 0.0)) {
+        if (!TER && active && g >= 0 && !(kzl == nk - 1 && L1 < m.n_z) && (!first || a != 0.0)) {
             const double* bp = first ? qn : qo;
             const int64_t o = int64_t(g) * m.ldz + kz;
 #pragma unroll
@@ -286,8 +286,9 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
         const double* sb = slice[ch & 1];
         double sl_next = 0.0;
         if (tid < SL && ch + 1 < n_chunk) sl_next = slice_value(ch + 1);
-        // prefetch the next chunk's q_s
-        if (ch + 1 < n_chunk && lane_ok && g >= 0) {
+        // prefetch the next chunk's q_s (box elements: the terrain instance
+        // needs those registers for its metric terms)
+        if (!TER && ch + 1 < n_chunk && lane_ok && g >= 0) {
             const int L0n = L0 + LPC;
             const int nkn = (min(L0n + LPC, m.n_z) - L0n) * N + 1;
             if (kzl < nkn) {
@@ -402,6 +403,12 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
                     }
                     const double mi = c * minv_h * sb[5 * NK + kzl];
                     const int64_t o = int64_t(g) * m.ldz + kz;
+                    if (TER && (!first || a != 0.0)) {
+                        // the terrain instance loads its base here (registers)
+                        const double* bp = first ? qn : qo;
+#pragma unroll
+                        for (int f = 0; f < NF; ++f) base[f] = bp[f * fs + o];
+                    }
                     if (first) {
                         // the dissipation pre-pass (if any) is already assembled:
                         // the first contributor adds it once
