@@ -129,3 +129,49 @@ def test_plane_slope_normal_and_tangent_bottom_tendency():
     assert np.abs(normal).max() <= 1e-13 * np.abs(R[1:4, bot]).max()
     assert np.abs(R[1:4, bot]).max() > 0
     assert np.all(R[3, terrain.top_nodes(m)] == 0.0)
+
+
+# ---------------------------------------------------------------- 2:1 meshes
+def test_flat_terrain_is_the_box_element_rhs_on_nonconforming_meshes():
+    for name, kw in (("small_amr2", {}), ("small_amr3", {"N": 5, "periodic": False})):
+        c = cases.get(name, **kw)
+        m = build(c)
+        q = cases.initial_state(c, m.node_xyz)
+        zs = np.zeros(m.n_dof)
+        bg = cases.reference_state(c, m.zl)
+        want = assembly.rhs(m, q, dict(rho0=bg["rho0"], theta0=bg["theta0"],
+                                       dtheta0dz=bg["dtheta0dz"]), c["phys"])
+        got = terrain.rhs(m, q, ref_global(c, m, zs), zs, c["phys"])
+        scale = np.abs(want).max(axis=1, keepdims=True)
+        assert np.all(np.abs(got - want) <= 1e-12 * scale), name
+
+
+def test_nonconforming_geometry_is_watertight_and_exact_for_linear_fields():
+    c = cases.get("small_amr3", N=4)
+    m = build(c)
+    zs = hills(c)(m.node_xyz[:, 0], m.node_xyz[:, 1])
+    zp = terrain.physical_z(m, zs)
+    # every local copy of a node (hanging copies included) has the height of
+    # the coarse face's interpolant there: the mesh has no gaps
+    zG = terrain.node_heights(m, zs)
+    assert np.abs(zp.reshape(-1) - m.Z @ zG).max() < 1e-9
+    _, Jinv, detJ = terrain.jacobian(m, zp)
+    assert np.all(detJ > 0)
+    a, b, cz = 3e-4, -7e-4, 2e-3
+    gx, gy, gz = terrain.gradient(m, Jinv, a * m.xl + b * m.yl + cz * zp)
+    for got, want in ((gx, a), (gy, b), (gz, cz)):
+        assert np.abs(got - want).max() <= 1e-11 * abs(cz)
+
+
+def test_mapped_masses_on_nonconforming_mesh_integrate_polynomial_terrain():
+    c = cases.get("small_amr3", N=3, periodic=False)
+    m = build(c)
+    Lx, Ly = c["Lx"], c["Ly"]
+    A, E = 900.0, 4e-8
+    zs = A + E * m.node_xyz[:, 0] ** 2
+    _, _, detJ = terrain.jacobian(m, terrain.physical_z(m, zs))
+    mL, MG = terrain.lumped_mass(m, detJ)
+    H = c["z_edges"][-1] - c["z_edges"][0]
+    exact = H * Lx * Ly - (A * Lx * Ly + E * Lx**3 * Ly / 12.0)
+    assert abs(mL.sum() - exact) <= 1e-12 * exact
+    assert abs(MG.sum() - exact) <= 1e-12 * exact
