@@ -173,20 +173,22 @@ int sem_mesh_set_dissipation(sem_mesh *mesh, double Cs, double sponge_gamma,
  *   h_rho0, h_theta0, h_dtheta0dz[n_dof], packed [h][kz]: the reference state
  *     at every node's physical height (p0 is the equation of state of rho0,
  *     theta0, as in sem_mesh_set_reference).
- * sem_stage then takes every derivative by the chain rule with the discrete
- * metric of the mapping (dzs/dx, dzs/dy from the element's nodal zs), uses the
- * mapped lumped masses (their terrain factor cancels in the mass-weighted
- * sum), keeps the rigid lid at the top, and at the terrain surface removes
- * the component of the momentum tendency along the unit normal
+ * Hanging points (Section 3.1) take the coarse face's interpolant of zs and
+ * of the reference state, so the mapped mesh stays watertight across 2:1
+ * faces.  sem_stage then takes every derivative by the chain rule with the
+ * discrete metric of the mapping (dzs/dx, dzs/dy from the element's nodal
+ * zs), uses the mapped lumped masses (w_i w_j w_k det J, assembled with the
+ * modified DSS), keeps the rigid lid at the top, and at the terrain surface
+ * removes the component of the momentum tendency along the unit normal
  * n ~ (-dzs/dx, -dzs/dy, 1), whose horizontal gradient is averaged over the
- * columns sharing the node with the horizontal lumped masses.  Flat terrain
- * (all zs = 0) reproduces the box-element stage.
- * Limits: conforming meshes only (SEM_ERR_MESH when the mesh has hanging
- * points); FP64 only; while terrain is set, sem_rhs, sem_dss, amr_flag,
+ * columns sharing the node with the lumped masses.  Flat terrain (all
+ * zs = 0) reproduces the box-element stage.
+ * Limits: FP64 only; while terrain is set, sem_rhs, sem_dss, amr_flag,
  * amr_features, the dissipation and SEM_FP32 stages return SEM_ERR_STATE.
  * h_zs = NULL removes the terrain.  Arrays are copied; synchronises the
  * device.  Errors: SEM_ERR_ARG (null mesh, zs out of range, non-positive
- * reference), SEM_ERR_MESH, SEM_ERR_STATE (dissipation enabled), SEM_ERR_HIP. */
+ * reference), SEM_ERR_MESH (non-positive assembled mass), SEM_ERR_STATE
+ * (dissipation enabled), SEM_ERR_HIP. */
 int sem_mesh_set_terrain(sem_mesh *mesh, const double *h_zs, const double *h_rho0,
                          const double *h_theta0, const double *h_dtheta0dz);
 

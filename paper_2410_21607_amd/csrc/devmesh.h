@@ -33,12 +33,15 @@ struct DevMesh {
     const double* sponge;
     const double* rx;
     // terrain-following coordinates (sem_mesh_set_terrain; zs null = flat
-    // boxes): surface height per unique horizontal node, the unit surface
-    // normal [3][n_h], the reference state at every node's physical height
-    // [5][n_h][ldz] (rho0, 1/rho0, 1/theta0, p0, dtheta0/dz), the factor
+    // boxes): surface height per unique horizontal node then per hanging
+    // point (the coarse face's interpolant), n_h + n_hh rows; the unit surface
+    // normal [3][n_h]; the inverse horizontal lumped mass with the terrain
+    // factor; the reference state [5][n_h + n_hh][ldz] (rho0, 1/rho0,
+    // 1/theta0, p0, dtheta0/dz; hanging rows interpolated); the factor
     // (H - zf)/(H - z0) per vertical node and 1/(H - z0)
     const double* zs;
     const double* nrm;
+    const double* minv_ht;
     const double* ref_n;
     const double* tfac;
     double inv_depth;

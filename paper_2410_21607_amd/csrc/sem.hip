@@ -660,83 +660,126 @@ int sem_mesh_set_terrain(sem_mesh* M, const double* zs, const double* rho0, cons
     DevMesh& d = M->d;
     HIPCHK(hipDeviceSynchronize());
     if (!zs) {
-        d.zs = d.nrm = d.ref_n = d.tfac = nullptr;
+        d.zs = d.nrm = d.minv_ht = d.ref_n = d.tfac = nullptr;
         return SEM_OK;
     }
     if (!rho0 || !theta0 || !dth0) return fail(SEM_ERR_ARG, "null reference array");
-    if (H.n_hh > 0) return fail(SEM_ERR_MESH, "terrain needs a conforming mesh (no hanging points)");
     if (d.cs > 0.0 || d.sponge) return fail(SEM_ERR_STATE, "terrain and the dissipation cannot be combined");
     const double z0 = H.z_edges.front(), top = H.z_edges.back(), depth = top - z0;
     for (int64_t h = 0; h < H.n_h; ++h)
         if (!(zs[h] >= 0.0) || !(zs[h] < depth))
             return fail(SEM_ERR_ARG, "terrain heights must lie in [0, H - z0)");
-    const int np1 = H.np1, np2 = np1 * np1;
-    // unit surface normal per horizontal node: the element-local gradient of
-    // zs (LGL derivative of its nodal values, 2/dx and 2/dy) averaged over the
-    // columns sharing the node with the weights w_i w_j dx dy
-    std::vector<double> gx(H.n_h, 0.0), gy(H.n_h, 0.0), wt(H.n_h, 0.0);
+    const int np1 = H.np1, np2 = np1 * np1, nzn = H.nzn, ldz = H.ldz;
+    const int64_t nh = H.n_h, nhh = H.n_hh;
+    for (int64_t h = 0; h < nh; ++h)
+        for (int k = 0; k < nzn; ++k)
+            if (!(rho0[h * nzn + k] > 0.0) || !(theta0[h * nzn + k] > 0.0))
+                return fail(SEM_ERR_ARG, "reference state must be positive");
+    // one buffer: zs[n_h + n_hh], nrm[3][n_h], minv_ht[n_h],
+    // ref_n[5][n_h + n_hh][ldz] (hanging points after the unique nodes), tfac[nzn]
+    const int64_t fs = (nh + nhh) * ldz;
+    const int64_t total = nh + nhh + 3 * nh + nh + 5 * fs + nzn;
+    std::vector<double> buf(size_t(total), 0.0);
+    double* b_zs = buf.data();
+    double* b_zh = b_zs + nh;
+    double* b_n = b_zh + nhh;
+    double* b_mi = b_n + 3 * nh;
+    double* b_ref = b_mi + nh;
+    double* b_tf = b_ref + 5 * fs;
+    const double gam = H.c_p / (H.c_p - H.R_d);
+    auto fill_ref = [&](double* dst, int64_t stride, int64_t o, double r, double t, double dt) {
+        dst[o] = r;
+        dst[stride + o] = 1.0 / r;
+        dst[2 * stride + o] = 1.0 / t;
+        dst[3 * stride + o] = H.p00 * std::pow(H.R_d * r * t / H.p00, gam);
+        dst[4 * stride + o] = dt;
+    };
+    for (int64_t h = 0; h < nh; ++h) {
+        b_zs[h] = zs[h];
+        for (int k = 0; k < nzn; ++k) {
+            const int64_t src = h * nzn + k;
+            fill_ref(b_ref, fs, h * ldz + k, rho0[src], theta0[src], dth0[src]);
+        }
+    }
+    // hanging points: the coarse face's interpolant of zs and of the reference
+    for (int64_t hh = 0; hh < nhh; ++hh) {
+        double z = 0.0;
+        for (int32_t r = H.hang_ptr[hh]; r < H.hang_ptr[hh + 1]; ++r) z += H.hang_w[r] * zs[H.hang_src[r]];
+        b_zh[hh] = z;
+        for (int k = 0; k < nzn; ++k) {
+            double ri = 0.0, ti = 0.0, di = 0.0;
+            for (int32_t r = H.hang_ptr[hh]; r < H.hang_ptr[hh + 1]; ++r) {
+                const int64_t src = int64_t(H.hang_src[r]) * nzn + k;
+                ri += H.hang_w[r] * rho0[src];
+                ti += H.hang_w[r] * theta0[src];
+                di += H.hang_w[r] * dth0[src];
+            }
+            if (!(ri > 0.0) || !(ti > 0.0)) return fail(SEM_ERR_ARG, "reference state must be positive");
+            fill_ref(b_ref, fs, (nh + hh) * ldz + k, ri, ti, di);
+        }
+    }
+    // per column position: the element-local gradient of zs (LGL derivative
+    // of its nodal values times 2/dx, 2/dy) and the horizontal lumped mass
+    // with the terrain factor (1 - zs/(H - z0)); both are summed onto the
+    // unique horizontal nodes, hanging positions through their rows (Z^T)
+    std::vector<double> gx(size_t(nh), 0.0), gy(size_t(nh), 0.0), wt(size_t(nh), 0.0), mh(size_t(nh), 0.0);
     const std::vector<double>& Dm = H.basis.D;
     const std::vector<double>& w = H.basis.w;
+    std::vector<double> zp(static_cast<size_t>(np2));
     for (int c = 0; c < H.n_col; ++c) {
         const int32_t* gm = &H.gmap[size_t(c) * np2];
+        for (int p = 0; p < np2; ++p) zp[p] = gm[p] >= 0 ? zs[gm[p]] : b_zh[-gm[p] - 1];
         for (int j = 0; j < np1; ++j)
             for (int i = 0; i < np1; ++i) {
                 double sx = 0.0, sy = 0.0;
                 for (int m = 0; m < np1; ++m) {
-                    sx += Dm[i * np1 + m] * zs[gm[j * np1 + m]];
-                    sy += Dm[j * np1 + m] * zs[gm[m * np1 + i]];
+                    sx += Dm[i * np1 + m] * zp[j * np1 + m];
+                    sy += Dm[j * np1 + m] * zp[m * np1 + i];
                 }
-                const int32_t h = gm[j * np1 + i];
-                const double wij = w[i] * w[j] * H.col_dx[c] * H.col_dy[c];
-                gx[h] += wij * sx * H.col_sx[c];
-                gy[h] += wij * sy * H.col_sy[c];
-                wt[h] += wij;
+                sx *= H.col_sx[c];
+                sy *= H.col_sy[c];
+                const double wij = w[i] * w[j] * 0.25 * H.col_dx[c] * H.col_dy[c];
+                const double mt = wij * (1.0 - zp[j * np1 + i] / depth);
+                const int32_t g = gm[j * np1 + i];
+                auto add = [&](int64_t h, double f) {
+                    gx[h] += f * mt * sx;
+                    gy[h] += f * mt * sy;
+                    wt[h] += f * mt;
+                    mh[h] += f * mt;
+                };
+                if (g >= 0) add(g, 1.0);
+                else
+                    for (int32_t r = H.hang_ptr[-g - 1]; r < H.hang_ptr[-g]; ++r) add(H.hang_src[r], H.hang_w[r]);
             }
     }
-    // one buffer: zs[n_h], nrm[3][n_h], ref_n[5][n_h][ldz], tfac[nzn]
-    const int64_t n_ref = 5 * H.n_h * int64_t(H.ldz);
-    const int64_t total = H.n_h + 3 * H.n_h + n_ref + H.nzn;
-    std::vector<double> buf(size_t(total), 0.0);
-    double* b_zs = buf.data();
-    double* b_n = b_zs + H.n_h;
-    double* b_ref = b_n + 3 * H.n_h;
-    double* b_tf = b_ref + n_ref;
-    const double gam = H.c_p / (H.c_p - H.R_d);
-    const int64_t fs = H.n_h * int64_t(H.ldz);
-    for (int64_t h = 0; h < H.n_h; ++h) {
-        b_zs[h] = zs[h];
+    for (int64_t h = 0; h < nh; ++h) {
+        if (!(mh[h] > 0.0)) return fail(SEM_ERR_MESH, "non-positive assembled mass");
         const double nx = -gx[h] / wt[h], ny = -gy[h] / wt[h];
         const double inv = 1.0 / std::sqrt(1.0 + nx * nx + ny * ny);
         b_n[h] = nx * inv;
-        b_n[H.n_h + h] = ny * inv;
-        b_n[2 * H.n_h + h] = inv;
-        for (int k = 0; k < H.nzn; ++k) {
-            const int64_t src = h * H.nzn + k, o = h * H.ldz + k;
-            const double r = rho0[src], t = theta0[src];
-            if (!(r > 0.0) || !(t > 0.0)) return fail(SEM_ERR_ARG, "reference state must be positive");
-            b_ref[o] = r;
-            b_ref[fs + o] = 1.0 / r;
-            b_ref[2 * fs + o] = 1.0 / t;
-            b_ref[3 * fs + o] = H.p00 * std::pow(H.R_d * r * t / H.p00, gam);
-            b_ref[4 * fs + o] = dth0[src];
-        }
+        b_n[nh + h] = ny * inv;
+        b_n[2 * nh + h] = inv;
+        b_mi[h] = 1.0 / mh[h];
     }
-    for (int k = 0; k < H.nzn; ++k) b_tf[k] = (top - H.zn[k]) / depth;
+    for (int k = 0; k < nzn; ++k) b_tf[k] = (top - H.zn[k]) / depth;
     if (M->terrain_bytes != int64_t(sizeof(double)) * total) {
         if (M->terrain_buf) {
             (void)hipFree(M->terrain_buf);
             M->ws_bytes -= M->terrain_bytes;
             M->terrain_buf = nullptr;
+            M->terrain_bytes = 0;
         }
         HIPCHK(hipMalloc(&M->terrain_buf, sizeof(double) * total));
         M->terrain_bytes = int64_t(sizeof(double)) * total;
         M->ws_bytes += M->terrain_bytes;
     }
     HIPCHK(hipMemcpy(M->terrain_buf, buf.data(), sizeof(double) * total, hipMemcpyHostToDevice));
-    d.zs = M->terrain_buf;
-    d.nrm = d.zs + H.n_h;
-    d.ref_n = d.nrm + 3 * H.n_h;
-    d.tfac = d.ref_n + n_ref;
+    double* base = M->terrain_buf;
+    d.zs = base;
+    d.nrm = base + nh + nhh;
+    d.minv_ht = d.nrm + 3 * nh;
+    d.ref_n = d.minv_ht + nh;
+    d.tfac = d.ref_n + 5 * fs;
     d.inv_depth = 1.0 / depth;
     return SEM_OK;
 }

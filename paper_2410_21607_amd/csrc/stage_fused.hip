@@ -85,8 +85,11 @@ __device__ __forceinline__ T pow1p_minus1(const DevMesh& m, T x) {
 //   d/dx = d/dx|box + a_x d/dzf,  d/dy = d/dy|box + a_y d/dzf,  d/dz = g_s d/dzf,
 //   a_x = -t_f g_s dzs/dx,  a_y = -t_f g_s dzs/dy,
 // so advection becomes the box horizontal part plus (u a_x + v a_y + w g_s) d/dzf.
-// The terrain factor of the lumped mass, 1/g_s, is the same in every element
-// sharing a node and cancels in the mass-weighted sum: the box masses serve.
+// The lumped mass gains the factor 1/g_s = 1 - zs/(H - z0) per position; it
+// still factorises into a horizontal part (assembled on the host with that
+// factor, hanging positions through their rows) and the vertical one.
+// Hanging positions take the coarse face's interpolant of zs and of the
+// reference state (host tables), so the mesh stays watertight.
 template <int NP, int LPC, typename T, bool TER>
 __global__ void __launch_bounds__(((NP * NP * (LPC * (NP - 1) + 1) + 63) / 64) * 64, 4)
 k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double b, double c,
@@ -163,11 +166,11 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
         kzl = 0;
     }
     __shared__ double s_zs[TER ? NP2 : 1];
-    __shared__ double s_ter[TER ? 3 : 1][TER ? NP2 : 1];   // g_s, g_s dzs/dx, g_s dzs/dy
+    __shared__ double s_ter[TER ? 4 : 1][TER ? NP2 : 1];   // g_s, g_s dzs/dx, g_s dzs/dy, 1/g_s
     if constexpr (TER) {
         for (int t = tid; t < NP2; t += WGT) {
             const int gz = m.gmap[col * NP2 + t];
-            s_zs[t] = gz >= 0 ? m.zs[gz] : 0.0;
+            s_zs[t] = m.zs[gz >= 0 ? gz : m.n_h - gz - 1];
         }
     }
     const bool lane_ok = (p < NP2) && (item < ncol);
@@ -176,6 +179,7 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
     const int nzn = m.nzn;
     const int64_t fs = int64_t(m.n_h) * m.ldz;
     const int64_t fsh = int64_t(m.n_hh) * m.ldz;
+    const int64_t fsr = int64_t(m.n_h + m.n_hh) * m.ldz;   // terrain reference rows
 
     int g = 0, r_beg = 0, r_end = 0;
     bool first = false;
@@ -189,7 +193,7 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
             r_beg = m.hang_ptr[-g - 1];
             r_end = m.hang_ptr[-g];
         } else {
-            minv_h = m.minv_h[g];
+            minv_h = TER ? m.minv_ht[g] : m.minv_h[g];
         }
     }
     __syncthreads();
@@ -197,6 +201,7 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
     const T* Dy = &sD[j * NP];
     const double mass_ij = sW[i] * sW[j] * 0.125 * dxc * dyc;
     const int lx0 = (j * NP) * NK + kzl, ly0 = i * NK + kzl;
+    const int rrow = TER ? (g >= 0 ? g : m.n_h - g - 1) : 0;   // terrain reference row
     // terrain: g_s and g_s times the box derivatives of zs per position (LDS)
     if constexpr (TER) {
         for (int t = tid; t < NP2; t += WGT) {
@@ -210,6 +215,7 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
             s_ter[0][t] = gs;
             s_ter[1][t] = gs * zx * m.col_sx[col];
             s_ter[2][t] = gs * zy * m.col_sy[col];
+            s_ter[3][t] = 1.0 - s_zs[t] * m.inv_depth;
         }
         __syncthreads();
     }
@@ -245,11 +251,12 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
             }
             double r0d, irho0, ith0, p0v;
             if constexpr (TER) {
-                const int64_t o = int64_t(g) * m.ldz + kz;
+                // per node; hanging rows hold the coarse face's interpolant
+                const int64_t o = int64_t(rrow) * m.ldz + kz;
                 r0d = m.ref_n[o];
-                irho0 = m.ref_n[fs + o];
-                ith0 = m.ref_n[2 * fs + o];
-                p0v = m.ref_n[3 * fs + o];
+                irho0 = m.ref_n[fsr + o];
+                ith0 = m.ref_n[2 * fsr + o];
+                p0v = m.ref_n[3 * fsr + o];
             } else {
                 const double* sp = slice[ch & 1];
                 r0d = sp[kzl];
@@ -329,7 +336,9 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
             Rh[1] -= ax * inv_rho;
             Rh[2] -= ay * inv_rho;
             dxy(7, 7, ax, ay);
-            if constexpr (TER) Rh[4] = -(u * ax + v * ay) - w * T(m.ref_n[4 * fs + int64_t(g) * m.ldz + kz]);
+            if constexpr (TER) {
+                Rh[4] = -(u * ax + v * ay) - w * T(m.ref_n[4 * fsr + int64_t(rrow) * m.ldz + kz]);
+            }
             else Rh[4] = -(u * ax + v * ay) - w * T(sb[4 * NK + kzl]);
             // terrain: a_x, a_y and the advecting vertical speed per node
             T a_x = 0, a_y = 0, wt = w, gs = 1;
@@ -386,6 +395,12 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
                 if (kzl == 0 && ch > 0) {
 #pragma unroll
                     for (int fl = 0; fl < NF; ++fl) acc[fl] += carry[(ch - 1) & 1][fl][pc];
+                }
+                if constexpr (TER) {
+                    // mapped lumped mass: the box mass times 1 - zs/(H - z0)
+                    const double mf = s_ter[3][pc];
+#pragma unroll
+                    for (int fl = 0; fl < NF; ++fl) acc[fl] *= mf;
                 }
                 if (g >= 0) {
                     bool lid = (kz == 0) || (kz == nzn - 1);
@@ -461,8 +476,21 @@ __global__ void k_stage_hanging(DevMesh m, FusedTables ft, double c, double* __r
 #pragma unroll
             for (int f = 0; f < NF; ++f) s[f] += w * ft.cH[f * fsh + o];
         }
-        const bool lid = (kz == 0) || (kz == nzn - 1);
-        const double mi = c * m.minv_h[h] * m.minv_v[kz];
+        bool lid = (kz == 0) || (kz == nzn - 1);
+        double mi = c * m.minv_h[h] * m.minv_v[kz];
+        if (m.zs) {
+            // terrain: mapped masses; at the surface drop the momentum
+            // tendency along the normal (linear, so per contribution)
+            mi = c * m.minv_ht[h] * m.minv_v[kz];
+            if (kz == 0) {
+                const double n0 = m.nrm[h], n1 = m.nrm[m.n_h + h], n2 = m.nrm[2 * m.n_h + h];
+                const double dn = s[1] * n0 + s[2] * n1 + s[3] * n2;
+                s[1] -= dn * n0;
+                s[2] -= dn * n1;
+                s[3] -= dn * n2;
+            }
+            lid = (kz == nzn - 1);
+        }
         const int64_t o = int64_t(h) * m.ldz + kz;
 #pragma unroll
         for (int f = 0; f < NF; ++f)
