@@ -164,15 +164,16 @@ def amr_throughput(device):
     return out
 
 
-def terrain_throughput(device, flat_ms=None, amp=2000.0, half_width=60e3, n_steps=20):
-    """The bench workload over a Gaussian mountain (terrain-following
-    coordinates): per-stage cost, and the roofline with the reference state
-    read per node (five FP64 arrays, 40 B per node on top of the state)."""
+def terrain_throughput(device, flat_ms=None, case_name=WORKLOAD, amp=2000.0, half_width=60e3,
+                       n_steps=20):
+    """A workload over a Gaussian mountain (terrain-following coordinates):
+    per-stage cost, and the roofline with the reference state read per node
+    (five FP64 arrays, 40 B per node on top of the state)."""
     import numpy as np
     import torch
     from paper_2410_21607_amd import api
     from synth import cases
-    case = cases.get(WORKLOAD)
+    case = cases.get(case_name)
     mesh = api.Mesh.from_case(case)
     hxy, _, zf = mesh.coords()
     zs = amp * np.exp(-(hxy[:, 0] ** 2 + hxy[:, 1] ** 2) / half_width ** 2)
@@ -187,7 +188,17 @@ def terrain_throughput(device, flat_ms=None, amp=2000.0, half_width=60e3, n_step
     t, q = timed_run(mesh, q0, case["dt"], api.SEM_FP64, n_steps)
     per_node = sum(algorithmic_bytes(1, s) for s in range(3)) / 3.0 + 5 * 8
     achieved = mesh.n_dof * per_node / t / 1e9
-    out = {"workload": WORKLOAD + " over a Gaussian mountain",
+    if flat_ms is None:
+        # the same mesh with box elements, for the cost ratio
+        fm = api.Mesh.from_case(case)
+        bgf = cases.reference_state(case, zf)
+        fm.set_reference(bgf["rho0"], bgf["theta0"], bgf["dtheta0dz"])
+        fq = fm.unpack(cases.initial_state(case, fm.node_xyz()), device=device)
+        tf, _ = timed_run(fm, fq, case["dt"], api.SEM_FP64, n_steps)
+        flat_ms = tf * 1e3
+        del fm, fq
+    out = {"workload": case_name + " over a Gaussian mountain",
+           "hanging_points": int(mesh.info["n_hh"]),
            "mountain": {"height_m": amp, "half_width_m": half_width},
            "n_dof": int(mesh.n_dof), "ms_per_stage": t * 1e3,
            "dof_stage_per_s": mesh.n_dof / t,
@@ -419,7 +430,9 @@ def main():
 
     dev = torch.device("cuda:0")
     if args.terrain_only:
-        print(json.dumps(terrain_throughput(dev)), flush=True)
+        print(json.dumps({"uniform": terrain_throughput(dev),
+                          "two_level_amr": terrain_throughput(dev, case_name="amr2_64x64x8_n4")}),
+              flush=True)
         return
     if args.tstar_only:
         print(json.dumps(tstar_study(dev)), flush=True)
@@ -515,7 +528,8 @@ def main():
     if not args.no_extras:
         res["fp32_variant"] = fp32_variant(case, mesh, q0)
         res["amr_two_level"] = amr_throughput(dev)
-        res["terrain"] = terrain_throughput(dev, flat_ms=res["ms_per_step"])
+        res["terrain"] = {"uniform": terrain_throughput(dev, flat_ms=res["ms_per_step"]),
+                          "two_level_amr": terrain_throughput(dev, case_name="amr2_64x64x8_n4")}
     if args.forecaster or not args.no_extras:
         res["amr_forecaster"] = forecaster_experiment(dev, args.fc_case, args.fc_seconds)
     if not args.no_cpu_baseline:
