@@ -176,6 +176,63 @@ struct Axis {
 
 using Row = std::vector<std::pair<int32_t, double>>;
 
+// Open-addressing table from a pair of non-negative 64-bit keys to int32
+// (linear probing, load factor at most 1/2, no erase, one entry per probe):
+// the numbering of ~10^5 positions needs no node allocation per entry.
+class PairTable {
+  public:
+    explicit PairTable(size_t n_max) {
+        size_t cap = 16;
+        while (cap < 2 * n_max + 2) cap <<= 1;
+        e_.assign(cap, Entry{-1, 0, 0});
+        mask_ = cap - 1;
+    }
+    // value of (a, b), or -1 when absent
+    int32_t find(int64_t a, int64_t b) const {
+        for (size_t i = slot(a, b);; i = (i + 1) & mask_) {
+            const Entry& e = e_[i];
+            if (e.a < 0) return -1;
+            if (e.a == a && e.b == b) return e.v;
+        }
+    }
+    // value of (a, b); inserts v (and sets inserted) when absent
+    int32_t find_or_insert(int64_t a, int64_t b, int32_t v, bool& inserted) {
+        for (size_t i = slot(a, b);; i = (i + 1) & mask_) {
+            Entry& e = e_[i];
+            if (e.a < 0) {
+                e = Entry{a, b, v};
+                ++size_;
+                inserted = true;
+                return v;
+            }
+            if (e.a == a && e.b == b) {
+                inserted = false;
+                return e.v;
+            }
+        }
+    }
+    size_t size() const { return size_; }
+    template <typename F>
+    void for_each(F f) const {
+        for (const Entry& e : e_)
+            if (e.a >= 0) f(e.a, e.b, e.v);
+    }
+
+  private:
+    struct Entry {
+        int64_t a, b;
+        int32_t v;
+    };
+    size_t slot(int64_t a, int64_t b) const {
+        uint64_t h = uint64_t(a) * 0x9E3779B97F4A7C15ull;
+        h ^= uint64_t(b) + 0x632BE59BD9B4E019ull + (h << 6) + (h >> 2);
+        h ^= h >> 29;
+        return size_t(h) & mask_;
+    }
+    std::vector<Entry> e_;
+    size_t mask_ = 0, size_ = 0;
+};
+
 }  // namespace
 
 // ------------------------------------------------------------------ build
@@ -294,8 +351,13 @@ int build_host_mesh(const MeshInput& in, HostMesh& m, std::string& err) {
 
     // ---- horizontal keys and hanging status
     Axis ax{in.nx0, L, in.periodic_x}, ay{in.ny0, L, in.periodic_y};
-    std::map<std::tuple<int, int64_t, int64_t>, int32_t> cmap;
-    for (int c = 0; c < in.n_col; ++c) cmap[{in.lev[c], in.ix[c], in.iy[c]}] = c;
+    // column of (level, ix, iy)
+    PairTable cmap(size_t(in.n_col));
+    auto lkey = [](int l, int64_t x) { return (int64_t(l) << 40) | x; };
+    for (int c = 0; c < in.n_col; ++c) {
+        bool ins;
+        cmap.find_or_insert(lkey(in.lev[c], in.ix[c]), in.iy[c], c, ins);
+    }
     auto kx_of = [&](int c, int i) { return ax.key(N, in.lev[c], in.ix[c], i); };
     auto ky_of = [&](int c, int j) { return ay.key(N, in.lev[c], in.iy[c], j); };
 
@@ -317,9 +379,8 @@ int build_host_mesh(const MeshInput& in, HostMesh& m, std::string& err) {
                         for (int b2 = 0; b2 < nyc && !found; ++b2) {
                             int64_t cx, cy;
                             if (!ax.wrap(cxs[a], lc, cx) || !ay.wrap(cys[b2], lc, cy)) continue;
-                            auto it = cmap.find({lc, cx, cy});
-                            if (it == cmap.end()) continue;
-                            int cc = it->second;
+                            const int cc = cmap.find(lkey(lc, cx), cy);
+                            if (cc < 0) continue;
                             bool nx_ = false, ny_ = false;
                             for (int t = 0; t < np1; ++t) {
                                 nx_ = nx_ || (kx_of(cc, t) == kx);
@@ -336,7 +397,11 @@ int build_host_mesh(const MeshInput& in, HostMesh& m, std::string& err) {
             }
     }
     // ---- number unique nodes (first touch) and hanging points
-    std::unordered_map<Key2, int32_t, Key2Hash> hid, hhid;
+    // keys of lattice positions are >= 0; interior LGL keys carry GLL_TAG (also >= 0)
+    // unique horizontal nodes: at most (N^2 + 2N + 1) per column, fewer when shared
+    size_t n_hang_slots = 0;
+    for (int32_t sc : src_col) n_hang_slots += sc >= 0;
+    PairTable hid(size_t(in.n_col) * size_t(N * N + 2 * N + 1)), hhid(n_hang_slots);
     m.gmap.assign(size_t(in.n_col) * np2, 0);
     std::vector<size_t> hh_first;   // (c, pos) slot that defined each hanging point
     for (int c = 0; c < in.n_col; ++c)
@@ -346,31 +411,23 @@ int build_host_mesh(const MeshInput& in, HostMesh& m, std::string& err) {
                 Key2 k{kx_of(c, i), ky_of(c, j)};
                 double x = m.col_x0[c] + 0.5 * (1.0 + B.x[i]) * m.col_dx[c];
                 double y = m.col_y0[c] + 0.5 * (1.0 + B.x[j]) * m.col_dy[c];
+                bool ins;
                 if (src_col[s] < 0) {
-                    auto it = hid.find(k);
-                    if (it == hid.end()) {
-                        int32_t id = int32_t(hid.size());
-                        hid.emplace(k, id);
-                        m.h_xy.push_back(x); m.h_xy.push_back(y);
-                        m.gmap[s] = id;
-                    } else {
-                        m.gmap[s] = it->second;
-                    }
+                    const int32_t id = hid.find_or_insert(k.kx, k.ky, int32_t(hid.size()), ins);
+                    if (ins) { m.h_xy.push_back(x); m.h_xy.push_back(y); }
+                    m.gmap[s] = id;
                 } else {
-                    auto it = hhid.find(k);
-                    if (it == hhid.end()) {
-                        int32_t id = int32_t(hhid.size());
-                        hhid.emplace(k, id);
+                    const int32_t id = hhid.find_or_insert(k.kx, k.ky, int32_t(hhid.size()), ins);
+                    if (ins) {
                         m.hh_xy.push_back(x); m.hh_xy.push_back(y);
                         hh_first.push_back(s);
-                        m.gmap[s] = -(id + 1);
-                    } else {
-                        m.gmap[s] = -(it->second + 1);
                     }
+                    m.gmap[s] = -(id + 1);
                 }
             }
-    for (auto& kv : hhid)
-        if (hid.count(kv.first)) { err = "a hanging point is also a conforming node"; return SEM_ERR_MESH; }
+    bool clash = false;
+    hhid.for_each([&](int64_t a, int64_t b, int32_t) { clash = clash || hid.find(a, b) >= 0; });
+    if (clash) { err = "a hanging point is also a conforming node"; return SEM_ERR_MESH; }
     m.n_h = int64_t(hid.size());
     m.n_hh = int64_t(hhid.size());
     if (m.n_h * int64_t(m.ldz) >= (int64_t(1) << 31) || m.n_hh * int64_t(m.ldz) >= (int64_t(1) << 31) ||
@@ -378,8 +435,10 @@ int build_host_mesh(const MeshInput& in, HostMesh& m, std::string& err) {
         err = "mesh too large for 32-bit node indices"; return SEM_ERR_MESH;
     }
     // ---- rows of every (c, pos), composed until the sources are unique nodes
-    std::vector<Row> rows(size_t(in.n_col) * np2);
-    std::vector<char> done(rows.size(), 0);
+    // rows of hanging slots only (a conforming slot is the unit row of its node)
+    std::vector<int32_t> row_of(size_t(in.n_col) * np2, -1);
+    std::vector<Row> rows;
+    std::vector<char> done(row_of.size(), 0);
     std::vector<double> wx(np1), wy(np1);
     // process coarse levels first so that sources are complete
     std::vector<int> order(in.n_col);
@@ -388,7 +447,7 @@ int build_host_mesh(const MeshInput& in, HostMesh& m, std::string& err) {
     for (int c : order)
         for (int p = 0; p < np2; ++p) {
             size_t s = size_t(c) * np2 + p;
-            if (src_col[s] < 0) { rows[s] = {{m.gmap[s], 1.0}}; done[s] = 1; continue; }
+            if (src_col[s] < 0) { done[s] = 1; continue; }
             int cc = src_col[s];
             lagrange_weights(B, src_sx[s], wx.data());
             lagrange_weights(B, src_sy[s], wy.data());
@@ -399,16 +458,19 @@ int build_host_mesh(const MeshInput& in, HostMesh& m, std::string& err) {
                     if (wt == 0.0) continue;
                     size_t ss = size_t(cc) * np2 + a + np1 * b2;
                     if (!done[ss]) { err = "hanging chain does not resolve"; return SEM_ERR_MESH; }
-                    for (auto& e : rows[ss]) acc[e.first] += wt * e.second;
+                    if (row_of[ss] < 0) acc[m.gmap[ss]] += wt;
+                    else for (auto& e : rows[row_of[ss]]) acc[e.first] += wt * e.second;
                 }
+            row_of[s] = int32_t(rows.size());
+            rows.emplace_back();
             for (auto& e : acc)
-                if (e.second != 0.0) rows[s].push_back(e);
+                if (e.second != 0.0) rows.back().push_back(e);
             done[s] = 1;
         }
     // hanging rows (one per hanging point)
     m.hang_ptr.assign(size_t(m.n_hh) + 1, 0);
     for (int64_t hh = 0; hh < m.n_hh; ++hh) {
-        const Row& r = rows[hh_first[hh]];
+        const Row& r = rows[row_of[hh_first[hh]]];
         for (auto& e : r) { m.hang_src.push_back(e.first); m.hang_w.push_back(e.second); }
         m.hang_ptr[hh + 1] = int32_t(m.hang_src.size());
     }
@@ -428,7 +490,19 @@ int build_host_mesh(const MeshInput& in, HostMesh& m, std::string& err) {
     }
     // assembly CSR and horizontal lumped mass
     {
-        std::vector<std::vector<int32_t>> a(size_t(m.n_h)), ah(size_t(m.n_hh));
+        // CSR by counting (slots in increasing order within every node)
+        m.asm_ptr.assign(size_t(m.n_h) + 1, 0);
+        m.asmH_ptr.assign(size_t(m.n_hh) + 1, 0);
+        for (int32_t g : m.gmap) {
+            if (g >= 0) ++m.asm_ptr[size_t(g) + 1];
+            else ++m.asmH_ptr[size_t(-g - 1) + 1];
+        }
+        for (int64_t h = 0; h < m.n_h; ++h) m.asm_ptr[h + 1] += m.asm_ptr[h];
+        for (int64_t h = 0; h < m.n_hh; ++h) m.asmH_ptr[h + 1] += m.asmH_ptr[h];
+        m.asm_slot.assign(size_t(m.asm_ptr.back()), 0);
+        m.asmH_slot.assign(size_t(m.asmH_ptr.back()), 0);
+        std::vector<int32_t> fa(m.asm_ptr.begin(), m.asm_ptr.end() - 1);
+        std::vector<int32_t> fh(m.asmH_ptr.begin(), m.asmH_ptr.end() - 1);
         std::vector<double> mh(size_t(m.n_h), 0.0);
         for (int c = 0; c < in.n_col; ++c)
             for (int j = 0; j < np1; ++j)
@@ -436,22 +510,12 @@ int build_host_mesh(const MeshInput& in, HostMesh& m, std::string& err) {
                     size_t s = size_t(c) * np2 + i + np1 * j;
                     int32_t g = m.gmap[s];
                     double mass = B.w[i] * B.w[j] * 0.25 * m.col_dx[c] * m.col_dy[c];
-                    if (g >= 0) { a[g].push_back(int32_t(s)); mh[g] += mass; }
+                    if (g >= 0) { m.asm_slot[size_t(fa[g]++)] = int32_t(s); mh[g] += mass; }
                     else {
-                        ah[-g - 1].push_back(int32_t(s));
-                        for (auto& e : rows[s]) mh[e.first] += mass * e.second;
+                        m.asmH_slot[size_t(fh[-g - 1]++)] = int32_t(s);
+                        for (auto& e : rows[row_of[s]]) mh[e.first] += mass * e.second;
                     }
                 }
-        m.asm_ptr.assign(size_t(m.n_h) + 1, 0);
-        for (int64_t h = 0; h < m.n_h; ++h) {
-            m.asm_slot.insert(m.asm_slot.end(), a[h].begin(), a[h].end());
-            m.asm_ptr[h + 1] = int32_t(m.asm_slot.size());
-        }
-        m.asmH_ptr.assign(size_t(m.n_hh) + 1, 0);
-        for (int64_t h = 0; h < m.n_hh; ++h) {
-            m.asmH_slot.insert(m.asmH_slot.end(), ah[h].begin(), ah[h].end());
-            m.asmH_ptr[h + 1] = int32_t(m.asmH_slot.size());
-        }
         m.minv_h.resize(size_t(m.n_h));
         for (int64_t h = 0; h < m.n_h; ++h) {
             if (!(mh[h] > 0)) { err = "non-positive assembled mass"; return SEM_ERR_MESH; }
@@ -467,8 +531,8 @@ int build_host_mesh(const MeshInput& in, HostMesh& m, std::string& err) {
         int32_t ids[4];
         bool ok = true;
         for (int q = 0; q < 4 && ok; ++q) {
-            auto it = cmap.find({l, bx + (q & 1), by + (q >> 1)});
-            if (it == cmap.end()) ok = false; else ids[q] = it->second;
+            const int32_t id = cmap.find(lkey(l, bx + (q & 1)), by + (q >> 1));
+            if (id < 0) ok = false; else ids[q] = id;
         }
         if (ok) for (int q = 0; q < 4; ++q) m.sib[size_t(c) * 4 + q] = ids[q];
     }
