@@ -381,11 +381,15 @@ int build_host_mesh(const MeshInput& in, HostMesh& m, std::string& err) {
                             if (!ax.wrap(cxs[a], lc, cx) || !ay.wrap(cys[b2], lc, cy)) continue;
                             const int cc = cmap.find(lkey(lc, cx), cy);
                             if (cc < 0) continue;
-                            bool nx_ = false, ny_ = false;
-                            for (int t = 0; t < np1; ++t) {
-                                nx_ = nx_ || (kx_of(cc, t) == kx);
-                                ny_ = ny_ || (ky_of(cc, t) == ky);
-                            }
+                            // only the coarse column's lattice nodes (its edges and,
+                            // for even N, its middle) can coincide with a finer
+                            // column's position; its other keys carry its level
+                            auto lattice_node = [&](int64_t k, auto key_of) {
+                                if (!Axis::is_lattice(k)) return false;
+                                if (key_of(cc, 0) == k || key_of(cc, N) == k) return true;
+                                return N % 2 == 0 && key_of(cc, N / 2) == k;
+                            };
+                            const bool nx_ = lattice_node(kx, kx_of), ny_ = lattice_node(ky, ky_of);
                             if (nx_ && ny_) continue;   // a node of the coarse column
                             size_t s = size_t(c) * np2 + i + np1 * j;
                             src_col[s] = cc;
@@ -398,10 +402,13 @@ int build_host_mesh(const MeshInput& in, HostMesh& m, std::string& err) {
     }
     // ---- number unique nodes (first touch) and hanging points
     // keys of lattice positions are >= 0; interior LGL keys carry GLL_TAG (also >= 0)
-    // unique horizontal nodes: at most (N^2 + 2N + 1) per column, fewer when shared
+    // Positions strictly inside a column belong to that column alone (never
+    // shared, never hanging): they take the next id directly.  The others
+    // (4N per column) go through the table.
     size_t n_hang_slots = 0;
     for (int32_t sc : src_col) n_hang_slots += sc >= 0;
-    PairTable hid(size_t(in.n_col) * size_t(N * N + 2 * N + 1)), hhid(n_hang_slots);
+    PairTable hid(size_t(in.n_col) * size_t(4 * N)), hhid(n_hang_slots);
+    int32_t n_unique = 0;
     m.gmap.assign(size_t(in.n_col) * np2, 0);
     std::vector<size_t> hh_first;   // (c, pos) slot that defined each hanging point
     for (int c = 0; c < in.n_col; ++c)
@@ -411,10 +418,14 @@ int build_host_mesh(const MeshInput& in, HostMesh& m, std::string& err) {
                 Key2 k{kx_of(c, i), ky_of(c, j)};
                 double x = m.col_x0[c] + 0.5 * (1.0 + B.x[i]) * m.col_dx[c];
                 double y = m.col_y0[c] + 0.5 * (1.0 + B.x[j]) * m.col_dy[c];
-                bool ins;
+                bool ins = true;
                 if (src_col[s] < 0) {
-                    const int32_t id = hid.find_or_insert(k.kx, k.ky, int32_t(hid.size()), ins);
-                    if (ins) { m.h_xy.push_back(x); m.h_xy.push_back(y); }
+                    const bool inside = i > 0 && i < N && j > 0 && j < N;
+                    const int32_t id = inside ? n_unique : hid.find_or_insert(k.kx, k.ky, n_unique, ins);
+                    if (ins) {
+                        ++n_unique;
+                        m.h_xy.push_back(x); m.h_xy.push_back(y);
+                    }
                     m.gmap[s] = id;
                 } else {
                     const int32_t id = hhid.find_or_insert(k.kx, k.ky, int32_t(hhid.size()), ins);
@@ -428,7 +439,7 @@ int build_host_mesh(const MeshInput& in, HostMesh& m, std::string& err) {
     bool clash = false;
     hhid.for_each([&](int64_t a, int64_t b, int32_t) { clash = clash || hid.find(a, b) >= 0; });
     if (clash) { err = "a hanging point is also a conforming node"; return SEM_ERR_MESH; }
-    m.n_h = int64_t(hid.size());
+    m.n_h = int64_t(n_unique);
     m.n_hh = int64_t(hhid.size());
     if (m.n_h * int64_t(m.ldz) >= (int64_t(1) << 31) || m.n_hh * int64_t(m.ldz) >= (int64_t(1) << 31) ||
         int64_t(in.n_col) * in.n_z * np1 * np2 >= (int64_t(1) << 31)) {
