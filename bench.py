@@ -407,6 +407,9 @@ def main():
                     help="run only the forecaster experiment and print its JSON")
     ap.add_argument("--terrain-only", action="store_true",
                     help="run only the terrain-following measurement and print its JSON")
+    ap.add_argument("--terrain-case", default="both",
+                    help="with --terrain-only: a workload name, or both (the bench mesh and the "
+                         "two-level AMR mesh)")
     ap.add_argument("--tstar-only", action="store_true",
                     help="run only the time-to-solution study (uniform vs AMR by level) and print its JSON")
     ap.add_argument("--fc-case", default="vortex3_64x64x8_n4")
@@ -430,9 +433,12 @@ def main():
 
     dev = torch.device("cuda:0")
     if args.terrain_only:
-        print(json.dumps({"uniform": terrain_throughput(dev),
-                          "two_level_amr": terrain_throughput(dev, case_name="amr2_64x64x8_n4")}),
-              flush=True)
+        if args.terrain_case == "both":
+            out = {"uniform": terrain_throughput(dev),
+                   "two_level_amr": terrain_throughput(dev, case_name="amr2_64x64x8_n4")}
+        else:
+            out = terrain_throughput(dev, case_name=args.terrain_case)
+        print(json.dumps(out), flush=True)
         return
     if args.tstar_only:
         print(json.dumps(tstar_study(dev)), flush=True)
