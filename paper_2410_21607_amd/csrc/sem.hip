@@ -83,6 +83,7 @@ k_rhs(DevMesh m, const double* __restrict__ q, const double* __restrict__ hv,
     constexpr int N = NP - 1;
     __shared__ T tile[8][NP3];
     __shared__ T sD[NP2];
+    __shared__ double s_zs[NP2];          // terrain: surface height per position
     const int e = blockIdx.x;
     const int c = e / m.n_z, layer = e - c * m.n_z;
     const int t = threadIdx.x;
@@ -90,7 +91,14 @@ k_rhs(DevMesh m, const double* __restrict__ q, const double* __restrict__ hv,
     const int i = t % NP, j = (t / NP) % NP, k = t / NP2;
     const int kz = layer * N + k;
     const int64_t fs = int64_t(m.n_h) * m.ldz, fsh = int64_t(m.n_hh) * m.ldz;
+    const int64_t fsr = int64_t(m.n_h + m.n_hh) * m.ldz;   // terrain reference rows
+    const bool ter = m.zs != nullptr;
+    if (ter && t < NP2) {
+        const int gz = m.gmap[c * NP2 + t];
+        s_zs[t] = m.zs[gz >= 0 ? gz : m.n_h - gz - 1];
+    }
     T rp = 0, u = 0, v = 0, w = 0, tp = 0, rho = 1, rho_p = 0;
+    double dth0 = 0.0;
     if (t < NP3) {
         const int g = m.gmap[c * NP2 + i + NP * j];
         double x[NF];
@@ -101,7 +109,23 @@ k_rhs(DevMesh m, const double* __restrict__ q, const double* __restrict__ hv,
 #pragma unroll
             for (int f = 0; f < NF; ++f) x[f] = hv[f * fsh + int64_t(-g - 1) * m.ldz + kz];
         }
-        const double r0 = m.rho0[kz], th0 = m.theta0[kz];
+        // reference state: per vertical node, or per node with terrain (the
+        // hanging rows hold the coarse face's interpolant)
+        double r0, ir0, ith0, p0;
+        if (ter) {
+            const int64_t o = int64_t(g >= 0 ? g : m.n_h - g - 1) * m.ldz + kz;
+            r0 = m.ref_n[o];
+            ir0 = m.ref_n[fsr + o];
+            ith0 = m.ref_n[2 * fsr + o];
+            p0 = m.ref_n[3 * fsr + o];
+            dth0 = m.ref_n[4 * fsr + o];
+        } else {
+            r0 = m.rho0[kz];
+            ir0 = 1.0 / r0;
+            ith0 = 1.0 / m.theta0[kz];
+            p0 = m.p0[kz];
+            dth0 = m.dth0[kz];
+        }
         rp = T(x[0]); u = T(x[1]); v = T(x[2]); w = T(x[3]); tp = T(x[4]);
         rho_p = rp;
         rho = T(r0) + rp;
@@ -109,9 +133,9 @@ k_rhs(DevMesh m, const double* __restrict__ q, const double* __restrict__ hv,
         // the ideal-gas pressure minus the reference pressure, free of cancellation
         T pp;
         if constexpr (sizeof(T) == 8) {
-            pp = m.p0[kz] * expm1(m.gamma * (log1p(x[0] / r0) + log1p(x[4] / th0)));
+            pp = p0 * expm1(m.gamma * (log1p(x[0] * ir0) + log1p(x[4] * ith0)));
         } else {
-            pp = T(m.p0[kz]) * expm1f(T(m.gamma) * (log1pf(rp / T(r0)) + log1pf(tp / T(th0))));
+            pp = T(p0) * expm1f(T(m.gamma) * (log1pf(rp * T(ir0)) + log1pf(tp * T(ith0))));
         }
         tile[0][t] = rho * u;
         tile[1][t] = rho * v;
@@ -141,6 +165,25 @@ k_rhs(DevMesh m, const double* __restrict__ q, const double* __restrict__ hv,
     }
 #pragma unroll
     for (int a = 0; a < 8; ++a) { d[a][0] *= sx; d[a][1] *= sy; d[a][2] *= sz; }
+    // terrain-following mapping: d/dx = box d/dx + a_x d/dzf, d/dy likewise,
+    // d/dz = g_s d/dzf (g_s = 1/(1 - zs/(H - z0)), a_x = -g_s (H - zf)/(H - z0) dzs/dx)
+    double mfac = 1.0;
+    if (ter) {
+        double zx = 0.0, zy = 0.0;
+        for (int mm = 0; mm < NP; ++mm) {
+            zx += m.D[i * NP + mm] * s_zs[mm + NP * j];
+            zy += m.D[j * NP + mm] * s_zs[i + NP * mm];
+        }
+        mfac = 1.0 - s_zs[i + NP * j] * m.inv_depth;
+        const double gs = 1.0 / mfac, tg = m.tfac[kz] * gs;
+        const T ax = T(-tg * zx * m.col_sx[c]), ay = T(-tg * zy * m.col_sy[c]);
+#pragma unroll
+        for (int a = 0; a < 8; ++a) {
+            d[a][0] += ax * d[a][2];
+            d[a][1] += ay * d[a][2];
+            d[a][2] *= T(gs);
+        }
+    }
     const T f = T(m.f), g = T(m.g);
     const T inv_rho = T(1) / rho;
     T R[NF];
@@ -148,8 +191,8 @@ k_rhs(DevMesh m, const double* __restrict__ q, const double* __restrict__ hv,
     R[1] = -(u * d[3][0] + v * d[3][1] + w * d[3][2]) - d[6][0] * inv_rho + f * v;
     R[2] = -(u * d[4][0] + v * d[4][1] + w * d[4][2]) - d[6][1] * inv_rho - f * u;
     R[3] = -(u * d[5][0] + v * d[5][1] + w * d[5][2]) - d[6][2] * inv_rho - rho_p * inv_rho * g;
-    R[4] = -(u * d[7][0] + v * d[7][1] + w * d[7][2]) - w * T(m.dth0[kz]);
-    const double mass = m.w[i] * m.w[j] * m.w[k] * 0.125 * m.col_dx[c] * m.col_dy[c] * m.dz[layer];
+    R[4] = -(u * d[7][0] + v * d[7][1] + w * d[7][2]) - w * T(dth0);
+    const double mass = m.w[i] * m.w[j] * m.w[k] * 0.125 * m.col_dx[c] * m.col_dy[c] * m.dz[layer] * mfac;
     const int64_t es = int64_t(m.n_col) * m.n_z * NP3;
 #pragma unroll
     for (int fld = 0; fld < NF; ++fld) rE[fld * es + int64_t(e) * NP3 + t] = mass * double(R[fld]);
@@ -314,15 +357,25 @@ __global__ void k_finalize(DevMesh m, const double* __restrict__ acc, double* __
     for (int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; t < n;
          t += int64_t(gridDim.x) * blockDim.x) {
         const int h = int(t / m.nzn), kz = int(t % m.nzn);
-        const double minv = m.minv_h[h] * m.minv_v[kz];
-        const bool lid = (kz == 0) || (kz == m.nzn - 1);
+        const bool ter = m.zs != nullptr;
+        const double minv = (ter ? m.minv_ht[h] : m.minv_h[h]) * m.minv_v[kz];
+        // rigid lids; with terrain the surface keeps only the tangential part
+        // of the momentum tendency
+        const bool lid = ter ? (kz == m.nzn - 1) : (kz == 0 || kz == m.nzn - 1);
         const int64_t o = int64_t(h) * m.ldz + kz, fs = int64_t(m.n_h) * m.ldz;
+        double v[NF];
 #pragma unroll
-        for (int f = 0; f < NF; ++f) {
-            double v = acc[f * fs + o] * minv;
-            if (f == 3 && lid) v = 0.0;
-            r[f * fs + o] = v;
+        for (int f = 0; f < NF; ++f) v[f] = acc[f * fs + o] * minv;
+        if (ter && kz == 0) {
+            const double n0 = m.nrm[h], n1 = m.nrm[m.n_h + h], n2 = m.nrm[2 * m.n_h + h];
+            const double dn = v[1] * n0 + v[2] * n1 + v[3] * n2;
+            v[1] -= dn * n0;
+            v[2] -= dn * n1;
+            v[3] -= dn * n2;
         }
+        if (lid) v[3] = 0.0;
+#pragma unroll
+        for (int f = 0; f < NF; ++f) r[f * fs + o] = v[f];
     }
 }
 
@@ -802,7 +855,7 @@ int sem_nc_project(const sem_mesh* M, int dir, const double* src, double* dst, v
 int sem_rhs(const sem_mesh* M, const double* q, const double* hv, double* rE, int prec, void* stream) {
     int rc = check_mesh(M);
     if (rc != SEM_OK) return rc;
-    if ((rc = check_flat(M, "sem_rhs")) != SEM_OK) return rc;
+    if (M->d.zs && prec != SEM_FP64) return fail(SEM_ERR_STATE, "terrain needs SEM_FP64");
     if (!q || !rE || (M->d.n_hh > 0 && !hv)) return fail(SEM_ERR_ARG, "null array");
     return sem_launch_rhs(M, q, hv, rE, prec, (hipStream_t)stream);
 }
@@ -810,7 +863,6 @@ int sem_rhs(const sem_mesh* M, const double* q, const double* hv, double* rE, in
 int sem_dss(const sem_mesh* M, int phase, const double* rE, double* acc, double* c, double* r,
             void* stream) {
     if (!M) return fail(SEM_ERR_ARG, "null mesh");
-    if (check_flat(M, "sem_dss") != SEM_OK) return SEM_ERR_STATE;
     const DevMesh& d = M->d;
     hipStream_t s = (hipStream_t)stream;
     if (phase == SEM_ASSEMBLE) {

@@ -5,6 +5,8 @@ sem_mesh_set_terrain) against the oracle's mapped elements (oracle.terrain):
   a plane slope, uniform and 2:1 nonconforming meshes, N = 3 to 7, every
   supported chunk depth;
 * several SSP-RK3 stages;
+* the unfused calls (scatter, sem_rhs, assemble, gather, finalize) against
+  the oracle and against the fused stage;
 * flat terrain against the box-element stage;
 * the error paths (heights out of range, FP32, calls that only know box
   elements).
@@ -117,6 +119,34 @@ def test_terrain_rhs_matches_oracle_every_chunk_depth(name, kw, shape, periodic)
     assert tried >= 2
 
 
+@pytest.mark.parametrize("name,kw,shape,periodic", CASES[:4] + CASES[7:], ids=IDS[:4] + IDS[7:])
+def test_terrain_unfused_calls_match_oracle_and_fused_stage(name, kw, shape, periodic):
+    """sem_nc_project(SCATTER) -> sem_rhs -> sem_dss(ASSEMBLE) ->
+    sem_nc_project(GATHER) -> sem_dss(FINALIZE) over terrain."""
+    S = Setup(name, kw, shape, periodic)
+    torch, api = S.torch, S.api
+    say("terrain unfused", name, kw, shape)
+    n, nh, nl = S.gm.n_state, S.gm.n_hstate, 5 * S.gm.n_local
+    z = lambda k: torch.zeros(k, dtype=torch.float64, device="cuda")
+    hv, rE, acc, cH, r = z(nh), z(nl), z(n), z(nh), z(n)
+    if nh:
+        api.sem_nc_project(S.gm, api.SEM_SCATTER, S.q_g, hv)
+    api.sem_rhs(S.gm, S.q_g, hv if nh else None, rE)
+    api.sem_dss(S.gm, api.SEM_ASSEMBLE, rE=rE, acc=acc, c=cH if nh else None)
+    if nh:
+        api.sem_nc_project(S.gm, api.SEM_GATHER, cH, acc)
+    api.sem_dss(S.gm, api.SEM_FINALIZE, acc=acc, r=r)
+    torch.cuda.synchronize()
+    got = S.to_oracle_order(r)
+    err = metrics.rel_l2(got, S.oracle_rhs(S.q_or), metrics.RHS_FLOORS)
+    say("  rel vs oracle", err)
+    assert err.max() <= TOL64
+    fused = S.gpu_rhs()
+    errf = metrics.rel_l2(got, fused, metrics.RHS_FLOORS)
+    say("  rel vs fused", errf)
+    assert errf.max() <= 1e-13
+
+
 @pytest.mark.parametrize("name,kw,shape,periodic", CASES[:3], ids=IDS[:3])
 def test_terrain_stages_match_oracle(name, kw, shape, periodic):
     S = Setup(name, kw, shape, periodic)
@@ -185,7 +215,7 @@ def test_terrain_error_paths():
     assert e.value.code == -5
     rE = torch.zeros(5 * gm.n_local, dtype=torch.float64, device="cuda")
     with pytest.raises(native.SemError) as e:
-        api.sem_rhs(gm, q, None, rE)
+        api.sem_rhs(gm, q, None, rE, api.SEM_FP32)
     assert e.value.code == -5
     with pytest.raises(native.SemError) as e:
         gm.set_dissipation(0.21, 0.0, 4000.0)
