@@ -185,8 +185,9 @@ int sem_mesh_set_dissipation(sem_mesh *mesh, double Cs, double sponge_gamma,
  * zs = 0) reproduces the box-element stage.
  * sem_rhs (element contributions with the mapped masses) and sem_dss
  * (FINALIZE: the terrain inverse mass, the surface rule and the top lid) do
- * the same per call.  Limits: FP64 only; while terrain is set, amr_flag,
- * amr_features, the dissipation and SEM_FP32 calls return SEM_ERR_STATE.
+ * the same per call, and amr_flag takes the vorticity criterion through the
+ * same chain rule.  Limits: FP64 only; while terrain is set, amr_features,
+ * the dissipation and SEM_FP32 calls return SEM_ERR_STATE.
  * h_zs = NULL removes the terrain.  Arrays are copied; synchronises the
  * device.  Errors: SEM_ERR_ARG (null mesh, zs out of range, non-positive
  * reference), SEM_ERR_MESH (non-positive assembled mass), SEM_ERR_STATE

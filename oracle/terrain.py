@@ -168,3 +168,13 @@ def node_heights(mesh, zsG):
     z0, H = mesh.z_edges[0], mesh.z_edges[-1]
     zf = mesh.node_xyz[:, 2]
     return zf + np.asarray(zsG, dtype=np.float64) * (H - zf) / (H - z0)
+
+
+def criterion_vorticity(mesh, qL, zsG):
+    """Vertical relative vorticity dv/dx - du/dy at every local node of the
+    mapped elements (element-local values, as the refinement criterion of
+    Section 4.1 reads them), by the chain rule of the mapping."""
+    _, Jinv, _ = jacobian(mesh, physical_z(mesh, zsG))
+    vx, _, _ = gradient(mesh, Jinv, qL[2])
+    _, uy, _ = gradient(mesh, Jinv, qL[1])
+    return vx - uy

@@ -395,11 +395,16 @@ k_amr_elem(DevMesh m, const double* __restrict__ q, int criterion, Thr thr, int 
     constexpr int NP2 = NP * NP, NP3 = NP2 * NP, N = NP - 1;
     __shared__ double su[NP3], sv[NP3];
     __shared__ double red[1024 / 64];
+    __shared__ double s_zs[NP2];          // terrain: surface height per position
     const int e = blockIdx.x;
     const int c = e / m.n_z, layer = e - c * m.n_z;
     const int t = threadIdx.x;
     const int i = t % NP, j = (t / NP) % NP, k = t / NP2;
     const int kz = layer * N + k;
+    if (m.zs && t < NP2) {
+        const int gz = m.gmap[c * NP2 + t];
+        s_zs[t] = m.zs[gz >= 0 ? gz : m.n_h - gz - 1];
+    }
     double u = 0, v = 0, w = 0;
     if (t < NP3) {
         const int g = m.gmap[c * NP2 + i + NP * j];
@@ -421,6 +426,20 @@ k_amr_elem(DevMesh m, const double* __restrict__ q, int criterion, Thr thr, int 
                 uy += m.D[j * NP + mm] * su[i + NP * (mm + NP * k)];
             }
             C = vx * (2.0 / m.col_dx[c]) - uy * (2.0 / m.col_dy[c]);
+            if (m.zs) {
+                // terrain-following mapping: d/dx = box d/dx + a_x d/dzf, d/dy likewise
+                double vz = 0, uz = 0, zx = 0, zy = 0;
+                for (int mm = 0; mm < NP; ++mm) {
+                    vz += m.D[k * NP + mm] * sv[i + NP * (j + NP * mm)];
+                    uz += m.D[k * NP + mm] * su[i + NP * (j + NP * mm)];
+                    zx += m.D[i * NP + mm] * s_zs[mm + NP * j];
+                    zy += m.D[j * NP + mm] * s_zs[i + NP * mm];
+                }
+                const double sz = 2.0 / m.dz[layer];
+                const double tg = m.tfac[kz] / (1.0 - s_zs[i + NP * j] * m.inv_depth);
+                const double ax = -tg * zx * (2.0 / m.col_dx[c]), ay = -tg * zy * (2.0 / m.col_dy[c]);
+                C += ax * vz * sz - ay * uz * sz;
+            }
         }
     }
     // workgroup maximum
@@ -504,12 +523,6 @@ int check_mesh(const sem_mesh* M) {
     return SEM_OK;
 }
 
-// calls that only know box elements
-int check_flat(const sem_mesh* M, const char* what) {
-    if (M && M->d.zs)
-        return fail(SEM_ERR_STATE, std::string(what) + " does not support terrain (use sem_stage)");
-    return SEM_OK;
-}
 
 }  // namespace
 
@@ -1019,7 +1032,6 @@ int sem_stage_get_tune(const sem_mesh* M, int* layers_per_chunk) {
 int amr_flag(const sem_mesh* M, const double* q, int criterion, const double* thr, int lvl_max,
              int8_t* ae, int8_t* ac, void* stream) {
     if (!M) return fail(SEM_ERR_ARG, "null mesh");
-    if (check_flat(M, "amr_flag") != SEM_OK) return SEM_ERR_STATE;
     if (!q || !ae || !ac) return fail(SEM_ERR_ARG, "null array");
     if (criterion != SEM_CRIT_SPEED && criterion != SEM_CRIT_VORTZ) return fail(SEM_ERR_ARG, "bad criterion");
     if (lvl_max < 0 || lvl_max > SEM_MAX_LEVEL) return fail(SEM_ERR_ARG, "lvl_max out of range");

@@ -8,6 +8,7 @@ sem_mesh_set_terrain) against the oracle's mapped elements (oracle.terrain):
 * the unfused calls (scatter, sem_rhs, assemble, gather, finalize) against
   the oracle and against the fused stage;
 * flat terrain against the box-element stage;
+* the refinement flags over terrain (both criteria, bit-exact);
 * the error paths (heights out of range, FP32, calls that only know box
   elements).
 
@@ -19,7 +20,8 @@ import numpy as np
 import pytest
 
 from harness import match, oracle_mesh
-from oracle import metrics, timestep
+from oracle import amr as oamr
+from oracle import assembly, metrics, timestep
 from oracle import terrain as oterrain
 from synth import cases
 
@@ -168,6 +170,37 @@ def test_terrain_stages_match_oracle(name, kw, shape, periodic):
     assert err.max() <= TOL64
 
 
+@pytest.mark.parametrize("name,kw,shape,periodic", [CASES[0], CASES[1], CASES[2], CASES[4]],
+                         ids=[IDS[0], IDS[1], IDS[2], IDS[4]])
+@pytest.mark.parametrize("criterion", [0, 1])
+def test_terrain_amr_flag_bit_exact(name, kw, shape, periodic, criterion):
+    """The refinement flags over terrain: |u| needs no metric; the vorticity
+    takes the chain rule of the mapping (oracle: full inverse Jacobian)."""
+    S = Setup(name, kw, shape, periodic)
+    torch, api = S.torch, S.api
+    say("terrain amr_flag", name, kw, shape, criterion)
+    qL = assembly.scatter(S.om, S.q_or)
+    C = oamr.criterion_speed(qL) if criterion == 0 else oterrain.criterion_vorticity(S.om, qL, S.zs)
+    cmax = np.sort(C.reshape(S.om.n_elem, -1).max(axis=1))
+    lvl = S.om.e_level
+    lvl_max = int(lvl.max()) + 1
+    # thresholds half-way across gaps between element maxima that are wide
+    # compared with round-off
+    gaps = np.nonzero(np.diff(cmax) > 1e-8 * np.abs(cmax).max())[0]
+    picks = np.linspace(0.2, 0.8, lvl_max)
+    sel = gaps[np.clip((picks * (len(gaps) - 1)).astype(int), 0, len(gaps) - 1)]
+    thr = np.sort(0.5 * (cmax[sel] + cmax[sel + 1]))
+    ef = oamr.element_flags(C.reshape(S.om.n_elem, -1), lvl, thr, lvl_max)
+    cf = oamr.column_flags(ef, S.c["columns"], S.om.n_z)
+    ae = torch.zeros(S.gm.info["n_elem"], dtype=torch.int8, device="cuda")
+    ac = torch.zeros(S.gm.info["n_col"], dtype=torch.int8, device="cuda")
+    api.amr_flag(S.gm, S.q_g, criterion, thr, lvl_max, ae, ac)
+    torch.cuda.synchronize()
+    assert np.array_equal(ae.cpu().numpy(), ef)
+    assert np.array_equal(ac.cpu().numpy(), cf)
+    assert len(set(ef.tolist())) >= 2
+
+
 def test_flat_terrain_matches_the_box_element_stage():
     import torch
     from paper_2410_21607_amd import api
@@ -220,8 +253,10 @@ def test_terrain_error_paths():
     with pytest.raises(native.SemError) as e:
         gm.set_dissipation(0.21, 0.0, 4000.0)
     assert e.value.code == -5
-    ae = torch.zeros(gm.info["n_elem"], dtype=torch.int8, device="cuda")
-    ac = torch.zeros(gm.info["n_col"], dtype=torch.int8, device="cuda")
-    with pytest.raises(native.SemError) as e:
-        api.amr_flag(gm, q, 0, [7.5], 1, ae, ac)
+    ne = gm.info["n_elem"]
+    feat = torch.zeros(ne * 16, dtype=torch.float32, device="cuda")
+    dem = torch.zeros(ne, dtype=torch.int8, device="cuda")
+    plain = torch.zeros(ne, dtype=torch.int8, device="cuda")
+    with pytest.raises(native.SemError) as e:    # features take box-metric derivatives
+        api.amr_features(gm, q, q, plain, 1, [1e-4], 1, np.ones(16), feat, dem)
     assert e.value.code == -5

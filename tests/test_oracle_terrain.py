@@ -216,3 +216,23 @@ def test_balanced_state_over_hills_converges_spectrally():
     assert res_w[-1] < 1e-5 * res_w[0]
     assert res_h[-1] < 1e-3 * res_h[0]                   # pressure-gradient error: 3e-3 -> 4e-7
     assert np.all(np.diff(np.log(res_h)) < 0)           # decays at every order
+
+
+def test_terrain_vorticity_of_solid_body_rotation_and_sheared_wind():
+    """u = -W y, v = W x has vorticity 2W everywhere, over any terrain; and a
+    wind v = a z (linear in the physical height) has none, although in the
+    terrain-following coordinates v varies along x over a slope."""
+    c = cases.get("small_amr3", N=4, periodic=False)
+    m = build(c)
+    W = 3e-4
+    q = np.zeros((5, m.n_dof))
+    q[1] = -W * m.node_xyz[:, 1]
+    q[2] = W * m.node_xyz[:, 0]
+    zs = hills(c)(m.node_xyz[:, 0], m.node_xyz[:, 1])
+    zeta = terrain.criterion_vorticity(m, assembly.scatter(m, q), zs)
+    assert np.abs(zeta - 2 * W).max() < 1e-9 * W
+    zs = 0.004 * (m.node_xyz[:, 0] + 0.5 * c["Lx"])
+    q = np.zeros((5, m.n_dof))
+    q[2] = 1e-3 * terrain.node_heights(m, zs)
+    zeta = terrain.criterion_vorticity(m, assembly.scatter(m, q), zs)
+    assert np.abs(zeta).max() < 1e-12
