@@ -15,8 +15,9 @@ Every ``interval`` RK3 steps the run reaches a boundary.  There:
    b. ``sem_adapt_columns`` (host) gives the new layout (split, 2:1 balance,
       merge);
    c. a new mesh handle over it, its reference state (the vertical structure
-      is unchanged, so the same per-level arrays are reused), the transfer
-      rows and one ``sem_transfer_apply`` launch;
+      is unchanged, so the same per-level arrays are reused; over terrain the
+      ``terrain`` hook gives the surface heights and the per-node reference of
+      the new mesh), the transfer rows and one ``sem_transfer_apply`` launch;
    d. a new ``Stepper`` (HIP graphs recaptured for the new mesh).
 
 The state at the previous boundary is kept on the current mesh
@@ -37,11 +38,15 @@ class AdaptiveRun:
     def __init__(self, mesh, q0, dt, reference, criterion, thresholds, lvl_max,
                  interval, precision=api.SEM_FP64, graph=True, layers_per_chunk=0,
                  forecaster=None, rebuild_every=1, on_boundary=None, wind_box=None,
-                 adapt=True):
+                 adapt=True, terrain=None):
         """mesh: api.Mesh; q0: padded state tensor on it; reference: tuple of
         (rho0, theta0, dtheta0dz) per vertical node (already set on mesh);
         wind_box: (x0, x1, y0, y1) of the maximum-wind diagnostic (default:
-        the whole domain); adapt=False keeps the mesh fixed (diagnostics only)."""
+        the whole domain); adapt=False keeps the mesh fixed (diagnostics only);
+        terrain: optional callable mesh -> (zs per horizontal node, rho0,
+        theta0, dtheta0dz per node), applied to every new mesh (the caller
+        sets it on the first one).  The solution moves between layouts in the
+        terrain-following coordinates."""
         self.mesh = mesh
         self.dt = float(dt)
         self.reference = tuple(np.asarray(a, dtype=np.float64) for a in reference)
@@ -56,6 +61,7 @@ class AdaptiveRun:
         self.rebuild_every = max(1, int(rebuild_every))
         self.adapt_enabled = bool(adapt)
         self.on_boundary = on_boundary
+        self.terrain = terrain
         p = mesh.params
         self.wind_box = wind_box or (-0.5 * p["Lx"], 0.5 * p["Lx"], -0.5 * p["Ly"], 0.5 * p["Ly"])
         self.timings = dict(step=0.0, flag=0.0, forecast=0.0, layout=0.0, mesh=0.0,
@@ -132,6 +138,8 @@ class AdaptiveRun:
             return False
         new = self.mesh.with_columns(cols)
         new.set_reference(*self.reference)
+        if self.terrain is not None:
+            new.set_terrain(*self.terrain(new))
         T = api.Transfer(self.mesh, new)
         t3 = time.perf_counter()
         self.timings["mesh"] += t3 - t2
