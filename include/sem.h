@@ -159,7 +159,9 @@ int sem_mesh_set_reference(sem_mesh *mesh, const double *h_rho0,
  * terms) and assembled with the same direct stiffness summation.  In
  * sem_stage they run as a pre-pass whose assembled tendency the column pass
  * adds.  Enabling allocates the pre-pass buffers once (5 element-local and 2
- * state arrays); compute calls never allocate.  Synchronises the device. */
+ * state arrays); compute calls never allocate.  Synchronises the device.
+ * Compute calls read the settings when they are enqueued: a HIP graph
+ * captured before this call keeps replaying the previous ones. */
 int sem_mesh_set_dissipation(sem_mesh *mesh, double Cs, double sponge_gamma,
                              double sponge_depth);
 
@@ -188,7 +190,9 @@ int sem_mesh_set_dissipation(sem_mesh *mesh, double Cs, double sponge_gamma,
  * the same per call, and amr_flag takes the vorticity criterion through the
  * same chain rule.  Limits: FP64 only; while terrain is set, amr_features,
  * the dissipation and SEM_FP32 calls return SEM_ERR_STATE.
- * h_zs = NULL removes the terrain.  Arrays are copied; synchronises the
+ * h_zs = NULL removes the terrain.  As for the dissipation, a HIP graph
+ * captured before this call keeps the previous geometry: capture after it.
+ * Arrays are copied; synchronises the
  * device.  Errors: SEM_ERR_ARG (null mesh, zs out of range, non-positive
  * reference), SEM_ERR_MESH (non-positive assembled mass), SEM_ERR_STATE
  * (dissipation enabled), SEM_ERR_HIP. */
