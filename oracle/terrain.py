@@ -68,21 +68,29 @@ def jacobian(mesh, zp):
 
 
 def gradient(mesh, Jinv, f):
-    """Physical gradient (d/dx, d/dy, d/dz) of local fields by the chain rule."""
-    D = derivative_matrix(mesh.N)
+    """Physical gradient (d/dx, d/dy, d/dz) of local fields by the chain rule,
+    in the precision of f (Jinv is expected in the same precision)."""
+    D = derivative_matrix(mesh.N).astype(np.asarray(f).dtype)
     r = reference_derivatives(D, f)
     return tuple(sum(Jinv[..., b, a] * r[b] for b in range(3)) for a in range(3))
 
 
-def element_rhs(mesh, qL, refL, Jinv, phys):
+def element_rhs(mesh, qL, refL, Jinv, phys, dtype=np.float64):
     """Strong-form right-hand side of Section 2 on mapped elements.
 
     The same pointwise terms as ``oracle.euler.element_rhs``, with every
     derivative taken by ``gradient``.  refL: local rho0, theta0, dtheta0dz.
-    Returns R_L, shape (5, E, n, n, n)."""
+    dtype: float64, or float32 for the reduced-precision variant, as in
+    ``oracle.euler.element_rhs``: state, reference, inverse Jacobian, the
+    derivatives and the pointwise terms are float32 arrays (p' is the exact
+    difference rounded to float32); the caller's assembly stays FP64.
+    Returns R_L, shape (5, E, n, n, n), float64."""
     rho0, theta0, dth0 = refL["rho0"], refL["theta0"], refL["dtheta0dz"]
     pp = euler.pressure_perturbation(rho0, theta0, qL[0], qL[4],
-                                     phys["R_d"], phys["c_p"], phys["p00"])
+                                     phys["R_d"], phys["c_p"], phys["p00"]).astype(dtype)
+    qL = np.asarray(qL).astype(dtype)
+    rho0, dth0 = np.asarray(rho0).astype(dtype), np.asarray(dth0).astype(dtype)
+    Jinv = np.asarray(Jinv).astype(dtype)
     rho_p, u, v, w, th_p = qL
     rho = rho0 + rho_p
     grad = lambda f: gradient(mesh, Jinv, f)
@@ -94,14 +102,14 @@ def element_rhs(mesh, qL, refL, Jinv, phys):
     wx, wy, wz = grad(w)
     px, py, pz = grad(pp)
     tx, ty, tz = grad(th_p)
-    f, g = phys["f"], phys["g"]
+    f, g = dtype(phys["f"]), dtype(phys["g"])
     R = np.empty_like(qL)
     R[0] = -(mx + my + mz)
     R[1] = -(u * ux + v * uy + w * uz) - px / rho + f * v
     R[2] = -(u * vx + v * vy + w * vz) - py / rho - f * u
     R[3] = -(u * wx + v * wy + w * wz) - pz / rho - (rho_p / rho) * g
     R[4] = -(u * tx + v * ty + w * tz) - w * dth0
-    return R
+    return R.astype(np.float64)
 
 
 def lumped_mass(mesh, detJ):
@@ -140,18 +148,19 @@ def surface_normal(mesh, zsG, Jinv, mL, MG):
     return np.stack([nx / nrm, ny / nrm, 1.0 / nrm]), bot
 
 
-def rhs(mesh, qG, refG, zsG, phys):
+def rhs(mesh, qG, refG, zsG, phys, dtype=np.float64):
     """Global right-hand side on the terrain-following mesh.
 
     qG: (5, n_dof) state; refG: dict of rho0, theta0, dtheta0dz per unique
-    node (at each node's physical height); zsG: surface height per unique node.
+    node (at each node's physical height); zsG: surface height per unique node;
+    dtype: precision of the element arithmetic (``element_rhs``).
     Scatter, mapped element RHS, mass-weighted gather, boundary rules."""
     zp = physical_z(mesh, zsG)
     _, Jinv, detJ = jacobian(mesh, zp)
     qL = assembly.scatter(mesh, qG)
     refL = {k: assembly.scatter(mesh, np.asarray(refG[k], dtype=np.float64)[None])[0]
             for k in ("rho0", "theta0", "dtheta0dz")}
-    RL = element_rhs(mesh, qL, refL, Jinv, phys)
+    RL = element_rhs(mesh, qL, refL, Jinv, phys, dtype)
     mL, MG = lumped_mass(mesh, detJ)
     RG = assembly.assemble(mesh, RL.reshape(5, -1) * mL[None]) / MG[None]
     # top: rigid lid
