@@ -186,6 +186,16 @@ def terrain_throughput(device, flat_ms=None, case_name=WORKLOAD, amp=2000.0, hal
     xyz[:, 2] = zp
     q0 = mesh.unpack(cases.initial_state(case, xyz), device=device)
     t, q = timed_run(mesh, q0, case["dt"], api.SEM_FP64, n_steps)
+    lpc64 = api.sem_stage_get_tune(mesh)
+    # reduced precision over the same terrain: after the same number of stages,
+    # the floor-scaled deviation from the FP64 run
+    t32, q32 = timed_run(mesh, q0, case["dt"], api.SEM_FP32, n_steps)
+    d32 = np.abs(mesh.pack(q32) - mesh.pack(q)).max(axis=1) / np.array([1e-3, 1.0, 1.0, 1.0, 0.1])
+    fp32 = {"ms_per_stage": t32 * 1e3, "dof_stage_per_s": mesh.n_dof / t32,
+            "layers_per_chunk": api.sem_stage_get_tune(mesh),
+            "max_floor_scaled_deviation_from_fp64": [float(x) for x in d32],
+            "stages": 3 * n_steps, "finite": bool(torch.isfinite(q32).all().item())}
+    del q32
     per_node = sum(algorithmic_bytes(1, s) for s in range(3)) / 3.0 + 5 * 8
     achieved = mesh.n_dof * per_node / t / 1e9
     if flat_ms is None:
@@ -202,11 +212,12 @@ def terrain_throughput(device, flat_ms=None, case_name=WORKLOAD, amp=2000.0, hal
            "mountain": {"height_m": amp, "half_width_m": half_width},
            "n_dof": int(mesh.n_dof), "ms_per_stage": t * 1e3,
            "dof_stage_per_s": mesh.n_dof / t,
-           "layers_per_chunk": api.sem_stage_get_tune(mesh),
+           "layers_per_chunk": lpc64,
            "algorithmic_bytes_per_node_stage": per_node,
            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                         "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS},
-           "finite": bool(torch.isfinite(q).all().item())}
+           "finite": bool(torch.isfinite(q).all().item()),
+           "fp32": fp32}
     if flat_ms:
         out["cost_ratio_over_flat"] = t * 1e3 / flat_ms
     del mesh, q0, q

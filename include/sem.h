@@ -73,6 +73,7 @@ extern "C" {
 
 #define SEM_FP64 0        /* all arithmetic in double                        */
 #define SEM_FP32 1        /* element arithmetic in float on perturbations;   */
+                          /* p' is evaluated in double and rounded once;     */
                           /* assembly, mass and stage update stay double     */
 
 #define SEM_SCATTER 0     /* sem_nc_project: unique nodes -> hanging points  */
@@ -188,8 +189,10 @@ int sem_mesh_set_dissipation(sem_mesh *mesh, double Cs, double sponge_gamma,
  * sem_rhs (element contributions with the mapped masses) and sem_dss
  * (FINALIZE: the terrain inverse mass, the surface rule and the top lid) do
  * the same per call, and amr_flag takes the vorticity criterion through the
- * same chain rule.  Limits: FP64 only; while terrain is set, amr_features,
- * the dissipation and SEM_FP32 calls return SEM_ERR_STATE.
+ * same chain rule.  SEM_FP32 (sem_stage, sem_rhs) keeps the metric factors
+ * in FP64 and rounds them to float with the rest of the element arithmetic.
+ * Limits: while terrain is set, amr_features and the dissipation return
+ * SEM_ERR_STATE.
  * h_zs = NULL removes the terrain.  As for the dissipation, a HIP graph
  * captured before this call keeps the previous geometry: capture after it.
  * Arrays are copied; synchronises the

@@ -130,13 +130,10 @@ k_rhs(DevMesh m, const double* __restrict__ q, const double* __restrict__ hv,
         rho_p = rp;
         rho = T(r0) + rp;
         // p' = p0 expm1(gamma (log1p(rho'/rho0) + log1p(theta'/theta0))):
-        // the ideal-gas pressure minus the reference pressure, free of cancellation
-        T pp;
-        if constexpr (sizeof(T) == 8) {
-            pp = p0 * expm1(m.gamma * (log1p(x[0] * ir0) + log1p(x[4] * ith0)));
-        } else {
-            pp = T(p0) * expm1f(T(m.gamma) * (log1pf(rp * T(ir0)) + log1pf(tp * T(ith0))));
-        }
+        // the ideal-gas pressure minus the reference pressure, free of
+        // cancellation; in FP64 for both precisions, rounded once (the
+        // hydrostatic balance in the w tendency cancels most of dp'/dz)
+        const T pp = T(p0 * expm1(m.gamma * (log1p(x[0] * ir0) + log1p(x[4] * ith0))));
         tile[0][t] = rho * u;
         tile[1][t] = rho * v;
         tile[2][t] = rho * w;
@@ -868,7 +865,6 @@ int sem_nc_project(const sem_mesh* M, int dir, const double* src, double* dst, v
 int sem_rhs(const sem_mesh* M, const double* q, const double* hv, double* rE, int prec, void* stream) {
     int rc = check_mesh(M);
     if (rc != SEM_OK) return rc;
-    if (M->d.zs && prec != SEM_FP64) return fail(SEM_ERR_STATE, "terrain needs SEM_FP64");
     if (!q || !rE || (M->d.n_hh > 0 && !hv)) return fail(SEM_ERR_ARG, "null array");
     return sem_launch_rhs(M, q, hv, rE, prec, (hipStream_t)stream);
 }
@@ -911,7 +907,6 @@ int sem_stage(const sem_mesh* M, double a, double b, double c, const double* qn,
     if (!qn || !qs || !qout) return fail(SEM_ERR_ARG, "null array");
     if (qout == qs || qout == qn) return fail(SEM_ERR_ARG, "qout must not alias qs or qn");
     if (prec != SEM_FP64 && prec != SEM_FP32) return fail(SEM_ERR_ARG, "bad precision");
-    if (M->d.zs && prec != SEM_FP64) return fail(SEM_ERR_STATE, "terrain needs SEM_FP64");
     if (dissipation_on(M) && (rc = dissip_prepass(M, qs, (hipStream_t)stream)) != SEM_OK) return rc;
     rc = sem::fused_stage_launch(M->d, M->fused, a, b, c, qn, qs, qout, prec, (hipStream_t)stream);
     if (rc != SEM_OK) return fail(rc, "fused stage launch failed");
@@ -984,7 +979,6 @@ int sem_stage_autotune(sem_mesh* M, const double* qn, const double* qs, double* 
     if (!qn || !qs || !qout) return fail(SEM_ERR_ARG, "null array");
     if (qout == qs || qout == qn) return fail(SEM_ERR_ARG, "qout must not alias qs or qn");
     if (prec != SEM_FP64 && prec != SEM_FP32) return fail(SEM_ERR_ARG, "bad precision");
-    if (M->d.zs && prec != SEM_FP64) return fail(SEM_ERR_STATE, "terrain needs SEM_FP64");
     if (reps < 1) reps = 5;
     hipStream_t s = (hipStream_t)stream;
     hipEvent_t e0, e1;

@@ -58,19 +58,14 @@ constexpr int wg_threads() {
 __device__ __noinline__ double pow1p_minus1_far(double x, double gamma) {
     return expm1(gamma * log1p(x));
 }
-__device__ __noinline__ float pow1p_minus1_far(float x, float gamma) {
-    return expm1f(gamma * log1pf(x));
-}
-
-template <typename T>
-__device__ __forceinline__ T pow1p_minus1(const DevMesh& m, T x) {
-    if (fabs(x) <= T(1.0 / 64.0)) {
-        T s = T(m.binom[10]);
+__device__ __forceinline__ double pow1p_minus1(const DevMesh& m, double x) {
+    if (fabs(x) <= 1.0 / 64.0) {
+        double s = m.binom[10];
 #pragma unroll
-        for (int n = 9; n >= 1; --n) s = s * x + T(m.binom[n]);
+        for (int n = 9; n >= 1; --n) s = s * x + m.binom[n];
         return s * x;
     }
-    return pow1p_minus1_far(x, T(m.gamma));
+    return pow1p_minus1_far(x, m.gamma);
 }
 
 // At least four waves per SIMD: two workgroups share a CU, so that one can
@@ -78,7 +73,7 @@ __device__ __forceinline__ T pow1p_minus1(const DevMesh& m, T x) {
 // loads of a chunk are issued one phase early: while the derivatives of chunk
 // ch run, the update base of its nodes, the next chunk's q_s (direct nodes)
 // and the next chunk's slice of the per-level tables are already in flight.
-// TER: terrain-following coordinates (FP64 only).  The columns keep their
+// TER: terrain-following coordinates.  The columns keep their
 // horizontal boxes; with g_s = 1/(1 - zs/(H - z0)) per position and
 // t_f = (H - zf)/(H - z0) per level, the chain rule of the mapping gives, with
 // d/dzf the box derivative 2/dz d/dzeta,
@@ -274,9 +269,13 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
             tile[5][lidx] = w;
             {
                 // p' = p0 ((rho theta)/(rho0 theta0))^gamma - p0 with x = a + b + a b,
-                // a = rho'/rho0, b = theta'/theta0 (no cancellation against p0)
-                const T ra = T(qv[0] * irho0), tb = T(qv[4] * ith0);
-                tile[6][lidx] = T(p0v) * pow1p_minus1<T>(m, ra + tb + ra * tb);
+                // a = rho'/rho0, b = theta'/theta0 (no cancellation against p0).
+                // Evaluated in FP64 from the FP64 state in both precisions and
+                // rounded once: the hydrostatic balance in the w tendency
+                // cancels most of dp'/dz, so a float evaluation's few-ulp error
+                // would dominate the float variant's error there.
+                const double ra = qv[0] * irho0, tb = qv[4] * ith0;
+                tile[6][lidx] = T(p0v * pow1p_minus1(m, ra + tb + ra * tb));
             }
             tile[7][lidx] = T(qv[4]);
         }
@@ -627,8 +626,8 @@ int fused_stage_launch(const DevMesh& m, const FusedPlan& P, double a, double b,
         if (ncol == 0) continue;
         int rc;
         if (m.zs) {
-            if (prec != SEM_FP64) return SEM_ERR_ARG;
-            rc = launch_t<double, true>(m, t, col0, ncol, a, b, c, qn, qs, qo, s);
+            rc = (prec == SEM_FP32) ? launch_t<float, true>(m, t, col0, ncol, a, b, c, qn, qs, qo, s)
+                                    : launch_t<double, true>(m, t, col0, ncol, a, b, c, qn, qs, qo, s);
         } else {
             rc = (prec == SEM_FP32) ? launch_t<float, false>(m, t, col0, ncol, a, b, c, qn, qs, qo, s)
                                     : launch_t<double, false>(m, t, col0, ncol, a, b, c, qn, qs, qo, s);

@@ -1,8 +1,10 @@
 """Reduced-precision variant against the oracle's own float32 mode: the GPU
 FP32 error (element arithmetic in float32, assembly and update in FP64)
-relative to the FP64 oracle must stay within four times the error of the
-oracle evaluating the same steps in float32, field by field, for one
-right-hand side and after three stages."""
+relative to the FP64 oracle must stay within twice the error of the oracle
+evaluating the same steps in float32, field by field, for one right-hand side
+and after three stages.  Both round p' once from its FP64 value and then take
+the same float32 steps, so the two errors differ only by the order of the
+roundings in the sums (observed ratio 0.85-1.04)."""
 
 import sys
 
@@ -23,7 +25,7 @@ def say(*a):
 
 @pytest.mark.parametrize("name,kw", [("vortex_8x8x4_n4", {}), ("small_amr3", {}),
                                      ("small_amr2", {"N": 7})])
-def test_fp32_within_four_times_oracle_fp32(name, kw):
+def test_fp32_within_twice_oracle_fp32(name, kw):
     import torch
     from paper_2410_21607_amd import api
     c = cases.get(name, **kw)
@@ -49,7 +51,7 @@ def test_fp32_within_four_times_oracle_fp32(name, kw):
     e_gpu = metrics.rel_l2(got, want, metrics.RHS_FLOORS)
     e_or = metrics.rel_l2(ref32, want, metrics.RHS_FLOORS)
     say("  rhs  gpu", e_gpu, "oracle fp32", e_or)
-    assert np.all(e_gpu <= 4.0 * e_or + 1e-13)
+    assert np.all(e_gpu <= 2.0 * e_or + 1e-13)
     # three stages
     w64, _ = timestep.run_stages(f64, q, c["dt"], 3)
     w32, _ = timestep.run_stages(f32, q, c["dt"], 3)
@@ -64,4 +66,4 @@ def test_fp32_within_four_times_oracle_fp32(name, kw):
     e_gpu = metrics.rel_l2(got, w64, metrics.STATE_FLOORS)
     e_or = metrics.rel_l2(w32, w64, metrics.STATE_FLOORS)
     say("  3 stages gpu", e_gpu, "oracle fp32", e_or)
-    assert np.all(e_gpu <= 4.0 * e_or + 1e-15)
+    assert np.all(e_gpu <= 2.0 * e_or + 1e-15)
