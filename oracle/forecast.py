@@ -7,7 +7,9 @@ with the criterion's so that the criterion overrides every refinement the
 forecaster misses.  Definitions written out here:
 
 features (per element e, element-local values and derivatives, zeta =
-dv/dx - du/dy, u_h = (u, v)):
+dv/dx - du/dy, u_h = (u, v); over terrain-following coordinates every
+derivative is the physical one, by the chain rule of the mapping as in
+``oracle.terrain``):
    0 level              1 max|zeta|            2 mean zeta
    3 max|u_h|           4 max|w|               5 max theta'
    6 min theta'         7 max|grad p'|         8 max|grad theta'|
@@ -30,16 +32,25 @@ forecast flags: class argmax of the logits (first maximum), clamped to the
 
 import numpy as np
 
+from . import terrain
 from .amr import column_flags
 from .euler import local_derivatives, pressure_perturbation
 from .gll import derivative_matrix
 
 
-def element_stats(mesh, qL, ref_local, phys, criterion):
-    """Raw per-element quantities of one state: dict of arrays (E,)."""
+def element_stats(mesh, qL, ref_local, phys, criterion, zsG=None):
+    """Raw per-element quantities of one state: dict of arrays (E,).
+
+    ref_local: rho0, theta0 at the local nodes (over terrain, at every node's
+    physical height); zsG: surface height per unique node, or None for box
+    elements."""
     rp, u, v, w, tp = qL
-    D = derivative_matrix(mesh.N)
-    d = lambda f: local_derivatives(D, f, mesh.e_dx, mesh.e_dy, mesh.e_dz)
+    if zsG is None:
+        D = derivative_matrix(mesh.N)
+        d = lambda f: local_derivatives(D, f, mesh.e_dx, mesh.e_dy, mesh.e_dz)
+    else:
+        _, Jinv, _ = terrain.jacobian(mesh, terrain.physical_z(mesh, zsG))
+        d = lambda f: terrain.gradient(mesh, Jinv, f)
     pp = pressure_perturbation(ref_local["rho0"], ref_local["theta0"], rp, tp,
                                phys["R_d"], phys["c_p"], phys["p00"])
     ux, uy, uz = d(u)
@@ -84,10 +95,12 @@ def neighbour_elements(mesh):
             for e in range(mesh.n_elem)]
 
 
-def features(mesh, qL, qL_prev, plain_elem, ref_local, phys, criterion, thr, lvl_max, scale):
-    """(features (E, 16) FP64 already scaled, dem (E,) int)."""
-    s = element_stats(mesh, qL, ref_local, phys, criterion)
-    sp = element_stats(mesh, qL_prev, ref_local, phys, criterion)
+def features(mesh, qL, qL_prev, plain_elem, ref_local, phys, criterion, thr, lvl_max, scale,
+             zsG=None):
+    """(features (E, 16) FP64 already scaled, dem (E,) int); zsG as in
+    ``element_stats``."""
+    s = element_stats(mesh, qL, ref_local, phys, criterion, zsG)
+    sp = element_stats(mesh, qL_prev, ref_local, phys, criterion, zsG)
     E = mesh.n_elem
     F = np.zeros((E, 16))
     F[:, 0] = mesh.e_level

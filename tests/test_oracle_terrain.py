@@ -260,3 +260,54 @@ def test_fp32_mode_is_float32_arithmetic_over_terrain(name):
     rest = np.zeros_like(q)
     for dt in (np.float64, np.float32):
         assert np.abs(terrain.rhs(m, rest, ref, zs, c["phys"], dtype=dt)).max() == 0.0
+
+
+def test_flat_terrain_features_are_the_box_features():
+    """The forecaster features over flat terrain reduce to the box-element
+    ones (the chain rule with the identity mapping)."""
+    from oracle import forecast
+    c = cases.get("small_amr2")
+    m = build(c)
+    q = cases.initial_state(c, m.node_xyz)
+    rng = np.random.default_rng(3)
+    qp = q * (1.0 + 0.05 * rng.standard_normal(q.shape))
+    qL, qLp = assembly.scatter(m, q), assembly.scatter(m, qp)
+    bg = cases.reference_state(c, m.zl)
+    refL = dict(rho0=bg["rho0"], theta0=bg["theta0"])
+    plain = rng.integers(-1, 2, size=m.n_elem)
+    thr, scale = [1e-4, 3e-4], np.ones(16)
+    box, dbox = forecast.features(m, qL, qLp, plain, refL, c["phys"], 1, thr, 2, scale)
+    ter, dter = forecast.features(m, qL, qLp, plain, refL, c["phys"], 1, thr, 2, scale,
+                                  zsG=np.zeros(m.n_dof))
+    assert np.all(np.abs(ter - box) <= 1e-12 * (np.abs(box).max(0) + 1e-300))
+    np.testing.assert_array_equal(dter, dbox)
+
+
+@pytest.mark.parametrize("name", ["vortex_8x8x4_n4", "small_amr2"])
+def test_terrain_features_of_linear_fields_are_exact(name):
+    """Winds and theta' linear in the physical coordinates over hills:
+    max|zeta| = mean zeta = 2 Omega, max|div u| = |a + b + c| and
+    max|grad theta'| = |(g1, g2, g3)| in every element, whatever the terrain
+    (a wrong metric term, sign or index in the chain rule breaks them)."""
+    from oracle import forecast
+    c = cases.get(name)
+    m = build(c)
+    zs = hills(c)(m.node_xyz[:, 0], m.node_xyz[:, 1])
+    zp = terrain.physical_z(m, zs)
+    om_, a, b, cz = 2e-4, 3e-5, -5e-5, 1e-4
+    g1, g2, g3 = 2e-6, -1e-6, 4e-3
+    x, y = m.xl, m.yl
+    qL = np.stack([np.zeros_like(x), a * x - om_ * y, om_ * x + b * y, cz * zp,
+                   g1 * x + g2 * y + g3 * zp])
+    bg = cases.reference_state(c, zp.reshape(-1))
+    refL = dict(rho0=bg["rho0"].reshape(x.shape), theta0=bg["theta0"].reshape(x.shape))
+    F, _ = forecast.features(m, qL, qL, np.zeros(m.n_elem), refL, c["phys"], 1, [1.0, 2.0], 2,
+                             np.ones(16), zsG=zs)
+    np.testing.assert_allclose(F[:, 1], 2 * om_, rtol=1e-10)
+    np.testing.assert_allclose(F[:, 2], 2 * om_, rtol=1e-10)
+    np.testing.assert_allclose(F[:, 9], abs(a + b + cz), rtol=1e-9)
+    np.testing.assert_allclose(F[:, 8], np.sqrt(g1 ** 2 + g2 ** 2 + g3 ** 2), rtol=1e-10)
+    # the box derivatives would see the terrain's slope in theta' and w
+    Fb, _ = forecast.features(m, qL, qL, np.zeros(m.n_elem), refL, c["phys"], 1, [1.0, 2.0], 2,
+                              np.ones(16))
+    assert np.abs(Fb[:, 8] - F[:, 8]).max() > 1e-3 * F[:, 8].max()
