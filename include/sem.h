@@ -191,8 +191,8 @@ int sem_mesh_set_dissipation(sem_mesh *mesh, double Cs, double sponge_gamma,
  * the same per call, and amr_flag takes the vorticity criterion through the
  * same chain rule.  SEM_FP32 (sem_stage, sem_rhs) keeps the metric factors
  * in FP64 and rounds them to float with the rest of the element arithmetic.
- * Limits: while terrain is set, amr_features and the dissipation return
- * SEM_ERR_STATE.
+ * amr_features takes its derivatives through the same chain rule.  Limit:
+ * while terrain is set, the dissipation returns SEM_ERR_STATE.
  * h_zs = NULL removes the terrain.  As for the dissipation, a HIP graph
  * captured before this call keeps the previous geometry: capture after it.
  * Arrays are copied; synchronises the
@@ -345,7 +345,9 @@ int sem_transfer_plan(const sem_mesh_desc *from, const sem_mesh_desc *to, int64_
 /* Per-element features, d_feat[n_elem][SEM_NFEAT] (float), each raw value
  * multiplied by h_scale[i] (host, SEM_NFEAT floats).  Raw features, from
  * element-local values and derivatives (LGL derivative matrix, as in the
- * criterion), zeta = dv/dx - du/dy, u_h = (u, v):
+ * criterion; with terrain set, the physical derivatives by the chain rule of
+ * the mapping and p' from the per-node reference), zeta = dv/dx - du/dy,
+ * u_h = (u, v):
  *   0 level, 1 max|zeta|, 2 mean zeta over the element's nodes, 3 max|u_h|,
  *   4 max|w|, 5 max theta', 6 min theta', 7 max|grad p'|, 8 max|grad theta'|,
  *   9 max|div u|, 10 max rho' - min rho', 11 largest feature-1 value and
@@ -356,7 +358,8 @@ int sem_transfer_plan(const sem_mesh_desc *from, const sem_mesh_desc *to, int64_
  * d_dem[n_elem] (int8) = the level the criterion asks for: the largest l in
  * 1..lvl_max with C_max > threshold(l) (0 if none), C as in amr_flag.
  * d_q, d_q_prev: states on this mesh (q[F][n_h][ldz]).  Uses the handle's
- * feature scratch, so calls on one handle must not overlap. */
+ * feature scratch, so calls on one handle must not overlap.  Errors:
+ * SEM_ERR_STATE (neither a reference nor terrain set), SEM_ERR_ARG. */
 int amr_features(const sem_mesh *mesh, const double *d_q, const double *d_q_prev,
                  const int8_t *d_plain_elem, int criterion, const double *h_thr, int lvl_max,
                  const float *h_scale, float *d_feat, int8_t *d_dem, void *stream);

@@ -43,8 +43,11 @@ __device__ __forceinline__ double wave_sum(double x) {
 //  10 rho' range, 11-12 (neighbour pass), 13 change of max|u_h| and
 //  14 change of max|zeta| since q_prev, 15 the criterion's own flag;
 // zeta = dv/dx - du/dy and every derivative element-local (tensor-product
-// LGL derivative, as in the criterion).  dem = number of thresholds the
-// criterion's element maximum exceeds (the level the criterion asks for).
+// LGL derivative, as in the criterion; over terrain-following coordinates the
+// physical derivative by the chain rule of the mapping: d/dx = box d/dx +
+// a_x d/dzf, d/dy likewise, d/dz = g_s d/dzf, and p' from the per-node
+// reference).  dem = number of thresholds the criterion's element maximum
+// exceeds (the level the criterion asks for).
 template <int NP>
 __global__ void __launch_bounds__(((NP * NP * NP + 63) / 64) * 64)
 k_features(DevMesh m, const double* __restrict__ q, const double* __restrict__ qp,
@@ -54,12 +57,18 @@ k_features(DevMesh m, const double* __restrict__ q, const double* __restrict__ q
     constexpr int NW = (NP3 + 63) / 64;
     __shared__ double su[NP3], sv[NP3], sw[NP3], st[NP3], spp[NP3], sup[NP3], svp[NP3];
     __shared__ double red[NW][A_N];
+    __shared__ double s_zs[NP2];          // terrain: surface height per position
     const int e = blockIdx.x;
     const int c = e / m.n_z, layer = e - c * m.n_z;
     const int t = threadIdx.x;
     const bool act = t < NP3;
     const int i = t % NP, j = (t / NP) % NP, k = t / NP2;
     const int kz = layer * N + k;
+    const bool ter = m.zs != nullptr;
+    if (ter && t < NP2) {
+        const int gz = m.gmap[c * NP2 + t];
+        s_zs[t] = m.zs[gz >= 0 ? gz : m.n_h - gz - 1];
+    }
     double rp = 0, u = 0, v = 0, w = 0, tp = 0, up = 0, vp = 0;
     if (act) {
         const int g = m.gmap[c * NP2 + i + NP * j];
@@ -72,7 +81,15 @@ k_features(DevMesh m, const double* __restrict__ q, const double* __restrict__ q
         vp = node_value(m, qp, g, 2, kz);
         su[t] = u; sv[t] = v; sw[t] = w; st[t] = tp; sup[t] = up; svp[t] = vp;
         // p' = p0 ((1 + rho'/rho0)(1 + theta'/theta0))^gamma - p0 without cancellation
-        spp[t] = m.p0[kz] * expm1(m.gamma * (log1p(rp / m.rho0[kz]) + log1p(tp / m.theta0[kz])));
+        if (ter) {
+            // per-node reference (hanging rows: the coarse face's interpolant)
+            const int64_t fsr = int64_t(m.n_h + m.n_hh) * m.ldz;
+            const int64_t o = int64_t(g >= 0 ? g : m.n_h - g - 1) * m.ldz + kz;
+            spp[t] = m.ref_n[3 * fsr + o] *
+                     expm1(m.gamma * (log1p(rp * m.ref_n[fsr + o]) + log1p(tp * m.ref_n[2 * fsr + o])));
+        } else {
+            spp[t] = m.p0[kz] * expm1(m.gamma * (log1p(rp / m.rho0[kz]) + log1p(tp / m.theta0[kz])));
+        }
     }
     __syncthreads();
     double a[A_N];
@@ -95,6 +112,25 @@ k_features(DevMesh m, const double* __restrict__ q, const double* __restrict__ q
         vx *= sx; ux *= sx; px *= sx; tx *= sx; vpx *= sx;
         uy *= sy; vy *= sy; py *= sy; ty *= sy; upy *= sy;
         wz *= szz; pz *= szz; tz *= szz;
+        if (ter) {
+            // terrain-following mapping: g_s = 1/(1 - zs/(H - z0)),
+            // a_x = -g_s (H - zf)/(H - z0) dzs/dx, a_y likewise
+            double uz = 0, vz = 0, upz = 0, vpz = 0, zx = 0, zy = 0;
+            for (int mm = 0; mm < NP; ++mm) {
+                const double dzm = m.D[k * NP + mm];
+                const int oz = i + NP * (j + NP * mm);
+                uz += dzm * su[oz]; vz += dzm * sv[oz]; upz += dzm * sup[oz]; vpz += dzm * svp[oz];
+                zx += m.D[i * NP + mm] * s_zs[mm + NP * j];
+                zy += m.D[j * NP + mm] * s_zs[i + NP * mm];
+            }
+            uz *= szz; vz *= szz; upz *= szz; vpz *= szz;
+            const double gs = 1.0 / (1.0 - s_zs[i + NP * j] * m.inv_depth);
+            const double tg = m.tfac[kz] * gs;
+            const double ax = -tg * zx * sx, ay = -tg * zy * sy;
+            vx += ax * vz; ux += ax * uz; px += ax * pz; tx += ax * tz; vpx += ax * vpz;
+            uy += ay * uz; vy += ay * vz; py += ay * pz; ty += ay * tz; upy += ay * upz;
+            wz *= gs; pz *= gs; tz *= gs;
+        }
         const double zeta = vx - uy, zetap = vpx - upy;
         a[A_ZABS] = fabs(zeta);
         a[A_ZSUM] = zeta;
@@ -253,8 +289,8 @@ int amr_features(const sem_mesh* M, const double* q, const double* q_prev, const
                  int criterion, const double* thr, int lvl_max, const float* scale, float* feat,
                  int8_t* dem, void* stream) {
     if (!M) return fail(SEM_ERR_ARG, "null mesh");
-    if (!M->have_ref) return fail(SEM_ERR_STATE, "sem_mesh_set_reference has not been called");
-    if (M->d.zs) return fail(SEM_ERR_STATE, "amr_features does not support terrain");
+    if (!M->have_ref && !M->d.zs)
+        return fail(SEM_ERR_STATE, "neither sem_mesh_set_reference nor sem_mesh_set_terrain has been called");
     if (!q || !q_prev || !plain || !feat || !dem || !scale) return fail(SEM_ERR_ARG, "null array");
     if (criterion != SEM_CRIT_SPEED && criterion != SEM_CRIT_VORTZ) return fail(SEM_ERR_ARG, "bad criterion");
     if (lvl_max < 0 || lvl_max > SEM_MAX_LEVEL) return fail(SEM_ERR_ARG, "lvl_max out of range");

@@ -8,9 +8,10 @@ sem_mesh_set_terrain) against the oracle's mapped elements (oracle.terrain):
 * the unfused calls (scatter, sem_rhs, assemble, gather, finalize) against
   the oracle and against the fused stage;
 * flat terrain against the box-element stage;
-* the refinement flags over terrain (both criteria, bit-exact);
+* the refinement flags over terrain (both criteria, bit-exact) and the
+  forecaster features (with the criterion's level, bit-exact);
 * SEM_FP32 over terrain against the oracle's float32 mapped elements;
-* the error paths (heights out of range, calls that only know box elements).
+* the error paths (heights out of range, the dissipation).
 
 Bar: floor-scaled relative L2 <= 1e-12 per field (FP64); SEM_FP32 within twice
 the oracle's own float32 error per field."""
@@ -229,7 +230,6 @@ def test_flat_terrain_matches_the_box_element_stage():
 
 
 def test_terrain_error_paths():
-    import torch
     from paper_2410_21607_amd import api, native
     c = cases.get("small_uniform", N=3)
     gm = api.Mesh.from_case(c)
@@ -242,17 +242,48 @@ def test_terrain_error_paths():
     with pytest.raises(native.SemError):           # non-positive reference
         gm.set_terrain(np.zeros(nh), zero, 300 * one, zero)
     gm.set_terrain(np.full(nh, 500.0), one, 300 * one, zero)
-    q = gm.state()
     with pytest.raises(native.SemError) as e:
         gm.set_dissipation(0.21, 0.0, 4000.0)
     assert e.value.code == -5
-    ne = gm.info["n_elem"]
+
+
+FEAT_SCALE = np.array([1.0, 1e3, 1e3, 0.05, 1.0, 1.0, 1.0, 20.0, 1e3, 1e4, 1e3, 1e3, 0.05, 0.5,
+                       1e4, 1.0])
+
+
+@pytest.mark.parametrize("name,kw,shape,periodic", [CASES[0], CASES[1], CASES[2], CASES[7]],
+                         ids=[IDS[0], IDS[1], IDS[2], IDS[7]])
+@pytest.mark.parametrize("criterion", [0, 1])
+def test_terrain_features_match_oracle(name, kw, shape, periodic, criterion):
+    """Forecaster features over terrain (physical derivatives by the chain
+    rule, p' from the per-node reference) against the oracle's, and the level
+    the criterion asks for, bit-exact."""
+    from oracle import forecast
+    S = Setup(name, kw, shape, periodic)
+    torch, api = S.torch, S.api
+    say("terrain features", name, kw, shape, criterion)
+    rng = np.random.default_rng(5)
+    qp = S.q_or * (1.0 + 0.05 * rng.standard_normal(S.q_or.shape))
+    qL, qLp = assembly.scatter(S.om, S.q_or), assembly.scatter(S.om, qp)
+    refL = {k: assembly.scatter(S.om, S.ref[k][None])[0] for k in ("rho0", "theta0")}
+    ne = S.om.n_elem
+    C = oamr.criterion_speed(qL) if criterion == 0 else oterrain.criterion_vorticity(S.om, qL, S.zs)
+    cmax = np.unique(C.reshape(ne, -1).max(axis=1))
+    gaps = np.argsort(np.diff(cmax))[::-1][:2]      # the two widest gaps
+    thr = np.sort(0.5 * (cmax[gaps] + cmax[gaps + 1]))
+    plain = rng.integers(-1, 2, size=ne).astype(np.int8)
+    want, dem_o = forecast.features(S.om, qL, qLp, plain, refL, S.c["phys"], criterion, thr, 2,
+                                    FEAT_SCALE, zsG=S.zs)
     feat = torch.zeros(ne * 16, dtype=torch.float32, device="cuda")
     dem = torch.zeros(ne, dtype=torch.int8, device="cuda")
-    plain = torch.zeros(ne, dtype=torch.int8, device="cuda")
-    with pytest.raises(native.SemError) as e:    # features take box-metric derivatives
-        api.amr_features(gm, q, q, plain, 1, [1e-4], 1, np.ones(16), feat, dem)
-    assert e.value.code == -5
+    api.amr_features(S.gm, S.q_g, S.gm.unpack(qp[:, S.perm]), torch.as_tensor(plain).cuda(),
+                     criterion, thr, 2, FEAT_SCALE, feat, dem)
+    torch.cuda.synchronize()
+    got = feat.cpu().numpy().reshape(ne, 16).astype(np.float64)
+    say("  worst relative error per feature", (np.abs(got - want) / (np.abs(want) + 1e-3)).max(0))
+    assert np.all(np.abs(got - want) <= 2e-6 * np.abs(want) + 1e-6)
+    np.testing.assert_array_equal(dem.cpu().numpy(), dem_o)
+    assert len(set(dem_o.tolist())) >= 2
 
 
 @pytest.mark.parametrize("name,kw,shape,periodic", [CASES[0], CASES[1], CASES[2], CASES[7]],
