@@ -24,6 +24,10 @@ mapping (nothing assumes the terrain-following form beyond ``physical_z``):
 * reference state given per unique node (its value at the node's physical
   height) and scattered like the solution.
 
+The sub-grid (horizontal Smagorinsky-Lilly) and absorbing-layer terms of the
+model setup follow ``oracle.euler.dissipation`` with physical derivatives, and
+the layer is placed by each node's physical height.
+
 Boundary: the top is a rigid lid (the w tendency is removed, as in
 ``oracle.assembly``).  At the terrain surface the momentum tendency loses its
 component along the surface normal n ~ (-dzs/dx, -dzs/dy, 1), with the
@@ -75,7 +79,37 @@ def gradient(mesh, Jinv, f):
     return tuple(sum(Jinv[..., b, a] * r[b] for b in range(3)) for a in range(3))
 
 
-def element_rhs(mesh, qL, refL, Jinv, phys, dtype=np.float64):
+def dissipation(mesh, qL, phys, Jinv, zp):
+    """The sub-grid and absorbing-layer tendencies of ``oracle.euler.dissipation``
+    on mapped elements, FP64: the strain rate and the divergence of the stress
+    take the physical derivatives (``gradient``), Delta stays the element's
+    mean horizontal node spacing (dx + dy)/(2N), and the absorbing layer is
+    evaluated at every node's physical height zp."""
+    grad = lambda f: gradient(mesh, Jinv, f)
+    out = np.zeros_like(qL)
+    cs = phys.get("Cs", 0.0)
+    if cs > 0.0:
+        u, v, w = qL[1], qL[2], qL[3]
+        ux, uy, uz = grad(u)
+        vx, vy, vz = grad(v)
+        wx, wy, wz = grad(w)
+        sxx, syy, szz = ux, vy, wz
+        sxy, sxz, syz = 0.5 * (uy + vx), 0.5 * (uz + wx), 0.5 * (vz + wy)
+        ss = sxx**2 + syy**2 + szz**2 + 2.0 * (sxy**2 + sxz**2 + syz**2)
+        delta = (mesh.e_dx + mesh.e_dy) / (2.0 * mesh.N)
+        nu = (cs * delta)[:, None, None, None] ** 2 * np.sqrt(2.0 * ss)
+        txx, txy, tyy, txz, tyz = (2.0 * nu * a for a in (sxx, sxy, syy, sxz, syz))
+        out[1] += grad(txx)[0] + grad(txy)[1]
+        out[2] += grad(txy)[0] + grad(tyy)[1]
+        out[3] += grad(txz)[0] + grad(tyz)[1]
+    gam = phys.get("sponge_gamma", 0.0)
+    if gam > 0.0:
+        rz = euler.sponge_profile(zp, mesh.z_edges[-1], gam, phys.get("sponge_depth", 4000.0))
+        out -= rz[None] * qL
+    return out
+
+
+def element_rhs(mesh, qL, refL, Jinv, phys, dtype=np.float64, zp=None):
     """Strong-form right-hand side of Section 2 on mapped elements.
 
     The same pointwise terms as ``oracle.euler.element_rhs``, with every
@@ -84,7 +118,10 @@ def element_rhs(mesh, qL, refL, Jinv, phys, dtype=np.float64):
     ``oracle.euler.element_rhs``: state, reference, inverse Jacobian, the
     derivatives and the pointwise terms are float32 arrays (p' is the exact
     difference rounded to float32); the caller's assembly stays FP64.
+    zp: physical heights of the local nodes, needed when phys enables the
+    dissipation (``dissipation``, evaluated in FP64 on the given state).
     Returns R_L, shape (5, E, n, n, n), float64."""
+    q64, Jinv64 = np.asarray(qL, dtype=np.float64), np.asarray(Jinv, dtype=np.float64)
     rho0, theta0, dth0 = refL["rho0"], refL["theta0"], refL["dtheta0dz"]
     pp = euler.pressure_perturbation(rho0, theta0, qL[0], qL[4],
                                      phys["R_d"], phys["c_p"], phys["p00"]).astype(dtype)
@@ -109,7 +146,10 @@ def element_rhs(mesh, qL, refL, Jinv, phys, dtype=np.float64):
     R[2] = -(u * vx + v * vy + w * vz) - py / rho - f * u
     R[3] = -(u * wx + v * wy + w * wz) - pz / rho - (rho_p / rho) * g
     R[4] = -(u * tx + v * ty + w * tz) - w * dth0
-    return R.astype(np.float64)
+    R = R.astype(np.float64)
+    if phys.get("Cs", 0.0) > 0.0 or phys.get("sponge_gamma", 0.0) > 0.0:
+        R += dissipation(mesh, q64, phys, Jinv64, zp)
+    return R
 
 
 def lumped_mass(mesh, detJ):
@@ -160,7 +200,7 @@ def rhs(mesh, qG, refG, zsG, phys, dtype=np.float64):
     qL = assembly.scatter(mesh, qG)
     refL = {k: assembly.scatter(mesh, np.asarray(refG[k], dtype=np.float64)[None])[0]
             for k in ("rho0", "theta0", "dtheta0dz")}
-    RL = element_rhs(mesh, qL, refL, Jinv, phys, dtype)
+    RL = element_rhs(mesh, qL, refL, Jinv, phys, dtype, zp)
     mL, MG = lumped_mass(mesh, detJ)
     RG = assembly.assemble(mesh, RL.reshape(5, -1) * mL[None]) / MG[None]
     # top: rigid lid

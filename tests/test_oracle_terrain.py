@@ -311,3 +311,75 @@ def test_terrain_features_of_linear_fields_are_exact(name):
     Fb, _ = forecast.features(m, qL, qL, np.zeros(m.n_elem), refL, c["phys"], 1, [1.0, 2.0], 2,
                               np.ones(16))
     assert np.abs(Fb[:, 8] - F[:, 8]).max() > 1e-3 * F[:, 8].max()
+
+
+def _diss_phys(c, cs=0.21, gamma=0.01, depth=4000.0):
+    ph = dict(c["phys"])
+    ph.update(Cs=cs, sponge_gamma=gamma, sponge_depth=depth)
+    return ph
+
+
+def test_flat_terrain_with_dissipation_is_the_box_element_rhs():
+    """Flat terrain with the Smagorinsky and absorbing-layer terms reduces to
+    the box-element right-hand side with the same terms (uniform and 2:1)."""
+    for name in ("vortex_8x8x4_n4", "small_amr2"):
+        c = cases.get(name)
+        m = build(c)
+        q = cases.initial_state(c, m.node_xyz)
+        ph = _diss_phys(c)
+        zs = np.zeros(m.n_dof)
+        bg = cases.reference_state(c, m.zl)
+        want = assembly.rhs(m, q, dict(rho0=bg["rho0"], theta0=bg["theta0"],
+                                       dtheta0dz=bg["dtheta0dz"]), ph)
+        got = terrain.rhs(m, q, ref_global(c, m, zs), zs, ph)
+        scale = np.abs(want).max(axis=1, keepdims=True)
+        assert np.all(np.abs(got - want) <= 1e-12 * scale)
+        # the terms are really on: without them the result differs
+        plain = terrain.rhs(m, q, ref_global(c, m, zs), zs, c["phys"])
+        assert np.abs(plain - got).max(axis=1)[1:4].min() > 1e-6 * scale[1:4].min()
+
+
+@pytest.mark.parametrize("name", ["vortex_8x8x4_n4", "small_amr2"])
+def test_uniform_strain_over_terrain_has_no_subgrid_tendency(name):
+    """Winds linear in the physical coordinates have a uniform strain rate,
+    hence a uniform stress with zero divergence: the sub-grid tendency
+    vanishes over hills (box derivatives would see a non-uniform strain)."""
+    c = cases.get(name)
+    m = build(c)
+    zs = hills(c)(m.node_xyz[:, 0], m.node_xyz[:, 1])
+    zp = terrain.physical_z(m, zs)
+    _, Jinv, _ = terrain.jacobian(m, zp)
+    x, y = m.xl, m.yl
+    qL = np.stack([np.zeros_like(x), 3e-5 * x - 2e-4 * y + 1e-3 * zp, 2e-4 * x + 5e-5 * y,
+                   -8e-5 * zp + 1e-6 * x, np.zeros_like(x)])
+    ph = _diss_phys(c, gamma=0.0)
+    out = terrain.dissipation(m, qL, ph, Jinv, zp)
+    # scale: the stress divided by the element width
+    delta = (m.e_dx + m.e_dy).max() / (2.0 * m.N)
+    tau = 2.0 * (0.21 * delta) ** 2 * 1e-3 * 1e-3
+    assert np.abs(out).max() <= 1e-9 * tau / m.e_dz.min()
+    from oracle.euler import dissipation as box_dissipation
+    assert np.abs(box_dissipation(m, qL, ph)[1:4]).max() > 1e-3 * tau / m.e_dz.min()
+
+
+def test_absorbing_layer_follows_the_physical_height():
+    """The layer coefficient at the domain top is min(1, gamma) in every
+    column (there the mapping leaves the height unchanged), and it reaches
+    nodes whose flat height is below the layer when the terrain lifts them
+    into it."""
+    c = cases.get("vortex_8x8x4_n4")
+    m = build(c)
+    H, depth, gamma = m.z_edges[-1], 7000.0, 0.02
+    zs = hills(c, amp=3000.0)(m.node_xyz[:, 0], m.node_xyz[:, 1])
+    zp = terrain.physical_z(m, zs)
+    _, Jinv, _ = terrain.jacobian(m, zp)
+    qL = np.ones((5,) + m.local_shape())
+    out = terrain.dissipation(m, qL, _diss_phys(c, cs=0.0, gamma=gamma, depth=depth), Jinv, zp)
+    rz = -out[0]
+    top = np.abs(m.zl - H) < 1e-9 * H
+    np.testing.assert_allclose(rz[top], min(1.0, gamma), rtol=1e-12)
+    assert np.all(rz[zp < H - depth] == 0.0)
+    lifted = (m.zl < H - depth) & (zp > H - depth + 1.0)
+    assert lifted.any() and np.all(rz[lifted] > 0.0)
+    for f in range(5):
+        assert np.array_equal(out[f], out[0])
