@@ -157,7 +157,9 @@ int sem_mesh_set_reference(sem_mesh *mesh, const double *h_rho0,
  *     gains -R(z) q', R(z) = min(1, max(0, sponge_gamma sin^2(pi/2 (1 - (z_top
  *     - z)/sponge_depth)))) for z >= z_top - sponge_depth, zero below.
  * Both are evaluated in FP64 element by element (strong form, like the other
- * terms) and assembled with the same direct stiffness summation.  In
+ * terms) and assembled with the same direct stiffness summation.  With
+ * terrain set (sem_mesh_set_terrain) the derivatives are the physical ones
+ * (chain rule of the mapping) and z is each node's physical height.  In
  * sem_stage they run as a pre-pass whose assembled tendency the column pass
  * adds.  Enabling allocates the pre-pass buffers once (5 element-local and 2
  * state arrays); compute calls never allocate.  Synchronises the device.
@@ -191,14 +193,13 @@ int sem_mesh_set_dissipation(sem_mesh *mesh, double Cs, double sponge_gamma,
  * the same per call, and amr_flag takes the vorticity criterion through the
  * same chain rule.  SEM_FP32 (sem_stage, sem_rhs) keeps the metric factors
  * in FP64 and rounds them to float with the rest of the element arithmetic.
- * amr_features takes its derivatives through the same chain rule.  Limit:
- * while terrain is set, the dissipation returns SEM_ERR_STATE.
+ * amr_features and the dissipation (sem_mesh_set_dissipation) take their
+ * derivatives through the same chain rule.
  * h_zs = NULL removes the terrain.  As for the dissipation, a HIP graph
  * captured before this call keeps the previous geometry: capture after it.
  * Arrays are copied; synchronises the
  * device.  Errors: SEM_ERR_ARG (null mesh, zs out of range, non-positive
- * reference), SEM_ERR_MESH (non-positive assembled mass), SEM_ERR_STATE
- * (dissipation enabled), SEM_ERR_HIP. */
+ * reference), SEM_ERR_MESH (non-positive assembled mass), SEM_ERR_HIP. */
 int sem_mesh_set_terrain(sem_mesh *mesh, const double *h_zs, const double *h_rho0,
                          const double *h_theta0, const double *h_dtheta0dz);
 

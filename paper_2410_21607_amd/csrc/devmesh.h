@@ -45,6 +45,8 @@ struct DevMesh {
     const double* ref_n;
     const double* tfac;
     double inv_depth;
+    double z_top, depth;      // H and H - z0 (physical heights z = H - t_f (H - z0 - zs))
+    double sp_gamma, sp_depth;   // absorbing layer (terrain: evaluated per node)
 };
 
 }  // namespace sem

@@ -211,6 +211,7 @@ k_dissip(DevMesh m, const double* __restrict__ q, const double* __restrict__ hv,
     __shared__ double sv[3][NP3];       // u, v, w
     __shared__ double st[5][NP3];       // 2 nu (S_xx, S_xy, S_yy, S_xz, S_yz)
     __shared__ double sD[NP2];
+    __shared__ double s_zs[NP2];        // terrain: surface height per position
     const int e = blockIdx.x;
     const int c = e / m.n_z, layer = e - c * m.n_z;
     const int t = threadIdx.x;
@@ -218,6 +219,11 @@ k_dissip(DevMesh m, const double* __restrict__ q, const double* __restrict__ hv,
     const int i = t % NP, j = (t / NP) % NP, k = t / NP2;
     const int kz = layer * N + k;
     const int64_t fs = int64_t(m.n_h) * m.ldz, fsh = int64_t(m.n_hh) * m.ldz;
+    const bool ter = m.zs != nullptr;
+    if (ter && t < NP2) {
+        const int gz = m.gmap[c * NP2 + t];
+        s_zs[t] = m.zs[gz >= 0 ? gz : m.n_h - gz - 1];
+    }
     double x[NF] = {0, 0, 0, 0, 0};
     if (t < NP3) {
         const int g = m.gmap[c * NP2 + i + NP * j];
@@ -234,6 +240,22 @@ k_dissip(DevMesh m, const double* __restrict__ q, const double* __restrict__ hv,
     }
     __syncthreads();
     const double sx = 2.0 / m.col_dx[c], sy = 2.0 / m.col_dy[c], sz = 2.0 / m.dz[layer];
+    // terrain-following mapping: d/dx = box d/dx + a_x d/dzf, d/dy likewise,
+    // d/dz = g_s d/dzf (g_s = 1/(1 - zs/(H - z0)), a_x = -g_s (H - zf)/(H - z0) dzs/dx);
+    // the lumped mass gains 1/g_s
+    double ax = 0.0, ay = 0.0, gs = 1.0, mfac = 1.0;
+    if (ter && t < NP3) {
+        double zx = 0.0, zy = 0.0;
+        for (int mm = 0; mm < NP; ++mm) {
+            zx += sD[i * NP + mm] * s_zs[mm + NP * j];
+            zy += sD[j * NP + mm] * s_zs[i + NP * mm];
+        }
+        mfac = 1.0 - s_zs[i + NP * j] * m.inv_depth;
+        gs = 1.0 / mfac;
+        const double tg = m.tfac[kz] * gs;
+        ax = -tg * zx * sx;
+        ay = -tg * zy * sy;
+    }
     double R[NF] = {0, 0, 0, 0, 0};
     const bool sgs = m.cs > 0.0;
     if (sgs && t < NP3) {
@@ -250,6 +272,14 @@ k_dissip(DevMesh m, const double* __restrict__ q, const double* __restrict__ hv,
         }
 #pragma unroll
         for (int a = 0; a < 3; ++a) { g3[a][0] *= sx; g3[a][1] *= sy; g3[a][2] *= sz; }
+        if (ter) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                g3[a][0] += ax * g3[a][2];
+                g3[a][1] += ay * g3[a][2];
+                g3[a][2] *= gs;
+            }
+        }
         const double sxx = g3[0][0], syy = g3[1][1], szz = g3[2][2];
         const double sxy = 0.5 * (g3[0][1] + g3[1][0]);
         const double sxz = 0.5 * (g3[0][2] + g3[2][0]);
@@ -267,26 +297,43 @@ k_dissip(DevMesh m, const double* __restrict__ q, const double* __restrict__ hv,
     __syncthreads();
     if (t >= NP3) return;
     if (sgs) {
-        double dx_[5] = {0, 0, 0, 0, 0}, dy_[5] = {0, 0, 0, 0, 0};
+        double dx_[5] = {0, 0, 0, 0, 0}, dy_[5] = {0, 0, 0, 0, 0}, dz_[5] = {0, 0, 0, 0, 0};
         for (int mm = 0; mm < NP; ++mm) {
-            const double dxm = sD[i * NP + mm], dym = sD[j * NP + mm];
-            const int ox = mm + NP * (j + NP * k), oy = i + NP * (mm + NP * k);
+            const double dxm = sD[i * NP + mm], dym = sD[j * NP + mm], dzm = sD[k * NP + mm];
+            const int ox = mm + NP * (j + NP * k), oy = i + NP * (mm + NP * k), oz = i + NP * (j + NP * mm);
 #pragma unroll
             for (int a = 0; a < 5; ++a) {
                 dx_[a] += dxm * st[a][ox];
                 dy_[a] += dym * st[a][oy];
+                if (ter) dz_[a] += dzm * st[a][oz];
             }
         }
-        R[1] = dx_[0] * sx + dy_[1] * sy;
-        R[2] = dx_[1] * sx + dy_[2] * sy;
-        R[3] = dx_[3] * sx + dy_[4] * sy;
+        // physical d/dx and d/dy of the stresses (box part plus the mapping's)
+        double tx[5], ty[5];
+#pragma unroll
+        for (int a = 0; a < 5; ++a) {
+            tx[a] = dx_[a] * sx + ax * (dz_[a] * sz);
+            ty[a] = dy_[a] * sy + ay * (dz_[a] * sz);
+        }
+        R[1] = tx[0] + ty[1];
+        R[2] = tx[1] + ty[2];
+        R[3] = tx[3] + ty[4];
     }
     if (m.sponge) {
-        const double rz = m.sponge[kz];
+        double rz = m.sponge[kz];
+        if (ter) {
+            // the layer at the node's physical height z = H - t_f (H - z0 - zs)
+            const double zp = m.z_top - m.tfac[kz] * (m.depth - s_zs[i + NP * j]);
+            rz = 0.0;
+            if (zp >= m.z_top - m.sp_depth) {
+                const double sn = sin(0.5 * M_PI * (1.0 - (m.z_top - zp) / m.sp_depth));
+                rz = fmin(1.0, fmax(0.0, m.sp_gamma * sn * sn));
+            }
+        }
 #pragma unroll
         for (int f = 0; f < NF; ++f) R[f] -= rz * x[f];
     }
-    const double mass = m.w[i] * m.w[j] * m.w[k] * 0.125 * m.col_dx[c] * m.col_dy[c] * m.dz[layer];
+    const double mass = m.w[i] * m.w[j] * m.w[k] * 0.125 * m.col_dx[c] * m.col_dy[c] * m.dz[layer] * mfac;
     const int64_t es = int64_t(m.n_col) * m.n_z * NP3;
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
@@ -727,7 +774,6 @@ int sem_mesh_set_terrain(sem_mesh* M, const double* zs, const double* rho0, cons
         return SEM_OK;
     }
     if (!rho0 || !theta0 || !dth0) return fail(SEM_ERR_ARG, "null reference array");
-    if (d.cs > 0.0 || d.sponge) return fail(SEM_ERR_STATE, "terrain and the dissipation cannot be combined");
     const double z0 = H.z_edges.front(), top = H.z_edges.back(), depth = top - z0;
     for (int64_t h = 0; h < H.n_h; ++h)
         if (!(zs[h] >= 0.0) || !(zs[h] < depth))
@@ -844,6 +890,8 @@ int sem_mesh_set_terrain(sem_mesh* M, const double* zs, const double* rho0, cons
     d.ref_n = d.minv_ht + nh;
     d.tfac = d.ref_n + 5 * fs;
     d.inv_depth = 1.0 / depth;
+    d.z_top = top;
+    d.depth = depth;
     return SEM_OK;
 }
 
@@ -917,8 +965,6 @@ int sem_mesh_set_dissipation(sem_mesh* M, double cs, double sponge_gamma, double
     if (!M) return fail(SEM_ERR_ARG, "null mesh");
     if (!(cs >= 0.0) || !(sponge_gamma >= 0.0) || (sponge_gamma > 0.0 && !(sponge_depth > 0.0)))
         return fail(SEM_ERR_ARG, "need Cs >= 0, sponge_gamma >= 0 and sponge_depth > 0");
-    if (M->d.zs && (cs > 0.0 || sponge_gamma > 0.0))
-        return fail(SEM_ERR_STATE, "terrain and the dissipation cannot be combined");
     const sem::HostMesh& H = M->host;
     DevMesh& d = M->d;
     HIPCHK(hipDeviceSynchronize());
@@ -954,6 +1000,8 @@ int sem_mesh_set_dissipation(sem_mesh* M, double cs, double sponge_gamma, double
     HIPCHK(hipMemcpy(M->diss_sponge, sp.data(), sizeof(double) * H.nzn, hipMemcpyHostToDevice));
     d.cs = cs;
     d.sponge = sponge_gamma > 0.0 ? M->diss_sponge : nullptr;
+    d.sp_gamma = sponge_gamma;
+    d.sp_depth = sponge_depth;
     d.rx = M->diss_r;
     return SEM_OK;
 }

@@ -11,7 +11,8 @@ sem_mesh_set_terrain) against the oracle's mapped elements (oracle.terrain):
 * the refinement flags over terrain (both criteria, bit-exact) and the
   forecaster features (with the criterion's level, bit-exact);
 * SEM_FP32 over terrain against the oracle's float32 mapped elements;
-* the error paths (heights out of range, the dissipation).
+* the horizontal Smagorinsky-Lilly and absorbing-layer terms over terrain;
+* the error paths (heights out of range, non-positive reference).
 
 Bar: floor-scaled relative L2 <= 1e-12 per field (FP64); SEM_FP32 within twice
 the oracle's own float32 error per field."""
@@ -242,9 +243,8 @@ def test_terrain_error_paths():
     with pytest.raises(native.SemError):           # non-positive reference
         gm.set_terrain(np.zeros(nh), zero, 300 * one, zero)
     gm.set_terrain(np.full(nh, 500.0), one, 300 * one, zero)
-    with pytest.raises(native.SemError) as e:
-        gm.set_dissipation(0.21, 0.0, 4000.0)
-    assert e.value.code == -5
+    gm.set_dissipation(0.21, 0.0, 4000.0)           # the terms combine with terrain
+    gm.set_terrain(None)
 
 
 FEAT_SCALE = np.array([1.0, 1e3, 1e3, 0.05, 1.0, 1.0, 1.0, 20.0, 1e3, 1e4, 1e3, 1e3, 0.05, 0.5,
@@ -352,6 +352,67 @@ def test_terrain_fp32_within_twice_oracle_fp32(name, kw, shape, periodic):
     e_or3 = metrics.rel_l2(w32, w64, metrics.STATE_FLOORS)
     say("  3 stages gpu", e_gpu, "oracle fp32", e_or3)
     assert np.all(e_gpu <= 2.0 * e_or3 + 1e-15)
+
+
+def _unfused_rhs(S, precision=None):
+    """scatter -> sem_rhs -> assemble -> gather -> finalize, in oracle order."""
+    torch, api = S.torch, S.api
+    n, nh, nl = S.gm.n_state, S.gm.n_hstate, 5 * S.gm.n_local
+    z = lambda k: torch.zeros(k, dtype=torch.float64, device="cuda")
+    hv, rE, acc, cH, r = z(nh), z(nl), z(n), z(nh), z(n)
+    if nh:
+        api.sem_nc_project(S.gm, api.SEM_SCATTER, S.q_g, hv)
+    api.sem_rhs(S.gm, S.q_g, hv if nh else None, rE,
+                api.SEM_FP64 if precision is None else precision)
+    api.sem_dss(S.gm, api.SEM_ASSEMBLE, rE=rE, acc=acc, c=cH if nh else None)
+    if nh:
+        api.sem_nc_project(S.gm, api.SEM_GATHER, cH, acc)
+    api.sem_dss(S.gm, api.SEM_FINALIZE, acc=acc, r=r)
+    torch.cuda.synchronize()
+    return S.to_oracle_order(r)
+
+
+@pytest.mark.parametrize("name,kw,shape,periodic", [CASES[0], CASES[1], CASES[2], CASES[7]],
+                         ids=[IDS[0], IDS[1], IDS[2], IDS[7]])
+def test_terrain_dissipation_matches_oracle(name, kw, shape, periodic):
+    """Horizontal Smagorinsky-Lilly and the absorbing layer over terrain
+    (physical derivatives, layer at the physical height) against the oracle's
+    mapped-element terms: the unfused calls, the fused stage (right-hand side
+    and three stages), the dissipation part on its own scale, and switching
+    the terms off again."""
+    S = Setup(name, kw, shape, periodic)
+    torch, api = S.torch, S.api
+    say("terrain dissipation", name, kw, shape)
+    phys = dict(S.c["phys"], Cs=0.21, sponge_gamma=0.05, sponge_depth=8000.0)
+    r_off = _unfused_rhs(S)
+    S.gm.set_dissipation(0.21, 0.05, 8000.0)
+    r_on = _unfused_rhs(S)
+    want_on = oterrain.rhs(S.om, S.q_or, S.ref, S.zs, phys)
+    want_off = S.oracle_rhs(S.q_or)
+    err = metrics.rel_l2(r_on, want_on, metrics.RHS_FLOORS)
+    dd = want_on - want_off
+    floors = np.maximum(np.abs(dd).max(axis=1), 1e-300) * 1e-3
+    err_d = metrics.rel_l2(r_on - r_off, dd, floors)
+    say("  unfused rel", err, "dissipation part rel", err_d)
+    assert np.abs(dd[1]).max() > 0 and np.abs(dd[0]).max() > 0
+    assert err.max() <= TOL64 and err_d.max() <= 1e-9
+    fused = S.gpu_rhs()
+    errf = metrics.rel_l2(fused, want_on, metrics.RHS_FLOORS)
+    say("  fused rel", errf)
+    assert errf.max() <= TOL64
+    dt = S.c["dt"]
+    want, _ = timestep.run_stages(lambda q: oterrain.rhs(S.om, q, S.ref, S.zs, phys), S.q_or, dt, 3)
+    qs, o = S.q_g.clone(), torch.zeros_like(S.q_g)
+    for st in range(3):
+        a, b, cc = timestep.stage_coefficients(st, dt)
+        api.sem_stage(S.gm, a, b, cc, S.q_g, qs, o)
+        qs, o = o, qs
+    torch.cuda.synchronize()
+    err3 = metrics.rel_l2(S.to_oracle_order(qs), want, metrics.STATE_FLOORS)
+    say("  3 stages rel", err3)
+    assert err3.max() <= TOL64
+    S.gm.set_dissipation(0.0, 0.0, 8000.0)
+    assert np.array_equal(_unfused_rhs(S), r_off)
 
 
 def _mountain_hook(case, amp=1000.0, half_width=40e3):
