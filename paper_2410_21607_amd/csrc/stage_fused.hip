@@ -139,13 +139,20 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
     const int item = xcd * (G >> 3) + min(xcd, G & 7) + rr;
     const int col = ft.col_order[col0 + min(item, ncol - 1)];
 
-    // Thread -> node of the chunk.  Nodes inside an element or on the chunk's
-    // bottom/top come first (RG per position); nodes on the planes between two
-    // stacked elements (LPC-1 per position, two z derivatives each) follow,
-    // so that they fill waves of their own instead of diverging every wave.
+    // Thread -> node of the chunk.  FP64: nodes inside an element or on the
+    // chunk's bottom/top come first (RG per position); nodes on the planes
+    // between two stacked elements (LPC-1 per position, two z derivatives
+    // each) follow, so that they fill waves of their own instead of making
+    // every wave run a second pass of FP64 z derivatives with most lanes
+    // masked.  Float: the natural order (kzl fastest within a position); the
+    // masked second pass is cheap at the float rate, and every wave then
+    // carries the same LDS load, so no wave waits long at the barriers.
     constexpr int RG = LPC * (N - 1) + 2;
     int kzl, p;
-    if (tid < NP2 * RG) {
+    if constexpr (sizeof(T) == 4) {
+        p = tid < NP2 * NK ? tid / NK : NP2;
+        kzl = tid < NP2 * NK ? tid - p * NK : 0;
+    } else if (tid < NP2 * RG) {
         p = tid / RG;
         const int r = tid - p * RG;
         if (r == 0) kzl = 0;
