@@ -311,37 +311,43 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
             }
         }
         if (active) {
-            // d/dx of tile tx and d/dy of tile ty at this node.  The empty asm
-            // pins both results before the next field's LDS reads may be
-            // issued (memory clobber), which bounds the live registers.
-            auto dxy = [&](int tx, int ty, T& ox, T& oy) {
-                T ax = 0, ay = 0;
+            // d/dx of tiles tx, tx2 and d/dy of tiles ty, ty2 at this node.  The
+            // empty asm pins the results before the next fields' LDS reads may
+            // be issued (memory clobber), which bounds the live registers; it
+            // also makes the LGL coefficients be read from LDS again after it,
+            // so each call serves two fields with one read of each coefficient
+            // (that halves the coefficient reads, about a quarter of the LDS
+            // traffic of the derivative phase).
+            auto dxy = [&](int tx, int ty, int tx2, int ty2, T& ox, T& oy, T& ox2, T& oy2) {
+                T ax = 0, ay = 0, ax2 = 0, ay2 = 0;
 #pragma unroll
                 for (int mm = 0; mm < NP; ++mm) {
-                    ax += Dx[mm] * tile[tx][lx0 + mm * NK];
-                    ay += Dy[mm] * tile[ty][ly0 + mm * NP * NK];
+                    const T cx = Dx[mm], cy = Dy[mm];
+                    ax += cx * tile[tx][lx0 + mm * NK];
+                    ay += cy * tile[ty][ly0 + mm * NP * NK];
+                    ax2 += cx * tile[tx2][lx0 + mm * NK];
+                    ay2 += cy * tile[ty2][ly0 + mm * NP * NK];
                 }
-                asm volatile("" : "+v"(ax), "+v"(ay) : : "memory");
+                asm volatile("" : "+v"(ax), "+v"(ay), "+v"(ax2), "+v"(ay2) : : "memory");
                 ox = ax * sx;
                 oy = ay * sy;
+                ox2 = ax2 * sx;
+                oy2 = ay2 * sy;
             };
             const T u = T(qv[1]), v = T(qv[2]), w = T(qv[3]);
             const T inv_rho = T(1) / rho;
             const T f = T(m.f), gr = T(m.g);
             // the parts of R without z derivatives
-            T Rh[NF], ax, ay;
-            dxy(0, 1, ax, ay);
+            T Rh[NF], ax, ay, bx, by;
+            dxy(0, 1, 3, 3, ax, ay, bx, by);
             Rh[0] = -(ax + ay);
-            dxy(3, 3, ax, ay);
-            Rh[1] = -(u * ax + v * ay) + f * v;
-            dxy(4, 4, ax, ay);
+            Rh[1] = -(u * bx + v * by) + f * v;
+            dxy(4, 4, 5, 5, ax, ay, bx, by);
             Rh[2] = -(u * ax + v * ay) - f * u;
-            dxy(5, 5, ax, ay);
-            Rh[3] = -(u * ax + v * ay) - T(qv[0]) * inv_rho * gr;
-            dxy(6, 6, ax, ay);
-            Rh[1] -= ax * inv_rho;
-            Rh[2] -= ay * inv_rho;
-            dxy(7, 7, ax, ay);
+            Rh[3] = -(u * bx + v * by) - T(qv[0]) * inv_rho * gr;
+            dxy(6, 6, 7, 7, bx, by, ax, ay);
+            Rh[1] -= bx * inv_rho;
+            Rh[2] -= by * inv_rho;
             if constexpr (TER) {
                 Rh[4] = -(u * ax + v * ay) - w * T(m.ref_n[4 * fsr + int64_t(rrow) * m.ldz + kz]);
             }
@@ -367,27 +373,42 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
                 const T sz = T(sb[6 * NK + LPC + el]);
                 const T* Dz = &sD[kk * NP];
                 const int lz0 = pc * NK + el * N;
-                auto ddz = [&](int tz) {
-                    T az = 0;
+                // two fields per call, as for d/dx and d/dy
+                auto ddz = [&](int tz, int tz2, T& oz, T& oz2) {
+                    T az = 0, az2 = 0;
 #pragma unroll
-                    for (int mm = 0; mm < NP; ++mm) az += Dz[mm] * tile[tz][lz0 + mm];
-                    asm volatile("" : "+v"(az) : : "memory");
-                    return az * sz;
+                    for (int mm = 0; mm < NP; ++mm) {
+                        const T cz = Dz[mm];
+                        az += cz * tile[tz][lz0 + mm];
+                        az2 += cz * tile[tz2][lz0 + mm];
+                    }
+                    asm volatile("" : "+v"(az), "+v"(az2) : : "memory");
+                    oz = az * sz;
+                    oz2 = az2 * sz;
                 };
-                T R[NF];
+                T R[NF], z0, z1;
                 if constexpr (TER) {
-                    const T pz = ddz(6) * inv_rho;
-                    R[0] = Rh[0] - (a_x * ddz(0) + a_y * ddz(1) + gs * ddz(2));
-                    R[1] = Rh[1] - wt * ddz(3) - a_x * pz;
-                    R[2] = Rh[2] - wt * ddz(4) - a_y * pz;
-                    R[3] = Rh[3] - wt * ddz(5) - gs * pz;
-                    R[4] = Rh[4] - wt * ddz(7);
+                    ddz(6, 7, z0, z1);
+                    const T pz = z0 * inv_rho;
+                    R[4] = Rh[4] - wt * z1;
+                    ddz(3, 4, z0, z1);
+                    R[1] = Rh[1] - wt * z0 - a_x * pz;
+                    R[2] = Rh[2] - wt * z1 - a_y * pz;
+                    T z2, z3;
+                    ddz(0, 1, z0, z1);
+                    ddz(2, 5, z2, z3);
+                    R[0] = Rh[0] - (a_x * z0 + a_y * z1 + gs * z2);
+                    R[3] = Rh[3] - wt * z3 - gs * pz;
                 } else {
-                    R[0] = Rh[0] - ddz(2);
-                    R[1] = Rh[1] - w * ddz(3);
-                    R[2] = Rh[2] - w * ddz(4);
-                    R[3] = Rh[3] - w * ddz(5) - ddz(6) * inv_rho;
-                    R[4] = Rh[4] - w * ddz(7);
+                    ddz(2, 3, z0, z1);
+                    R[0] = Rh[0] - z0;
+                    R[1] = Rh[1] - w * z1;
+                    ddz(4, 5, z0, z1);
+                    R[2] = Rh[2] - w * z0;
+                    T z2, z3;
+                    ddz(6, 7, z2, z3);
+                    R[3] = Rh[3] - w * z1 - z2 * inv_rho;
+                    R[4] = Rh[4] - w * z3;
                 }
                 const double mass = mass_ij * sW[kk] * dzl;
 #pragma unroll
