@@ -139,12 +139,13 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
     const int item = xcd * (G >> 3) + min(xcd, G & 7) + rr;
     const int col = ft.col_order[col0 + min(item, ncol - 1)];
 
-    // Thread -> node of the chunk.  FP64: nodes inside an element or on the
-    // chunk's bottom/top come first (RG per position); nodes on the planes
-    // between two stacked elements (LPC-1 per position, two z derivatives
-    // each) follow, so that they fill waves of their own instead of making
-    // every wave run a second pass of FP64 z derivatives with most lanes
-    // masked.  Float: the natural order (kzl fastest within a position); the
+    // Thread -> node of the chunk.  FP64: nodes on the planes between two
+    // stacked elements (LPC-1 per position, two z derivatives each) come
+    // first, so that they fill waves of their own instead of making every
+    // wave run a second pass of FP64 z derivatives with most lanes masked,
+    // and so that these longest waves are the oldest, which issue first;
+    // nodes inside an element or on the chunk's bottom/top follow (RG per
+    // position).  Float: the natural order (kzl fastest within a position); the
     // masked second pass is cheap at the float rate, and every wave then
     // carries the same LDS load, so no wave waits long at the barriers.
     constexpr int RG = LPC * (N - 1) + 2;
@@ -152,20 +153,23 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
     if constexpr (sizeof(T) == 4) {
         p = tid < NP2 * NK ? tid / NK : NP2;
         kzl = tid < NP2 * NK ? tid - p * NK : 0;
-    } else if (tid < NP2 * RG) {
-        p = tid / RG;
-        const int r = tid - p * RG;
-        if (r == 0) kzl = 0;
-        else if (r == RG - 1) kzl = NK - 1;
-        else if constexpr (N > 1) kzl = ((r - 1) / (N - 1)) * N + (r - 1) % (N - 1) + 1;
-        else kzl = 0;
-    } else if constexpr (LPC > 1) {
-        const int t2 = tid - NP2 * RG;
-        p = t2 / (LPC - 1);
-        kzl = (t2 - p * (LPC - 1) + 1) * N;
     } else {
-        p = NP2;
-        kzl = 0;
+        constexpr int NI = (LPC > 1) ? NP2 * (LPC - 1) : 0;
+        if (tid < NI) {
+            p = tid / (LPC - 1 > 0 ? LPC - 1 : 1);
+            kzl = (tid - p * (LPC - 1) + 1) * N;
+        } else if (tid < NI + NP2 * RG) {
+            const int t2 = tid - NI;
+            p = t2 / RG;
+            const int r = t2 - p * RG;
+            if (r == 0) kzl = 0;
+            else if (r == RG - 1) kzl = NK - 1;
+            else if constexpr (N > 1) kzl = ((r - 1) / (N - 1)) * N + (r - 1) % (N - 1) + 1;
+            else kzl = 0;
+        } else {
+            p = NP2;
+            kzl = 0;
+        }
     }
     __shared__ double s_zs[TER ? NP2 : 1];
     __shared__ double s_ter[TER ? 4 : 1][TER ? NP2 : 1];   // g_s, g_s dzs/dx, g_s dzs/dy, 1/g_s
