@@ -189,7 +189,6 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
 
     int g = 0, r_beg = 0, r_end = 0;
     bool first = false;
-    double minv_h = 0.0;
     const double dxc = m.col_dx[col], dyc = m.col_dy[col];
     const T sx = T(m.col_sx[col]), sy = T(m.col_sy[col]);
     if (lane_ok) {
@@ -198,14 +197,19 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
         if (g < 0) {
             r_beg = m.hang_ptr[-g - 1];
             r_end = m.hang_ptr[-g];
-        } else {
-            minv_h = TER ? m.minv_ht[g] : m.minv_h[g];
         }
     }
+    // per-position constants in LDS rather than in every thread's registers:
+    // the horizontal inverse mass and the horizontal mass weight
+    __shared__ double s_mh[NP2], s_mij[NP2];
+    for (int t = tid; t < NP2; t += WGT) {
+        const int gt = m.gmap[col * NP2 + t];
+        s_mh[t] = gt >= 0 ? (TER ? m.minv_ht[gt] : m.minv_h[gt]) : 0.0;
+    }
     __syncthreads();
+    for (int t = tid; t < NP2; t += WGT) s_mij[t] = sW[t % NP] * sW[t / NP] * 0.125 * dxc * dyc;
     const T* Dx = &sD[i * NP];
     const T* Dy = &sD[j * NP];
-    const double mass_ij = sW[i] * sW[j] * 0.125 * dxc * dyc;
     const int lx0 = (j * NP) * NK + kzl, ly0 = i * NK + kzl;
     const int rrow = TER ? (g >= 0 ? g : m.n_h - g - 1) : 0;   // terrain reference row
     // terrain: g_s and g_s times the box derivatives of zs per position (LDS)
@@ -414,7 +418,7 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
                     R[3] = Rh[3] - w * z1 - z2 * inv_rho;
                     R[4] = Rh[4] - w * z3;
                 }
-                const double mass = mass_ij * sW[kk] * dzl;
+                const double mass = s_mij[pc] * sW[kk] * dzl;
 #pragma unroll
                 for (int fl = 0; fl < NF; ++fl) acc[fl] += mass * double(R[fl]);
             }
@@ -447,7 +451,7 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
                         }
                         lid = (kz == nzn - 1);
                     }
-                    const double mi = c * minv_h * sb[5 * NK + kzl];
+                    const double mi = c * s_mh[pc] * sb[5 * NK + kzl];
                     const int64_t o = int64_t(g) * m.ldz + kz;
                     if (TER && (!first || a != 0.0)) {
                         // the terrain instance loads its base here (registers)
