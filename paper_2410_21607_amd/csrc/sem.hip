@@ -201,11 +201,12 @@ k_rhs(DevMesh m, const double* __restrict__ q, const double* __restrict__ hv,
 //   and w (S_zx, S_zy), nu = (C_s Delta)^2 sqrt(2 S:S), Delta = (dx+dy)/(2N),
 // with S from the element-local velocity derivatives; and the Rayleigh layer,
 // R_f -= R(kz) q'_f for every field.  accumulate = true adds to rE (the
-// unfused element right-hand side), false overwrites it.
+// unfused element right-hand side), false overwrites it; col selects the
+// column-row layout of rE (see sum_local).
 template <int NP>
 __global__ void __launch_bounds__(((NP * NP * NP + 63) / 64) * 64)
 k_dissip(DevMesh m, const double* __restrict__ q, const double* __restrict__ hv,
-         double* __restrict__ rE, bool accumulate) {
+         double* __restrict__ rE, bool accumulate, bool col) {
     constexpr int NP2 = NP * NP, NP3 = NP2 * NP;
     constexpr int N = NP - 1;
     __shared__ double sv[3][NP3];       // u, v, w
@@ -216,7 +217,10 @@ k_dissip(DevMesh m, const double* __restrict__ q, const double* __restrict__ hv,
     const int c = e / m.n_z, layer = e - c * m.n_z;
     const int t = threadIdx.x;
     if (t < NP2) sD[t] = m.D[t];
-    const int i = t % NP, j = (t / NP) % NP, k = t / NP2;
+    // node of this thread, k fastest (vertical runs of the state and of the
+    // column-row output are contiguous); tl is its element-local index
+    const int k = t % NP, i = (t / NP) % NP, j = t / NP2;
+    const int tl = i + NP * (j + NP * k);
     const int kz = layer * N + k;
     const int64_t fs = int64_t(m.n_h) * m.ldz, fsh = int64_t(m.n_hh) * m.ldz;
     const bool ter = m.zs != nullptr;
@@ -234,9 +238,9 @@ k_dissip(DevMesh m, const double* __restrict__ q, const double* __restrict__ hv,
 #pragma unroll
             for (int f = 0; f < NF; ++f) x[f] = hv[f * fsh + int64_t(-g - 1) * m.ldz + kz];
         }
-        sv[0][t] = x[1];
-        sv[1][t] = x[2];
-        sv[2][t] = x[3];
+        sv[0][tl] = x[1];
+        sv[1][tl] = x[2];
+        sv[2][tl] = x[3];
     }
     __syncthreads();
     const double sx = 2.0 / m.col_dx[c], sy = 2.0 / m.col_dy[c], sz = 2.0 / m.dz[layer];
@@ -288,11 +292,11 @@ k_dissip(DevMesh m, const double* __restrict__ q, const double* __restrict__ hv,
         const double delta = (m.col_dx[c] + m.col_dy[c]) / (2.0 * N);
         const double cd = m.cs * delta;
         const double two_nu = 2.0 * cd * cd * sqrt(2.0 * ss);
-        st[0][t] = two_nu * sxx;
-        st[1][t] = two_nu * sxy;
-        st[2][t] = two_nu * syy;
-        st[3][t] = two_nu * sxz;
-        st[4][t] = two_nu * syz;
+        st[0][tl] = two_nu * sxx;
+        st[1][tl] = two_nu * sxy;
+        st[2][tl] = two_nu * syy;
+        st[3][tl] = two_nu * sxz;
+        st[4][tl] = two_nu * syz;
     }
     __syncthreads();
     if (t >= NP3) return;
@@ -337,15 +341,19 @@ k_dissip(DevMesh m, const double* __restrict__ q, const double* __restrict__ hv,
     const int64_t es = int64_t(m.n_col) * m.n_z * NP3;
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
-        const int64_t o = f * es + int64_t(e) * NP3 + t;
+        const int64_t o = f * es + (col ? (int64_t(c) * NP2 + i + NP * j) * (int64_t(m.n_z) * NP) + layer * NP + k
+                                        : int64_t(e) * NP3 + tl);
         rE[o] = (accumulate ? rE[o] : 0.0) + mass * R[f];
     }
 }
 
 // sum of element contributions at the local copies of (slot-list, kz)
+// rE layouts: element-local [F][elem][k][j][i] (col = false, the sem_rhs /
+// sem_dss layout), or column rows [F][col][pos][layer][k] (col = true, the
+// dissipation pre-pass's own buffer), where consecutive kz are contiguous.
 __device__ __forceinline__ void sum_local(const DevMesh& m, const double* __restrict__ rE,
                                           const int* __restrict__ slots, int s0, int s1, int kz,
-                                          double* out) {
+                                          double* out, bool col) {
     const int np1 = m.N + 1, np2 = np1 * np1, np3 = np2 * np1;
     const int64_t es = int64_t(m.n_col) * m.n_z * np3;
     int lay[2], kk[2], nv = 0;
@@ -363,33 +371,34 @@ __device__ __forceinline__ void sum_local(const DevMesh& m, const double* __rest
         const int slot = slots[s];
         const int c = slot / np2, pos = slot - c * np2;
         for (int a = 0; a < nv; ++a) {
-            const int64_t idx = int64_t(c * m.n_z + lay[a]) * np3 + pos + np2 * kk[a];
+            const int64_t idx = col ? (int64_t(c) * np2 + pos) * (int64_t(m.n_z) * np1) + lay[a] * np1 + kk[a]
+                                    : int64_t(c * m.n_z + lay[a]) * np3 + pos + np2 * kk[a];
 #pragma unroll
             for (int f = 0; f < NF; ++f) out[f] += rE[f * es + idx];
         }
     }
 }
 
-__global__ void k_assemble(DevMesh m, const double* __restrict__ rE, double* __restrict__ acc) {
+__global__ void k_assemble(DevMesh m, const double* __restrict__ rE, double* __restrict__ acc, bool col) {
     const int64_t n = int64_t(m.n_h) * m.nzn;
     for (int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; t < n;
          t += int64_t(gridDim.x) * blockDim.x) {
         const int h = int(t / m.nzn), kz = int(t % m.nzn);
         double s[NF];
-        sum_local(m, rE, m.asm_slot, m.asm_ptr[h], m.asm_ptr[h + 1], kz, s);
+        sum_local(m, rE, m.asm_slot, m.asm_ptr[h], m.asm_ptr[h + 1], kz, s, col);
         const int64_t o = int64_t(h) * m.ldz + kz, fs = int64_t(m.n_h) * m.ldz;
 #pragma unroll
         for (int f = 0; f < NF; ++f) acc[f * fs + o] = s[f];
     }
 }
 
-__global__ void k_assemble_hang(DevMesh m, const double* __restrict__ rE, double* __restrict__ cH) {
+__global__ void k_assemble_hang(DevMesh m, const double* __restrict__ rE, double* __restrict__ cH, bool col) {
     const int64_t n = int64_t(m.n_hh) * m.nzn;
     for (int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; t < n;
          t += int64_t(gridDim.x) * blockDim.x) {
         const int hh = int(t / m.nzn), kz = int(t % m.nzn);
         double s[NF];
-        sum_local(m, rE, m.asmH_slot, m.asmH_ptr[hh], m.asmH_ptr[hh + 1], kz, s);
+        sum_local(m, rE, m.asmH_slot, m.asmH_ptr[hh], m.asmH_ptr[hh + 1], kz, s, col);
         const int64_t o = int64_t(hh) * m.ldz + kz, fsh = int64_t(m.n_hh) * m.ldz;
 #pragma unroll
         for (int f = 0; f < NF; ++f) cH[f * fsh + o] = s[f];
@@ -571,9 +580,10 @@ int check_mesh(const sem_mesh* M) {
 }  // namespace
 
 // m * (sub-grid + absorbing-layer tendency) of every element into rE
-// (added to what is there when accumulate is true)
+// (added to what is there when accumulate is true), in the element layout or
+// in column rows (col)
 int launch_dissip(const sem_mesh* M, const double* q, const double* hv, double* rE, bool accumulate,
-                  hipStream_t s) {
+                  bool col, hipStream_t s) {
     const DevMesh& d = M->d;
     const int nb = d.n_col * d.n_z;
     switch (d.N) {
@@ -581,7 +591,7 @@ int launch_dissip(const sem_mesh* M, const double* q, const double* hv, double* 
     case NN:                                                                                      \
         hipLaunchKernelGGL((sem::k_dissip<NN + 1>), dim3(nb),                                     \
                            dim3((((NN + 1) * (NN + 1) * (NN + 1) + 63) / 64) * 64), 0, s, d, q, hv, \
-                           rE, accumulate);                                                       \
+                           rE, accumulate, col);                                                  \
         break;
         CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
 #undef CASE
@@ -599,7 +609,7 @@ static int sem_launch_rhs(const sem_mesh* M, const double* q, const double* hv, 
     if (prec == SEM_FP64) rc = launch_rhs_t<double>(M, q, hv, rE, s);
     else if (prec == SEM_FP32) rc = launch_rhs_t<float>(M, q, hv, rE, s);
     else return fail(SEM_ERR_ARG, "precision must be SEM_FP64 or SEM_FP32");
-    if (rc == SEM_OK && dissipation_on(M)) rc = launch_dissip(M, q, hv, rE, true, s);
+    if (rc == SEM_OK && dissipation_on(M)) rc = launch_dissip(M, q, hv, rE, true, false, s);
     return rc;
 }
 
@@ -613,13 +623,15 @@ int dissip_prepass(const sem_mesh* M, const double* q, hipStream_t s) {
                            M->diss_c);
         hv = M->diss_c;
     }
-    int rc = launch_dissip(M, q, hv, M->diss_rE, false, s);
+    // the pre-pass's own element buffer in column rows: the assembly then
+    // reads consecutive kz from consecutive addresses
+    int rc = launch_dissip(M, q, hv, M->diss_rE, false, true, s);
     if (rc != SEM_OK) return rc;
     hipLaunchKernelGGL(sem::k_assemble, dim3(grid_for(int64_t(d.n_h) * d.nzn)), dim3(256), 0, s, d, M->diss_rE,
-                       M->diss_acc);
+                       M->diss_acc, true);
     if (d.n_hh > 0) {
         hipLaunchKernelGGL(sem::k_assemble_hang, dim3(grid_for(int64_t(d.n_hh) * d.nzn)), dim3(256), 0, s, d,
-                           M->diss_rE, M->diss_c);
+                           M->diss_rE, M->diss_c, true);
         hipLaunchKernelGGL(sem::k_nc_gather, dim3(grid_for(int64_t(d.n_hT) * d.nzn)), dim3(256), 0, s, d,
                            M->diss_c, M->diss_acc);
     }
@@ -924,9 +936,11 @@ int sem_dss(const sem_mesh* M, int phase, const double* rE, double* acc, double*
     hipStream_t s = (hipStream_t)stream;
     if (phase == SEM_ASSEMBLE) {
         if (!rE || !acc || (d.n_hh > 0 && !c)) return fail(SEM_ERR_ARG, "null array");
-        hipLaunchKernelGGL(sem::k_assemble, dim3(grid_for(int64_t(d.n_h) * d.nzn)), dim3(256), 0, s, d, rE, acc);
+        hipLaunchKernelGGL(sem::k_assemble, dim3(grid_for(int64_t(d.n_h) * d.nzn)), dim3(256), 0, s, d, rE, acc,
+                           false);
         if (d.n_hh > 0)
-            hipLaunchKernelGGL(sem::k_assemble_hang, dim3(grid_for(int64_t(d.n_hh) * d.nzn)), dim3(256), 0, s, d, rE, c);
+            hipLaunchKernelGGL(sem::k_assemble_hang, dim3(grid_for(int64_t(d.n_hh) * d.nzn)), dim3(256), 0, s, d, rE, c,
+                               false);
     } else if (phase == SEM_FINALIZE) {
         if (!acc || !r) return fail(SEM_ERR_ARG, "null array");
         hipLaunchKernelGGL(sem::k_finalize, dim3(grid_for(int64_t(d.n_h) * d.nzn)), dim3(256), 0, s, d, acc, r);
