@@ -203,24 +203,34 @@ k_rhs(DevMesh m, const double* __restrict__ q, const double* __restrict__ hv,
 // R_f -= R(kz) q'_f for every field.  accumulate = true adds to rE (the
 // unfused element right-hand side), false overwrites it; col selects the
 // column-row layout of rE (see sum_local).
+// stacked elements of one column per workgroup (about 500 threads)
 template <int NP>
-__global__ void __launch_bounds__(((NP * NP * NP + 63) / 64) * 64)
+constexpr int dissip_layers() { return NP * NP * NP <= 125 ? 4 : (NP * NP * NP <= 343 ? 2 : 1); }
+
+template <int NP>
+__global__ void __launch_bounds__(((dissip_layers<NP>() * NP * NP * NP + 63) / 64) * 64)
 k_dissip(DevMesh m, const double* __restrict__ q, const double* __restrict__ hv,
          double* __restrict__ rE, bool accumulate, bool col) {
     constexpr int NP2 = NP * NP, NP3 = NP2 * NP;
     constexpr int N = NP - 1;
-    __shared__ double sv[3][NP3];       // u, v, w
-    __shared__ double st[5][NP3];       // 2 nu (S_xx, S_xy, S_yy, S_xz, S_yz)
+    constexpr int L = dissip_layers<NP>(), NPL = L * NP3;
+    __shared__ double sv[3][NPL];       // u, v, w of the L elements
+    __shared__ double st[5][NPL];       // 2 nu (S_xx, S_xy, S_yy, S_xz, S_yz)
     __shared__ double sD[NP2];
     __shared__ double s_zs[NP2];        // terrain: surface height per position
-    const int e = blockIdx.x;
-    const int c = e / m.n_z, layer = e - c * m.n_z;
+    const int nzb = (m.n_z + L - 1) / L;
+    const int c = blockIdx.x / nzb, layer0 = (blockIdx.x - c * nzb) * L;
     const int t = threadIdx.x;
     if (t < NP2) sD[t] = m.D[t];
-    // node of this thread, k fastest (vertical runs of the state and of the
-    // column-row output are contiguous); tl is its element-local index
-    const int k = t % NP, i = (t / NP) % NP, j = t / NP2;
-    const int tl = i + NP * (j + NP * k);
+    // node of this thread, k fastest, then the element of the stack (vertical
+    // runs of the state and of the column-row output are contiguous); tl is
+    // its index in the LDS tiles, el * NP3 + the element-local index
+    const int k = t % NP, el = (t / NP) % L, i = (t / (NP * L)) % NP, j = t / (NP * L * NP);
+    const int layer = layer0 + el;
+    const bool active = t < NPL && layer < m.n_z;
+    const int e = c * m.n_z + layer;
+    const int eo = el * NP3;
+    const int tl = eo + i + NP * (j + NP * k);
     const int kz = layer * N + k;
     const int64_t fs = int64_t(m.n_h) * m.ldz, fsh = int64_t(m.n_hh) * m.ldz;
     const bool ter = m.zs != nullptr;
@@ -229,7 +239,7 @@ k_dissip(DevMesh m, const double* __restrict__ q, const double* __restrict__ hv,
         s_zs[t] = m.zs[gz >= 0 ? gz : m.n_h - gz - 1];
     }
     double x[NF] = {0, 0, 0, 0, 0};
-    if (t < NP3) {
+    if (active) {
         const int g = m.gmap[c * NP2 + i + NP * j];
         if (g >= 0) {
 #pragma unroll
@@ -243,12 +253,12 @@ k_dissip(DevMesh m, const double* __restrict__ q, const double* __restrict__ hv,
         sv[2][tl] = x[3];
     }
     __syncthreads();
-    const double sx = 2.0 / m.col_dx[c], sy = 2.0 / m.col_dy[c], sz = 2.0 / m.dz[layer];
+    const double sx = 2.0 / m.col_dx[c], sy = 2.0 / m.col_dy[c], sz = active ? 2.0 / m.dz[layer] : 0.0;
     // terrain-following mapping: d/dx = box d/dx + a_x d/dzf, d/dy likewise,
     // d/dz = g_s d/dzf (g_s = 1/(1 - zs/(H - z0)), a_x = -g_s (H - zf)/(H - z0) dzs/dx);
     // the lumped mass gains 1/g_s
     double ax = 0.0, ay = 0.0, gs = 1.0, mfac = 1.0;
-    if (ter && t < NP3) {
+    if (ter && active) {
         double zx = 0.0, zy = 0.0;
         for (int mm = 0; mm < NP; ++mm) {
             zx += sD[i * NP + mm] * s_zs[mm + NP * j];
@@ -262,11 +272,12 @@ k_dissip(DevMesh m, const double* __restrict__ q, const double* __restrict__ hv,
     }
     double R[NF] = {0, 0, 0, 0, 0};
     const bool sgs = m.cs > 0.0;
-    if (sgs && t < NP3) {
+    if (sgs && active) {
         double g3[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};   // g3[a][b] = d(u_a)/d(x_b)
         for (int mm = 0; mm < NP; ++mm) {
             const double dxm = sD[i * NP + mm], dym = sD[j * NP + mm], dzm = sD[k * NP + mm];
-            const int ox = mm + NP * (j + NP * k), oy = i + NP * (mm + NP * k), oz = i + NP * (j + NP * mm);
+            const int ox = eo + mm + NP * (j + NP * k), oy = eo + i + NP * (mm + NP * k),
+                      oz = eo + i + NP * (j + NP * mm);
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 g3[a][0] += dxm * sv[a][ox];
@@ -299,12 +310,13 @@ k_dissip(DevMesh m, const double* __restrict__ q, const double* __restrict__ hv,
         st[4][tl] = two_nu * syz;
     }
     __syncthreads();
-    if (t >= NP3) return;
+    if (!active) return;
     if (sgs) {
         double dx_[5] = {0, 0, 0, 0, 0}, dy_[5] = {0, 0, 0, 0, 0}, dz_[5] = {0, 0, 0, 0, 0};
         for (int mm = 0; mm < NP; ++mm) {
             const double dxm = sD[i * NP + mm], dym = sD[j * NP + mm], dzm = sD[k * NP + mm];
-            const int ox = mm + NP * (j + NP * k), oy = i + NP * (mm + NP * k), oz = i + NP * (j + NP * mm);
+            const int ox = eo + mm + NP * (j + NP * k), oy = eo + i + NP * (mm + NP * k),
+                      oz = eo + i + NP * (j + NP * mm);
 #pragma unroll
             for (int a = 0; a < 5; ++a) {
                 dx_[a] += dxm * st[a][ox];
@@ -342,7 +354,7 @@ k_dissip(DevMesh m, const double* __restrict__ q, const double* __restrict__ hv,
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
         const int64_t o = f * es + (col ? (int64_t(c) * NP2 + i + NP * j) * (int64_t(m.n_z) * NP) + layer * NP + k
-                                        : int64_t(e) * NP3 + tl);
+                                        : int64_t(e) * NP3 + (tl - eo));
         rE[o] = (accumulate ? rE[o] : 0.0) + mass * R[f];
     }
 }
@@ -405,28 +417,51 @@ __global__ void k_assemble_hang(DevMesh m, const double* __restrict__ rE, double
     }
 }
 
+// r = M_G^-1 acc at unique node (h, kz), then the boundary rules: rigid lids;
+// with terrain the surface keeps only the tangential part of the momentum
+// tendency
+__device__ __forceinline__ void finalize_node(const DevMesh& m, int h, int kz, double* v) {
+    const bool ter = m.zs != nullptr;
+    const double minv = (ter ? m.minv_ht[h] : m.minv_h[h]) * m.minv_v[kz];
+    const bool lid = ter ? (kz == m.nzn - 1) : (kz == 0 || kz == m.nzn - 1);
+#pragma unroll
+    for (int f = 0; f < NF; ++f) v[f] *= minv;
+    if (ter && kz == 0) {
+        const double n0 = m.nrm[h], n1 = m.nrm[m.n_h + h], n2 = m.nrm[2 * m.n_h + h];
+        const double dn = v[1] * n0 + v[2] * n1 + v[3] * n2;
+        v[1] -= dn * n0;
+        v[2] -= dn * n1;
+        v[3] -= dn * n2;
+    }
+    if (lid) v[3] = 0.0;
+}
+
 __global__ void k_finalize(DevMesh m, const double* __restrict__ acc, double* __restrict__ r) {
     const int64_t n = int64_t(m.n_h) * m.nzn;
     for (int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; t < n;
          t += int64_t(gridDim.x) * blockDim.x) {
         const int h = int(t / m.nzn), kz = int(t % m.nzn);
-        const bool ter = m.zs != nullptr;
-        const double minv = (ter ? m.minv_ht[h] : m.minv_h[h]) * m.minv_v[kz];
-        // rigid lids; with terrain the surface keeps only the tangential part
-        // of the momentum tendency
-        const bool lid = ter ? (kz == m.nzn - 1) : (kz == 0 || kz == m.nzn - 1);
         const int64_t o = int64_t(h) * m.ldz + kz, fs = int64_t(m.n_h) * m.ldz;
         double v[NF];
 #pragma unroll
-        for (int f = 0; f < NF; ++f) v[f] = acc[f * fs + o] * minv;
-        if (ter && kz == 0) {
-            const double n0 = m.nrm[h], n1 = m.nrm[m.n_h + h], n2 = m.nrm[2 * m.n_h + h];
-            const double dn = v[1] * n0 + v[2] * n1 + v[3] * n2;
-            v[1] -= dn * n0;
-            v[2] -= dn * n1;
-            v[3] -= dn * n2;
-        }
-        if (lid) v[3] = 0.0;
+        for (int f = 0; f < NF; ++f) v[f] = acc[f * fs + o];
+        finalize_node(m, h, kz, v);
+#pragma unroll
+        for (int f = 0; f < NF; ++f) r[f * fs + o] = v[f];
+    }
+}
+
+// assemble and finalize in one pass, for meshes without hanging points (no
+// Z^T contribution has to arrive between the two)
+__global__ void k_assemble_finalize(DevMesh m, const double* __restrict__ rE, double* __restrict__ r, bool col) {
+    const int64_t n = int64_t(m.n_h) * m.nzn;
+    for (int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; t < n;
+         t += int64_t(gridDim.x) * blockDim.x) {
+        const int h = int(t / m.nzn), kz = int(t % m.nzn);
+        double v[NF];
+        sum_local(m, rE, m.asm_slot, m.asm_ptr[h], m.asm_ptr[h + 1], kz, v, col);
+        finalize_node(m, h, kz, v);
+        const int64_t o = int64_t(h) * m.ldz + kz, fs = int64_t(m.n_h) * m.ldz;
 #pragma unroll
         for (int f = 0; f < NF; ++f) r[f * fs + o] = v[f];
     }
@@ -585,14 +620,16 @@ int check_mesh(const sem_mesh* M) {
 int launch_dissip(const sem_mesh* M, const double* q, const double* hv, double* rE, bool accumulate,
                   bool col, hipStream_t s) {
     const DevMesh& d = M->d;
-    const int nb = d.n_col * d.n_z;
     switch (d.N) {
 #define CASE(NN)                                                                                  \
-    case NN:                                                                                      \
+    case NN: {                                                                                    \
+        constexpr int L = sem::dissip_layers<NN + 1>();                                           \
+        const int nb = d.n_col * ((d.n_z + L - 1) / L);                                           \
         hipLaunchKernelGGL((sem::k_dissip<NN + 1>), dim3(nb),                                     \
-                           dim3((((NN + 1) * (NN + 1) * (NN + 1) + 63) / 64) * 64), 0, s, d, q, hv, \
-                           rE, accumulate, col);                                                  \
-        break;
+                           dim3(((L * (NN + 1) * (NN + 1) * (NN + 1) + 63) / 64) * 64), 0, s, d, q, \
+                           hv, rE, accumulate, col);                                              \
+        break;                                                                                    \
+    }
         CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
 #undef CASE
         default: return fail(SEM_ERR_N, "unsupported N");
@@ -627,14 +664,18 @@ int dissip_prepass(const sem_mesh* M, const double* q, hipStream_t s) {
     // reads consecutive kz from consecutive addresses
     int rc = launch_dissip(M, q, hv, M->diss_rE, false, true, s);
     if (rc != SEM_OK) return rc;
+    if (d.n_hh == 0) {
+        hipLaunchKernelGGL(sem::k_assemble_finalize, dim3(grid_for(int64_t(d.n_h) * d.nzn)), dim3(256), 0, s, d,
+                           M->diss_rE, M->diss_r, true);
+        HIPCHK(hipGetLastError());
+        return SEM_OK;
+    }
     hipLaunchKernelGGL(sem::k_assemble, dim3(grid_for(int64_t(d.n_h) * d.nzn)), dim3(256), 0, s, d, M->diss_rE,
                        M->diss_acc, true);
-    if (d.n_hh > 0) {
-        hipLaunchKernelGGL(sem::k_assemble_hang, dim3(grid_for(int64_t(d.n_hh) * d.nzn)), dim3(256), 0, s, d,
-                           M->diss_rE, M->diss_c, true);
-        hipLaunchKernelGGL(sem::k_nc_gather, dim3(grid_for(int64_t(d.n_hT) * d.nzn)), dim3(256), 0, s, d,
-                           M->diss_c, M->diss_acc);
-    }
+    hipLaunchKernelGGL(sem::k_assemble_hang, dim3(grid_for(int64_t(d.n_hh) * d.nzn)), dim3(256), 0, s, d,
+                       M->diss_rE, M->diss_c, true);
+    hipLaunchKernelGGL(sem::k_nc_gather, dim3(grid_for(int64_t(d.n_hT) * d.nzn)), dim3(256), 0, s, d,
+                       M->diss_c, M->diss_acc);
     hipLaunchKernelGGL(sem::k_finalize, dim3(grid_for(int64_t(d.n_h) * d.nzn)), dim3(256), 0, s, d, M->diss_acc,
                        M->diss_r);
     HIPCHK(hipGetLastError());
