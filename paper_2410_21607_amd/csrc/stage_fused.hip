@@ -33,6 +33,7 @@
 
 #include <algorithm>
 #include <string>
+#include <type_traits>
 
 #include "mesh_build.h"
 #include "sem.h"
@@ -96,6 +97,10 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
     __shared__ T tile[NT][NP2 * NK];              // [field][p][kzl], kzl fastest
     __shared__ double carry[2][NF][NP2];
     __shared__ T sD[NP2];
+    // per position and tap, the x and y coefficients side by side: one 2-wide
+    // LDS read serves both derivatives of a call
+    using T2 = typename std::conditional<sizeof(T) == 8, double2, float2>::type;
+    __shared__ T2 sDxy[NP2 * NP];
     __shared__ double sW[NP];
     // the chunk's slice of the per-level tables, double-buffered: rho0,
     // 1/rho0, 1/theta0, p0, dtheta0/dz, 1/M_v at its NK levels, then dz and
@@ -104,6 +109,11 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
     __shared__ double slice[2][SL];
     const int tid = threadIdx.x;
     for (int t = tid; t < NP2; t += WGT) sD[t] = T(m.D[t]);
+    for (int t = tid; t < NP2 * NP; t += WGT) {
+        const int pp = t / NP, mm = t - pp * NP;
+        sDxy[t].x = T(m.D[(pp % NP) * NP + mm]);
+        sDxy[t].y = T(m.D[(pp / NP) * NP + mm]);
+    }
     for (int t = tid; t < NP; t += WGT) sW[t] = m.w[t];
     // this thread's slice entry: source table, offset, step per chunk, limit
     const double* sl_src = nullptr;
@@ -208,8 +218,7 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
     }
     __syncthreads();
     for (int t = tid; t < NP2; t += WGT) s_mij[t] = sW[t % NP] * sW[t / NP] * 0.125 * dxc * dyc;
-    const T* Dx = &sD[i * NP];
-    const T* Dy = &sD[j * NP];
+    const T2* Dxy = &sDxy[pc * NP];
     const int lx0 = (j * NP) * NK + kzl, ly0 = i * NK + kzl;
     const int rrow = TER ? (g >= 0 ? g : m.n_h - g - 1) : 0;   // terrain reference row
     // terrain: g_s and g_s times the box derivatives of zs per position (LDS)
@@ -330,7 +339,8 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
                 T ax = 0, ay = 0, ax2 = 0, ay2 = 0;
 #pragma unroll
                 for (int mm = 0; mm < NP; ++mm) {
-                    const T cx = Dx[mm], cy = Dy[mm];
+                    const T2 cxy = Dxy[mm];
+                    const T cx = cxy.x, cy = cxy.y;
                     ax += cx * tile[tx][lx0 + mm * NK];
                     ay += cy * tile[ty][ly0 + mm * NP * NK];
                     ax2 += cx * tile[tx2][lx0 + mm * NK];
