@@ -43,7 +43,7 @@ namespace sem {
 namespace {
 
 constexpr int NF = SEM_NFIELDS;
-constexpr int NT = 8;   // LDS tiles: rho u, rho v, rho w, u, v, w, p', theta'
+// LDS tiles: rho u, rho v, rho w and u singly; (v, w) and (p', theta') as pairs
 
 template <int NP, int LPC>
 constexpr int wg_threads() {
@@ -94,13 +94,16 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
     constexpr int NP2 = NP * NP, N = NP - 1;
     constexpr int NK = LPC * N + 1;               // vertical nodes of a full chunk
     constexpr int WGT = wg_threads<NP, LPC>();
-    __shared__ T tile[NT][NP2 * NK];              // [field][p][kzl], kzl fastest
+    __shared__ T tile[4][NP2 * NK];               // rho u, rho v, rho w, u: [field][p][kzl], kzl fastest
     __shared__ double carry[2][NF][NP2];
     __shared__ T sD[NP2];
     // per position and tap, the x and y coefficients side by side: one 2-wide
     // LDS read serves both derivatives of a call
     using T2 = typename std::conditional<sizeof(T) == 8, double2, float2>::type;
     __shared__ T2 sDxy[NP2 * NP];
+    // (v, w) and (p', theta'), always differentiated together: one 2-wide
+    // element per node, so one LDS read per tap serves both fields
+    __shared__ T2 tpr[2][NP2 * NK];
     __shared__ double sW[NP];
     // the chunk's slice of the per-level tables, double-buffered: rho0,
     // 1/rho0, 1/theta0, p0, dtheta0/dz, 1/M_v at its NK levels, then dz and
@@ -289,8 +292,12 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
             tile[1][lidx] = rho * v;
             tile[2][lidx] = rho * w;
             tile[3][lidx] = u;
-            tile[4][lidx] = v;
-            tile[5][lidx] = w;
+            {
+                T2 vw;
+                vw.x = v;
+                vw.y = w;
+                tpr[0][lidx] = vw;
+            }
             {
                 // p' = p0 ((rho theta)/(rho0 theta0))^gamma - p0 with x = a + b + a b,
                 // a = rho'/rho0, b = theta'/theta0 (no cancellation against p0).
@@ -299,9 +306,11 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
                 // cancels most of dp'/dz, so a float evaluation's few-ulp error
                 // would dominate the float variant's error there.
                 const double ra = qv[0] * irho0, tb = qv[4] * ith0;
-                tile[6][lidx] = T(p0v * pow1p_minus1(m, ra + tb + ra * tb));
+                T2 pt;
+                pt.x = T(p0v * pow1p_minus1(m, ra + tb + ra * tb));
+                pt.y = T(qv[4]);
+                tpr[1][lidx] = pt;
             }
-            tile[7][lidx] = T(qv[4]);
         }
         __syncthreads();
         // update base of the nodes finished in this chunk (q^n for the first
@@ -352,6 +361,25 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
                 ox2 = ax2 * sx;
                 oy2 = ay2 * sy;
             };
+            // the same for the two fields of a pair
+            auto dxyp = [&](int pr, T& ox, T& oy, T& ox2, T& oy2) {
+                T ax = 0, ay = 0, ax2 = 0, ay2 = 0;
+#pragma unroll
+                for (int mm = 0; mm < NP; ++mm) {
+                    const T2 cxy = Dxy[mm];
+                    const T cx = cxy.x, cy = cxy.y;
+                    const T2 a = tpr[pr][lx0 + mm * NK], b = tpr[pr][ly0 + mm * NP * NK];
+                    ax += cx * a.x;
+                    ay += cy * b.x;
+                    ax2 += cx * a.y;
+                    ay2 += cy * b.y;
+                }
+                asm volatile("" : "+v"(ax), "+v"(ay), "+v"(ax2), "+v"(ay2) : : "memory");
+                ox = ax * sx;
+                oy = ay * sy;
+                ox2 = ax2 * sx;
+                oy2 = ay2 * sy;
+            };
             const T u = T(qv[1]), v = T(qv[2]), w = T(qv[3]);
             const T inv_rho = T(1) / rho;
             const T f = T(m.f), gr = T(m.g);
@@ -360,10 +388,10 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
             dxy(0, 1, 3, 3, ax, ay, bx, by);
             Rh[0] = -(ax + ay);
             Rh[1] = -(u * bx + v * by) + f * v;
-            dxy(4, 4, 5, 5, ax, ay, bx, by);
+            dxyp(0, ax, ay, bx, by);
             Rh[2] = -(u * ax + v * ay) - f * u;
             Rh[3] = -(u * bx + v * by) - T(qv[0]) * inv_rho * gr;
-            dxy(6, 6, 7, 7, bx, by, ax, ay);
+            dxyp(1, bx, by, ax, ay);
             Rh[1] -= bx * inv_rho;
             Rh[2] -= by * inv_rho;
             if constexpr (TER) {
@@ -404,27 +432,40 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
                     oz = az * sz;
                     oz2 = az2 * sz;
                 };
+                auto ddzp = [&](int pr, T& oz, T& oz2) {
+                    T az = 0, az2 = 0;
+#pragma unroll
+                    for (int mm = 0; mm < NP; ++mm) {
+                        const T cz = Dz[mm];
+                        const T2 a = tpr[pr][lz0 + mm];
+                        az += cz * a.x;
+                        az2 += cz * a.y;
+                    }
+                    asm volatile("" : "+v"(az), "+v"(az2) : : "memory");
+                    oz = az * sz;
+                    oz2 = az2 * sz;
+                };
                 T R[NF], z0, z1;
                 if constexpr (TER) {
-                    ddz(6, 7, z0, z1);
+                    ddzp(1, z0, z1);
                     const T pz = z0 * inv_rho;
                     R[4] = Rh[4] - wt * z1;
-                    ddz(3, 4, z0, z1);
-                    R[1] = Rh[1] - wt * z0 - a_x * pz;
-                    R[2] = Rh[2] - wt * z1 - a_y * pz;
+                    ddzp(0, z0, z1);
+                    R[2] = Rh[2] - wt * z0 - a_y * pz;
+                    R[3] = Rh[3] - wt * z1 - gs * pz;
                     T z2, z3;
                     ddz(0, 1, z0, z1);
-                    ddz(2, 5, z2, z3);
+                    ddz(2, 3, z2, z3);
                     R[0] = Rh[0] - (a_x * z0 + a_y * z1 + gs * z2);
-                    R[3] = Rh[3] - wt * z3 - gs * pz;
+                    R[1] = Rh[1] - wt * z3 - a_x * pz;
                 } else {
                     ddz(2, 3, z0, z1);
                     R[0] = Rh[0] - z0;
                     R[1] = Rh[1] - w * z1;
-                    ddz(4, 5, z0, z1);
+                    ddzp(0, z0, z1);
                     R[2] = Rh[2] - w * z0;
                     T z2, z3;
-                    ddz(6, 7, z2, z3);
+                    ddzp(1, z2, z3);
                     R[3] = Rh[3] - w * z1 - z2 * inv_rho;
                     R[4] = Rh[4] - w * z3;
                 }
