@@ -215,9 +215,13 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
     // per-position constants in LDS rather than in every thread's registers:
     // the horizontal inverse mass and the horizontal mass weight
     __shared__ double s_mh[NP2], s_mij[NP2];
+    // row offset g * ldz of every direct position (read where needed rather
+    // than kept in registers across the chunk loop)
+    __shared__ int64_t s_row[NP2];
     for (int t = tid; t < NP2; t += WGT) {
         const int gt = m.gmap[col * NP2 + t];
         s_mh[t] = gt >= 0 ? (TER ? m.minv_ht[gt] : m.minv_h[gt]) : 0.0;
+        s_row[t] = gt >= 0 ? int64_t(gt) * m.ldz : 0;
     }
     __syncthreads();
     for (int t = tid; t < NP2; t += WGT) s_mij[t] = sW[t % NP] * sW[t / NP] * 0.125 * dxc * dyc;
@@ -259,7 +263,7 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
 #pragma unroll
                     for (int f = 0; f < NF; ++f) qv[f] = pf[f];
                 } else {
-                    const int64_t o = int64_t(g) * m.ldz + kz;
+                    const int64_t o = s_row[pc] + kz;
 #pragma unroll
                     for (int f = 0; f < NF; ++f) qv[f] = qs[f * fs + o];
                 }
@@ -318,7 +322,7 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
         double base[NF] = {0, 0, 0, 0, 0};
         if (!TER && active && g >= 0 && !(kzl == nk - 1 && L1 < m.n_z) && (!first || a != 0.0)) {
             const double* bp = first ? qn : qo;
-            const int64_t o = int64_t(g) * m.ldz + kz;
+            const int64_t o = s_row[pc] + kz;
 #pragma unroll
             for (int f = 0; f < NF; ++f) base[f] = bp[f * fs + o];
         }
@@ -331,7 +335,7 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
             const int L0n = L0 + LPC;
             const int nkn = (min(L0n + LPC, m.n_z) - L0n) * N + 1;
             if (kzl < nkn) {
-                const int64_t o = int64_t(g) * m.ldz + L0n * N + kzl;
+                const int64_t o = s_row[pc] + L0n * N + kzl;
 #pragma unroll
                 for (int f = 0; f < NF; ++f) pf[f] = qs[f * fs + o];
             }
@@ -503,7 +507,7 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
                         lid = (kz == nzn - 1);
                     }
                     const double mi = c * s_mh[pc] * sb[5 * NK + kzl];
-                    const int64_t o = int64_t(g) * m.ldz + kz;
+                    const int64_t o = s_row[pc] + kz;
                     if (TER && (!first || a != 0.0)) {
                         // the terrain instance loads its base here (registers)
                         const double* bp = first ? qn : qo;
