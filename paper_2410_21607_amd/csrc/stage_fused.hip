@@ -218,16 +218,19 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
     // row offset g * ldz of every direct position (read where needed rather
     // than kept in registers across the chunk loop)
     __shared__ int64_t s_row[NP2];
+    // terrain: row offset of every position's reference rows (hanging points
+    // after the unique nodes)
+    __shared__ int64_t s_rrow[TER ? NP2 : 1];
     for (int t = tid; t < NP2; t += WGT) {
         const int gt = m.gmap[col * NP2 + t];
         s_mh[t] = gt >= 0 ? (TER ? m.minv_ht[gt] : m.minv_h[gt]) : 0.0;
         s_row[t] = gt >= 0 ? int64_t(gt) * m.ldz : 0;
+        if constexpr (TER) s_rrow[t] = int64_t(gt >= 0 ? gt : m.n_h - gt - 1) * m.ldz;
     }
     __syncthreads();
     for (int t = tid; t < NP2; t += WGT) s_mij[t] = sW[t % NP] * sW[t / NP] * 0.125 * dxc * dyc;
     const T2* Dxy = &sDxy[pc * NP];
     const int lx0 = (j * NP) * NK + kzl, ly0 = i * NK + kzl;
-    const int rrow = TER ? (g >= 0 ? g : m.n_h - g - 1) : 0;   // terrain reference row
     // terrain: g_s and g_s times the box derivatives of zs per position (LDS)
     if constexpr (TER) {
         for (int t = tid; t < NP2; t += WGT) {
@@ -278,7 +281,7 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
             double r0d, irho0, ith0, p0v;
             if constexpr (TER) {
                 // per node; hanging rows hold the coarse face's interpolant
-                const int64_t o = int64_t(rrow) * m.ldz + kz;
+                const int64_t o = s_rrow[pc] + kz;
                 r0d = m.ref_n[o];
                 irho0 = m.ref_n[fsr + o];
                 ith0 = m.ref_n[2 * fsr + o];
@@ -399,7 +402,7 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
             Rh[1] -= bx * inv_rho;
             Rh[2] -= by * inv_rho;
             if constexpr (TER) {
-                Rh[4] = -(u * ax + v * ay) - w * T(m.ref_n[4 * fsr + int64_t(rrow) * m.ldz + kz]);
+                Rh[4] = -(u * ax + v * ay) - w * T(m.ref_n[4 * fsr + s_rrow[pc] + kz]);
             }
             else Rh[4] = -(u * ax + v * ay) - w * T(sb[4 * NK + kzl]);
             // terrain: a_x, a_y and the advecting vertical speed per node
