@@ -14,7 +14,9 @@ roofline : HBM roofline of the fused stage, algorithmic bytes 80 B (stage 1)
            stream it replays on; `traffic` is the HBM bytes per stage read from
            the committed rocprofv3 counter summary when it matches the kernel
            source, else null
-cpu_baseline : the FP64 oracle on the host, one stage of the same workload
+cpu_baseline : the FP64 oracle on the host cores, timed before any GPU call
+               (one thread and all cores; this workload at 3 stages and the
+               8 x 8 x 4 workload at 10 stages)
 """
 
 import argparse
@@ -37,24 +39,51 @@ def algorithmic_bytes(n_dof, stage):
     return n_dof * (80 if stage == 0 else 120)
 
 
-def cpu_baseline(case, n_stages=1):
-    """Time the oracle (as it stands) on one stage of the same workload."""
+def cpu_baseline(plan=(("vortex_8x8x4_n4", 10), (WORKLOAD, 3))):
+    """Time the oracle (as it stands, never tuned) on the host cores before
+    any GPU call: for every (workload, stages) of the plan, the stages once
+    with the BLAS/OpenMP pools at one thread and once at every core of this
+    process's affinity mask.  The mesh and initial state are built once per
+    workload and not timed.  value = the bench workload's rate with all
+    cores; each leg also reports process CPU time over wall time, the
+    parallelism the oracle actually reached."""
     import numpy as np
+    from threadpoolctl import threadpool_limits
     from oracle import assembly, timestep
     from oracle.mesh import OracleMesh
     from synth import cases
-    om = OracleMesh(case["N"], case["nx0"], case["ny0"], case["Lx"], case["Ly"], case["z_edges"],
-                    case["columns"], case["periodic_x"], case["periodic_y"])
-    q0 = cases.initial_state(case, om.node_xyz)
-    bl = cases.reference_state(case, om.zl)
-    ref = dict(rho0=bl["rho0"], theta0=bl["theta0"], dtheta0dz=bl["dtheta0dz"])
-    t = time.perf_counter()
-    timestep.run_stages(lambda q: assembly.rhs(om, q, ref, case["phys"]), q0, case["dt"], n_stages)
-    el = time.perf_counter() - t
-    return {"value": om.n_dof * n_stages / el, "unit": "DOF-stage/s", "cores": 1,
+    n_cores = len(os.sched_getaffinity(0))
+    legs = []
+    for name, n_stages in plan:
+        case = cases.get(name)
+        om = OracleMesh(case["N"], case["nx0"], case["ny0"], case["Lx"], case["Ly"], case["z_edges"],
+                        case["columns"], case["periodic_x"], case["periodic_y"])
+        q0 = cases.initial_state(case, om.node_xyz)
+        bl = cases.reference_state(case, om.zl)
+        ref = dict(rho0=bl["rho0"], theta0=bl["theta0"], dtheta0dz=bl["dtheta0dz"])
+        for threads in (1, n_cores):
+            with threadpool_limits(limits=threads):
+                w0, c0 = time.perf_counter(), time.process_time()
+                timestep.run_stages(lambda q: assembly.rhs(om, q, ref, case["phys"]), q0, case["dt"],
+                                    n_stages)
+                wall, cpu = time.perf_counter() - w0, time.process_time() - c0
+            legs.append({"workload": name, "n_dof": int(om.n_dof), "stages": n_stages,
+                         "threads": threads, "seconds": wall,
+                         "dof_stage_per_s": om.n_dof * n_stages / wall,
+                         "ms_per_stage": wall / n_stages * 1e3,
+                         "cpu_time_over_wall": cpu / wall})
+            print(f"  cpu baseline {name}: {n_stages} stages, {threads} thread(s): {wall:.1f} s",
+                  file=sys.stderr, flush=True)
+        del om, q0, bl, ref
+    main = [g for g in legs if g["workload"] == WORKLOAD and g["threads"] == n_cores][-1]
+    return {"value": main["dof_stage_per_s"], "unit": "DOF-stage/s", "cores": n_cores,
             "kind": "oracle",
-            "sample": f"{n_stages} SSP-RK3 stage(s) of {case['name']} (full mesh, {om.n_dof} unique "
-                      f"nodes), single-threaded NumPy/SciPy, mesh setup not timed; {el:.1f} s"}
+            "sample": f"{main['stages']} SSP-RK3 stages of {WORKLOAD} (full mesh, {main['n_dof']} unique "
+                      f"nodes) with the BLAS/OpenMP pools at {n_cores} threads (the affinity mask); "
+                      f"mesh set-up not timed; the oracle's NumPy/SciPy steps ran at "
+                      f"{main['cpu_time_over_wall']:.2f} CPU-seconds per second; legs lists both "
+                      f"thread settings and the 8x8x4 workload at 10 stages",
+            "legs": legs}
 
 
 def kernel_source_hash():
@@ -154,11 +183,17 @@ def amr_throughput(device):
         fm.set_reference(bg["rho0"], bg["theta0"], bg["dtheta0dz"])
         fq = fm.unpack(cases.initial_state(fine, fm.node_xyz()), device=device)
         tf, _ = timed_run(fm, fq, case["dt"], api.SEM_FP64, 20)
+        per_node = sum(algorithmic_bytes(1, s) for s in range(3)) / 3.0
+        achieved = mesh.n_dof * per_node / t / 1e9
         out[name] = {"n_dof": int(mesh.n_dof), "n_col": int(mesh.info["n_col"]),
                      "hanging_points": int(mesh.info["n_hh"]),
                      "dof_stage_per_s": mesh.n_dof / t, "ms_per_stage": t * 1e3,
                      "uniform_finest_ms_per_stage": tf * 1e3,
-                     "cost_ratio_uniform_over_amr": tf / t}
+                     "cost_ratio_uniform_over_amr": tf / t,
+                     "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                                  "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                                  "algorithmic_bytes_per_node_stage": per_node,
+                                  "note": "wall time of graph-replayed RK3 steps"}}
         del mesh, fm, q0, fq
         torch.cuda.empty_cache()
     return out
@@ -177,9 +212,7 @@ def terrain_throughput(device, flat_ms=None, case_name=WORKLOAD, amp=2000.0, hal
     mesh = api.Mesh.from_case(case)
     hxy, _, zf = mesh.coords()
     zs = amp * np.exp(-(hxy[:, 0] ** 2 + hxy[:, 1] ** 2) / half_width ** 2)
-    zp = np.tile(zf, zs.size)
-    ze = np.asarray(case["z_edges"], dtype=np.float64)
-    zp = zp + np.repeat(zs, zf.size) * (ze[-1] - zp) / (ze[-1] - ze[0])
+    zp = mesh.heights(zs)
     bg = cases.reference_state(case, zp)
     mesh.set_terrain(zs, bg["rho0"], bg["theta0"], bg["dtheta0dz"])
     xyz = mesh.node_xyz()
@@ -433,8 +466,10 @@ def main():
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU column "
               "partition is a design, not part of this build", file=sys.stderr)
         sys.exit(2)
-    for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
-        os.environ[k] = "1"
+    # the oracle's CPU baseline runs first, before anything touches the GPU
+    cpu_base = None
+    if not (args.no_cpu_baseline or args.terrain_only or args.tstar_only or args.forecaster_only):
+        cpu_base = cpu_baseline()
 
     import numpy as np
     import torch
@@ -549,8 +584,8 @@ def main():
                           "two_level_amr": terrain_throughput(dev, case_name="amr2_64x64x8_n4")}
     if args.forecaster or not args.no_extras:
         res["amr_forecaster"] = forecaster_experiment(dev, args.fc_case, args.fc_seconds)
-    if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(case)
+    if cpu_base is not None:
+        res["cpu_baseline"] = cpu_base
     print(json.dumps(res), flush=True)
 
 

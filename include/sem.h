@@ -203,6 +203,24 @@ int sem_mesh_set_dissipation(sem_mesh *mesh, double Cs, double sponge_gamma,
 int sem_mesh_set_terrain(sem_mesh *mesh, const double *h_zs, const double *h_rho0,
                          const double *h_theta0, const double *h_dtheta0dz);
 
+/* Physical height of every unique node (host output h_z[n_dof], packed
+ * [h][kz]) under the terrain-following mapping of sem_mesh_set_terrain:
+ * z = zf + zs (H - zf) / (H - z0) for a node at flat height zf over a unique
+ * horizontal node with surface height zs.  h_zs[n_h] gives the surface to
+ * map with (it need not be set on the handle: the reference state at the
+ * physical heights is needed before sem_mesh_set_terrain); h_zs = NULL uses
+ * the handle's terrain, or flat heights when none is set.  Host only.
+ * Errors: SEM_ERR_ARG (null mesh or h_z, zs outside [0, H - z0)). */
+int sem_mesh_heights(const sem_mesh *mesh, const double *h_zs, double *h_z);
+
+/* Set-up epoch of a mesh handle: a counter that every call changing what a
+ * captured HIP graph of compute calls would read (sem_stage_tune,
+ * sem_stage_autotune, sem_mesh_set_reference, sem_mesh_set_terrain,
+ * sem_mesh_set_dissipation) increments.  A graph captured at epoch e may be
+ * replayed only while the epoch is still e; afterwards it can read freed
+ * tables or stale settings, so capture it again. */
+int sem_mesh_get_epoch(const sem_mesh *mesh, int64_t *epoch);
+
 /* Modified-DSS interpolation across nonconforming faces (Section 3.1).
  * SEM_SCATTER: d_dst = hv[F][n_hh][ldz] is overwritten with Z_h d_src, the
  *              values at hanging points interpolated from d_src = q[F][n_h][ldz].
@@ -411,6 +429,7 @@ int mlp_backward(const float *d_params, const float *d_x, int64_t n_rows, const 
                  void *stream);
 int mlp_adam_step(float *d_params, const float *d_grad, float *d_m, float *d_v, int t, float lr,
                   float beta1, float beta2, float eps, void *stream);
+
 
 /* Message of the last failed call on this thread ("" if none). */
 const char *sem_last_error(void);

@@ -230,17 +230,28 @@ class Mesh:
                     *[a.ctypes.data_as(native.c_dp) for a in arrs])
         self.terrain = z.copy()
 
-    def node_heights(self):
-        """Physical height of every unique node in state order (flat heights
-        when no terrain is set)."""
-        xyz = self.node_xyz()
-        if self.terrain is None:
-            return xyz[:, 2]
-        _, _, zf = self.coords()
-        ze = np.asarray(self.params["z_edges"], dtype=np.float64)
-        z0, top = float(ze[0]), float(ze[-1])
-        zs = np.repeat(self.terrain, zf.size)
-        return xyz[:, 2] + zs * (top - xyz[:, 2]) / (top - z0)
+    def heights(self, zs=None):
+        """Physical height of every unique node in state order, from the
+        library (sem_mesh_heights): under the surface ``zs`` per unique
+        horizontal node if given, else under the mesh's terrain (flat heights
+        when none is set)."""
+        out = np.zeros(self.n_dof)
+        z = None
+        if zs is not None:
+            z = np.ascontiguousarray(np.asarray(zs, dtype=np.float64))
+            if z.size != self.info["n_h"]:
+                raise ValueError("zs needs one value per unique horizontal node")
+        native.call("sem_mesh_heights", self.handle,
+                    None if z is None else z.ctypes.data_as(native.c_dp),
+                    out.ctypes.data_as(native.c_dp))
+        return out
+
+    def epoch(self):
+        """Set-up epoch (sem_mesh_get_epoch): changes whenever a captured HIP
+        graph of this mesh's compute calls would go stale."""
+        e = ctypes.c_int64()
+        native.call("sem_mesh_get_epoch", self.handle, ctypes.byref(e))
+        return e.value
 
     def state(self, device="cuda"):
         """A zeroed state tensor (padding stays zero under every compute call)."""

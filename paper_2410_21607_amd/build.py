@@ -3,6 +3,7 @@
 import os
 import shutil
 import subprocess
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
@@ -26,10 +27,10 @@ def hipcc():
 
 
 def build(verbose=False):
-    """Compile every source and link libsem.so (always rebuilds)."""
+    """Compile every source (in parallel) and link libsem.so (always rebuilds)."""
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
-    objs = []
+    objs, cmds = [], []
     for src in SOURCES:
         path = os.path.join(CSRC, src)
         if not os.path.exists(path):
@@ -41,8 +42,14 @@ def build(verbose=False):
                    "-c", path, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
-        subprocess.run(cmd, check=True)
+        cmds.append(cmd)
         objs.append(obj)
+    jobs = max(1, min(len(cmds), len(os.sched_getaffinity(0)), 8))
+    with ThreadPoolExecutor(max_workers=jobs) as ex:
+        for r in ex.map(lambda c: subprocess.run(c, capture_output=True, text=True), cmds):
+            if r.stdout or r.stderr:
+                print(r.stdout + r.stderr, end="", flush=True)
+            r.check_returncode()
     tmp = LIB + ".tmp"
     cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC"] + objs + ["-o", tmp]
     if verbose:

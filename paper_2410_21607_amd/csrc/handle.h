@@ -45,7 +45,11 @@ struct sem_mesh {
     double* terrain_buf = nullptr; // zs, normals, per-node reference, tfac (sem_mesh_set_terrain)
     int64_t terrain_bytes = 0;
     const double* d_hxy = nullptr; // x, y of every unique horizontal node
+    std::vector<double> zs_host;   // terrain heights per unique horizontal node (empty = flat)
     int64_t ws_bytes = 0;
+    // bumped by every call that changes what a captured kernel node reads
+    // (tables freed or moved, settings passed by value)
+    int64_t epoch = 0;
     ~sem_mesh() {
         sem::fused_plan_free(fused);
         if (feat_aux) (void)hipFree(feat_aux);

@@ -813,6 +813,7 @@ int sem_mesh_set_reference(sem_mesh* M, const double* rho0, const double* theta0
         }
     }
     M->have_ref = true;
+    ++M->epoch;
     return SEM_OK;
 }
 
@@ -824,6 +825,8 @@ int sem_mesh_set_terrain(sem_mesh* M, const double* zs, const double* rho0, cons
     HIPCHK(hipDeviceSynchronize());
     if (!zs) {
         d.zs = d.nrm = d.minv_ht = d.ref_n = d.tfac = nullptr;
+        M->zs_host.clear();
+        ++M->epoch;
         return SEM_OK;
     }
     if (!rho0 || !theta0 || !dth0) return fail(SEM_ERR_ARG, "null reference array");
@@ -945,6 +948,25 @@ int sem_mesh_set_terrain(sem_mesh* M, const double* zs, const double* rho0, cons
     d.inv_depth = 1.0 / depth;
     d.z_top = top;
     d.depth = depth;
+    M->zs_host.assign(zs, zs + nh);
+    ++M->epoch;
+    return SEM_OK;
+}
+
+int sem_mesh_heights(const sem_mesh* M, const double* zs, double* z) {
+    if (!M || !z) return fail(SEM_ERR_ARG, "null argument");
+    const sem::HostMesh& H = M->host;
+    const double z0 = H.z_edges.front(), top = H.z_edges.back(), depth = top - z0;
+    const double* s = zs ? zs : (M->zs_host.empty() ? nullptr : M->zs_host.data());
+    if (zs)
+        for (int64_t h = 0; h < H.n_h; ++h)
+            if (!(zs[h] >= 0.0) || !(zs[h] < depth))
+                return fail(SEM_ERR_ARG, "terrain heights must lie in [0, H - z0)");
+    for (int64_t h = 0; h < H.n_h; ++h)
+        for (int k = 0; k < H.nzn; ++k) {
+            const double zf = H.zn[k];
+            z[h * H.nzn + k] = s ? zf + s[h] * (top - zf) / depth : zf;
+        }
     return SEM_OK;
 }
 
@@ -1027,6 +1049,7 @@ int sem_mesh_set_dissipation(sem_mesh* M, double cs, double sponge_gamma, double
         d.cs = 0.0;
         d.sponge = nullptr;
         d.rx = nullptr;
+        ++M->epoch;
         return SEM_OK;
     }
     const int64_t nloc = int64_t(H.n_col) * H.n_z * H.np1 * H.np1 * H.np1;
@@ -1058,6 +1081,7 @@ int sem_mesh_set_dissipation(sem_mesh* M, double cs, double sponge_gamma, double
     d.sp_gamma = sponge_gamma;
     d.sp_depth = sponge_depth;
     d.rx = M->diss_r;
+    ++M->epoch;
     return SEM_OK;
 }
 
@@ -1072,6 +1096,13 @@ int sem_stage_tune(sem_mesh* M, int layers_per_chunk) {
     HIPCHK(hipDeviceSynchronize());
     sem::fused_plan_free(M->fused);
     M->fused = P;
+    ++M->epoch;
+    return SEM_OK;
+}
+
+int sem_mesh_get_epoch(const sem_mesh* M, int64_t* epoch) {
+    if (!M || !epoch) return fail(SEM_ERR_ARG, "null argument");
+    *epoch = M->epoch;
     return SEM_OK;
 }
 

@@ -52,6 +52,8 @@ SIGNATURES = {
     "sem_mesh_set_reference": (c_int, [c_void_p, c_dp, c_dp, c_dp]),
     "sem_mesh_set_dissipation": (c_int, [c_void_p, c_double, c_double, c_double]),
     "sem_mesh_set_terrain": (c_int, [c_void_p, c_dp, c_dp, c_dp, c_dp]),
+    "sem_mesh_heights": (c_int, [c_void_p, c_dp, c_dp]),
+    "sem_mesh_get_epoch": (c_int, [c_void_p, ctypes.POINTER(ctypes.c_int64)]),
     "sem_nc_project": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p]),
     "sem_rhs": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_void_p]),
     "sem_dss": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),

@@ -9,7 +9,10 @@ One time step is three calls of ``sem_stage``:
 
 With ``graph=True`` the three launches (and every kernel inside them) are
 captured once per buffer parity into HIP graphs and replayed; two graphs
-alternate the roles of the two state buffers, so no copy is needed.
+alternate the roles of the two state buffers, so no copy is needed.  The
+graphs remember the mesh's set-up epoch at capture; a replay after any call
+that changed the mesh's tables or settings (re-tuning, terrain, dissipation)
+captures them again first, so a stale graph is never replayed.
 """
 
 import torch
@@ -42,6 +45,8 @@ class Stepper:
         self.cur = 0
         self.steps = 0
         self.graphs = None
+        self.captures = 0
+        self.epoch = None
         if graph:
             self._capture()
 
@@ -60,14 +65,17 @@ class Stepper:
 
     def _capture(self):
         # warm the kernels up on a side stream, then capture both parities
+        self.graphs = None
+        self.epoch = self.mesh.epoch()
         s = torch.cuda.Stream()
         s.wait_stream(torch.cuda.current_stream())
-        save = self.buf[0].clone()
+        save = [b.clone() for b in self.buf]
         with torch.cuda.stream(s):
             self._step_eager(self.buf[0], self.buf[1], s)
         torch.cuda.current_stream().wait_stream(s)
         torch.cuda.synchronize()
-        self.buf[0].copy_(save)
+        for b, v in zip(self.buf, save):
+            b.copy_(v)
         self.graphs = []
         for parity in (0, 1):
             g = torch.cuda.CUDAGraph()
@@ -76,11 +84,14 @@ class Stepper:
                                  torch.cuda.current_stream())
             self.graphs.append(g)
         torch.cuda.synchronize()
+        self.captures += 1
 
     def step(self, n=1):
         """Advance n full RK3 steps (3 stages each)."""
         for _ in range(n):
             if self.graphs is not None:
+                if self.mesh.epoch() != self.epoch:
+                    self._capture()
                 self.graphs[self.cur].replay()
             else:
                 self._step_eager(self.buf[self.cur], self.buf[1 - self.cur])

@@ -36,17 +36,20 @@ def run_case(name, n_stages, precision=0, graph=True):
     scratch = torch.zeros_like(q_g)
     lpc, ms = api.sem_stage_autotune(gm, q_g, q_g.clone(), scratch, precision, reps=3)
     say("  autotuned layers_per_chunk", lpc, "ms/stage", ms)
-    if n_stages % 3 == 0:
+    # whole RK3 steps as HIP-graph replays (the benchmark's configuration),
+    # then the remaining stages of a partial step one call at a time
+    qn = q_g
+    if n_stages >= 3:
         st = Stepper(gm, q_g, c["dt"], precision, graph=graph)
         st.step(n_stages // 3)
-        out = st.q
-    else:
-        qs, out = q_g.clone(), torch.zeros_like(q_g)
-        for s in range(n_stages):
-            a, b, cc = timestep.stage_coefficients(s % 3, c["dt"])
-            api.sem_stage(gm, a, b, cc, q_g, qs, out, precision)
-            qs, out = out, qs
-        out = qs
+        qn = st.q.clone()
+        del st
+    qs, out = qn.clone(), torch.zeros_like(q_g)
+    for s in range(n_stages % 3):
+        a, b, cc = timestep.stage_coefficients(s, c["dt"])
+        api.sem_stage(gm, a, b, cc, qn, qs, out, precision)
+        qs, out = out, qs
+    out = qs
     torch.cuda.synchronize()
     ref = oracle_reference_local(c, om)
     want, _ = timestep.run_stages(lambda q: assembly.rhs(om, q, ref, c["phys"]), q_or, c["dt"],
@@ -72,13 +75,15 @@ def test_bench_workload_fp32():
     assert err.max() <= 1e-6 and dv <= 1e-6
 
 
+# the two-level AMR workloads at ten stages (three graph-replayed RK3 steps
+# and the first stage of a fourth)
 @pytest.mark.timeout(900)
 def test_two_level_amr_n4():
-    err, dv = run_case("amr2_64x64x8_n4", 3)
-    assert err.max() <= 1e-12
+    err, dv = run_case("amr2_64x64x8_n4", 10)
+    assert err.max() <= 1e-12 and dv <= 1e-12
 
 
-@pytest.mark.timeout(1200)
+@pytest.mark.timeout(1500)
 def test_two_level_amr_n7():
-    err, dv = run_case("amr2_64x64x8_n7", 1, graph=False)
-    assert err.max() <= 1e-12
+    err, dv = run_case("amr2_64x64x8_n7", 10)
+    assert err.max() <= 1e-12 and dv <= 1e-12

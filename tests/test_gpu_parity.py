@@ -180,18 +180,74 @@ def test_stages_match_oracle(name, kw):
     assert err.max() <= TOL64
 
 
-def test_stage_update_elementwise():
+@pytest.mark.parametrize("alias", ["none", "qout=qs", "qout=qn", "qout=r"])
+def test_stage_update_matches_oracle(alias):
+    """sem_stage_update against oracle.timestep.stage_update on the same
+    seeded arrays, every entry including the row padding, for each of the
+    three SSP-RK3 stages; the call allows its output to alias any input."""
     S = get(*CASES[0])
     torch, api = S.torch, S.api
-    say("stage_update")
+    say("stage_update", alias)
     n = S.gm.n_state
-    g = torch.Generator(device="cuda").manual_seed(5)
-    qn, qs, r = (torch.rand(n, dtype=torch.float64, device="cuda", generator=g) for _ in range(3))
-    out = torch.zeros_like(qn)
-    api.sem_stage_update(S.gm, 0.75, 0.25, 0.1, qn, qs, r, out)
+    rng = np.random.default_rng(11)
+    for st in range(3):
+        a, b, cc = timestep.stage_coefficients(st, S.c["dt"])
+        qn, qs, r = (rng.standard_normal(n) for _ in range(3))
+        want = timestep.stage_update(a, b, cc, qn, qs, r)
+        dqn, dqs, dr = (torch.from_numpy(v.copy()).cuda() for v in (qn, qs, r))
+        out = {"none": torch.zeros_like(dqn), "qout=qs": dqs, "qout=qn": dqn, "qout=r": dr}[alias]
+        api.sem_stage_update(S.gm, a, b, cc, dqn, dqs, dr, out)
+        torch.cuda.synchronize()
+        got = out.cpu().numpy()
+        # one fused multiply-add chain against numpy's separate roundings
+        np.testing.assert_allclose(got, want, rtol=4e-16, atol=4e-16 * np.abs(want).max())
+
+
+def _unfused_stage(S, a, b, cc, qn, qs):
+    """q_out by the per-step calls: scatter, element right-hand side,
+    assemble, gather, finalize, stage update."""
+    torch, api = S.torch, S.api
+    n, nh, nl = S.gm.n_state, S.gm.n_hstate, 5 * S.gm.n_local
+    z = lambda k: torch.zeros(k, dtype=torch.float64, device="cuda")
+    hv, rE, acc, cH, r, out = z(nh), z(nl), z(n), z(nh), z(n), z(n)
+    if nh:
+        api.sem_nc_project(S.gm, api.SEM_SCATTER, qs, hv)
+    api.sem_rhs(S.gm, qs, hv if nh else None, rE, api.SEM_FP64)
+    api.sem_dss(S.gm, api.SEM_ASSEMBLE, rE=rE, acc=acc, c=cH if nh else None)
+    if nh:
+        api.sem_nc_project(S.gm, api.SEM_GATHER, cH, acc)
+    api.sem_dss(S.gm, api.SEM_FINALIZE, acc=acc, r=r)
+    api.sem_stage_update(S.gm, a, b, cc, qn, qs, r, out)
     torch.cuda.synchronize()
-    want = 0.75 * qn.cpu().numpy() + 0.25 * qs.cpu().numpy() + 0.1 * r.cpu().numpy()
-    np.testing.assert_allclose(out.cpu().numpy(), want, rtol=1e-15, atol=1e-15)
+    return out
+
+
+@pytest.mark.parametrize("name,kw", CASES, ids=IDS)
+def test_fused_stage_equals_unfused_composition(name, kw):
+    """sem_stage against the composition of the per-step calls on the same
+    input: the stage output of each of the three SSP-RK3 stages within 1e-14
+    relative (floor-scaled), and the bare right-hand side ((a, b, c) =
+    (0, 0, 1)) within 1e-13, the two paths summing the same contributions in
+    different orders."""
+    S = get(name, kw)
+    torch, api = S.torch, S.api
+    say("fused vs unfused", name, kw)
+    dt = S.c["dt"]
+    rng = np.random.default_rng(3)
+    qn_h = S.gm.pack(S.q_g)
+    # q_s: the workload's state with a relative perturbation of every field,
+    # so that q^n and q_s differ and a, b and c all matter
+    qs_h = qn_h * (1.0 + 1e-3 * rng.standard_normal(qn_h.shape))
+    qn, qs = S.gm.unpack(qn_h), S.gm.unpack(qs_h)
+    for st, (a, b, cc) in enumerate([timestep.stage_coefficients(k, dt) for k in range(3)]
+                                    + [(0.0, 0.0, 1.0)]):
+        fused = torch.zeros_like(qn)
+        api.sem_stage(S.gm, a, b, cc, qn, qs, fused, api.SEM_FP64)
+        unf = _unfused_stage(S, a, b, cc, qn, qs)
+        floors = metrics.STATE_FLOORS if st < 3 else metrics.RHS_FLOORS
+        err = metrics.rel_l2(S.gm.pack(fused), S.gm.pack(unf), floors)
+        say("  stage" if st < 3 else "  rhs", st, "rel", err)
+        assert err.max() <= (1e-14 if st < 3 else 1e-13)
 
 
 @pytest.mark.parametrize("name,kw", [CASES[0], CASES[2], CASES[4], CASES[5]],

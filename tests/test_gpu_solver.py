@@ -124,3 +124,39 @@ def test_hydrostatic_rest_stays_at_rest(precision):
     q = gm.pack(st.q)
     assert np.all(np.isfinite(q))
     assert np.abs(q[1:4]).max() <= 1e-10
+
+
+def test_graph_recaptured_after_mesh_changes():
+    """A captured RK3 step holds the fused tables of its capture.  Re-tuning
+    (which frees and rebuilds them), or switching the dissipation on and off,
+    bumps the mesh's set-up epoch; the stepper must capture again before its
+    next replay, and the replays must still match eager steps bit for bit."""
+    import torch
+    from paper_2410_21607_amd import api
+    from paper_2410_21607_amd.solver import Stepper
+    c, gm, om, perm, q_or, q_g = setup("small_amr2")
+    say("graph epoch")
+    eager = Stepper(gm, q_g, c["dt"])
+    graph = Stepper(gm, q_g, c["dt"], graph=True)
+    assert graph.captures == 1
+    e0 = gm.epoch()
+    graph.step()
+    eager.step()
+    torch.cuda.synchronize()
+    assert torch.equal(graph.q, eager.q)
+    for k, change in enumerate((lambda: api.sem_stage_tune(gm, 1), lambda: api.sem_stage_tune(gm, 2),
+                                lambda: gm.set_dissipation(0.0, 0.0))):
+        change()
+        assert gm.epoch() > e0
+        e0 = gm.epoch()
+        graph.step()
+        eager.step()
+        torch.cuda.synchronize()
+        assert graph.captures == 2 + k, "stale graph replayed"
+        assert torch.equal(graph.q, eager.q), f"replay after change {k} differs"
+    # no change, no capture
+    graph.step()
+    eager.step()
+    torch.cuda.synchronize()
+    assert graph.captures == 4 and torch.equal(graph.q, eager.q)
+    api.sem_stage_tune(gm, 0)

@@ -71,8 +71,10 @@ class Setup:
         assert np.all(zs_nodes == zs_nodes[:, :1])      # constant along every column
         self.gm.set_terrain(zs_nodes[:, 0], *(self.ref[k][self.perm]
                                              for k in ("rho0", "theta0", "dtheta0dz")))
-        # the binding's physical heights agree with the oracle's
-        np.testing.assert_allclose(self.gm.node_heights(), zp[self.perm], rtol=0, atol=1e-9)
+        # the library's physical heights agree with the oracle's, both under
+        # the surface passed in and under the one now set on the handle
+        np.testing.assert_allclose(self.gm.heights(), zp[self.perm], rtol=0, atol=1e-9)
+        np.testing.assert_allclose(self.gm.heights(zs_nodes[:, 0]), zp[self.perm], rtol=0, atol=1e-9)
         self.q_g = self.gm.unpack(self.q_or[:, self.perm])
 
     def to_oracle_order(self, flat):
@@ -418,14 +420,11 @@ def test_terrain_dissipation_matches_oracle(name, kw, shape, periodic):
 def _mountain_hook(case, amp=1000.0, half_width=40e3):
     """Terrain hook of an adaptive run: a Gaussian mountain, reference state
     per node at the nodes' physical heights."""
-    ze = np.asarray(case["z_edges"], dtype=np.float64)
 
     def hook(mesh):
         hxy, _, zf = mesh.coords()
         zs = amp * np.exp(-(hxy[:, 0] ** 2 + hxy[:, 1] ** 2) / half_width ** 2)
-        zp = np.tile(zf, zs.size)
-        zp = zp + np.repeat(zs, zf.size) * (ze[-1] - zp) / (ze[-1] - ze[0])
-        bg = cases.reference_state(case, zp)
+        bg = cases.reference_state(case, mesh.heights(zs))
         return zs, bg["rho0"], bg["theta0"], bg["dtheta0dz"]
     return hook
 
@@ -455,7 +454,7 @@ def test_adaptive_run_over_terrain_matches_uniform_finest():
         mesh.set_reference(*ref)
         mesh.set_terrain(*hook(mesh))
         xyz = mesh.node_xyz()
-        xyz[:, 2] = mesh.node_heights()
+        xyz[:, 2] = mesh.heights()
         q0 = mesh.unpack(cases.initial_state(cc, xyz))
         r = AdaptiveRun(mesh, q0, cc["dt"], ref, a["criterion"], a["thresholds"], a["lvl_max"],
                         a["interval"], adapt=adapt, terrain=hook)
