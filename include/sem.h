@@ -88,6 +88,7 @@ extern "C" {
 #define SEM_MLP_OUT 3
 #define SEM_MLP_NPARAM 5443 /* 64*16 + 64 + 64*64 + 64 + 3*64 + 3          */
 #define SEM_MLP_WORK 260  /* mlp_backward workspace floats per sample        */
+#define SEM_MLP_NOALLOC_MAX 2048 /* largest batch of mlp_backward_noalloc     */
 
 #define SEM_CRIT_SPEED 0  /* amr_flag criteria: |u| at every node           */
 #define SEM_CRIT_VORTZ 1  /* vertical vorticity dv/dx - du/dy (element-local)*/
@@ -430,6 +431,20 @@ int mlp_backward(const float *d_params, const float *d_x, int64_t n_rows, const 
 int mlp_adam_step(float *d_params, const float *d_grad, float *d_m, float *d_v, int t, float lr,
                   float beta1, float beta2, float eps, void *stream);
 
+/* mlp_backward without a caller workspace, for callers that cannot allocate
+ * device memory (code under HIP graph capture, training loops that must not
+ * call hipMalloc).  Same arguments, kernels and results as mlp_backward
+ * minus d_work: the per-sample workspace is a file-scope device array of
+ * SEM_MLP_NOALLOC_MAX * SEM_MLP_WORK floats (about 2.1 MB per GPU, held until
+ * the process ends), whose device address is looked up once per GPU on its
+ * first call.  The call itself allocates nothing.  Errors: SEM_ERR_ARG also
+ * for n > SEM_MLP_NOALLOC_MAX.  Every call on one GPU uses that GPU's single
+ * array, so calls that overlap on one GPU (other streams, other threads)
+ * race: order them on one stream.  No state carries over between calls
+ * (each call writes every workspace entry it reads). */
+int mlp_backward_noalloc(const float *d_params, const float *d_x, int64_t n_rows,
+                         const int8_t *d_class, const int32_t *d_idx, int64_t n,
+                         float *d_grad, float *d_loss, void *stream);
 
 /* Message of the last failed call on this thread ("" if none). */
 const char *sem_last_error(void);

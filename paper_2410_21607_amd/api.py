@@ -475,6 +475,19 @@ def mlp_backward(params, x, cls, idx, work, grad, loss, stream=None):
                 _stream(stream))
 
 
+def mlp_backward_noalloc(params, x, cls, idx, grad, loss, stream=None):
+    """mlp_backward with the library's own per-GPU workspace (no caller
+    allocation); at most SEM_MLP_NOALLOC_MAX samples per call."""
+    rows = x.shape[0]
+    n = rows if idx is None else idx.numel()
+    native.call("mlp_backward_noalloc", _ptr(params, torch.float32, MLP_NPARAM, "params"),
+                _ptr(x, torch.float32, rows * 16, "x"), int(rows),
+                _ptr(cls, torch.int8, rows, "cls"),
+                None if idx is None else _ptr(idx, torch.int32, n, "idx"), int(n),
+                _ptr(grad, torch.float32, MLP_NPARAM, "grad"), _ptr(loss, torch.float32, 1, "loss"),
+                _stream(stream))
+
+
 def mlp_adam_step(params, grad, m, v, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
     native.call("mlp_adam_step", _ptr(params, torch.float32, MLP_NPARAM, "params"),
                 _ptr(grad, torch.float32, MLP_NPARAM, "grad"), _ptr(m, torch.float32, MLP_NPARAM, "m"),

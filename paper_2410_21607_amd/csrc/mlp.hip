@@ -13,6 +13,7 @@
 //                   fixed order (deterministic, accumulated in double);
 //   k_adam        : element-wise Adam update.
 #include <cmath>
+#include <mutex>
 
 #include "handle.h"
 
@@ -192,10 +193,36 @@ __global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float
     p[r] -= lr * (mr / c1) / (sqrtf(vr / c2) + eps);
 }
 
+// Workspace of mlp_backward_noalloc: one array per GPU, held until the
+// process ends, shared by every call on that GPU (see sem.h).
+static __device__ __align__(256) float scratch[size_t(SEM_MLP_NOALLOC_MAX) * SEM_MLP_WORK];
+
 }  // namespace sem
 
 namespace {
 using sem::fail;
+
+// device address of `scratch` on each GPU, looked up once per device with
+// that device current (the host-side name is not a device address)
+constexpr int kMaxDevices = 64;
+float* g_scratch_ptr[kMaxDevices] = {};
+std::mutex g_scratch_mu;
+
+int scratch_for_current_device(float** out) {
+    int dev = -1;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(SEM_ERR_HIP, "device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(sem::scratch)));
+        if (!p) return fail(SEM_ERR_HIP, "no device address for the workspace array");
+        g_scratch_ptr[dev] = static_cast<float*>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return SEM_OK;
+}
+
 int grid_of(int64_t n) {
     int64_t g = (n + 255) / 256;
     if (g < 1) g = 1;
@@ -221,6 +248,30 @@ int mlp_backward(const float* p, const float* x, int64_t n_rows, const int8_t* c
     if (!p || !x || !cls || !work || !grad || !loss) return fail(SEM_ERR_ARG, "null array");
     if (n < 1) return fail(SEM_ERR_ARG, "empty batch");
     if (n_rows < 1 || (!idx && n > n_rows)) return fail(SEM_ERR_ARG, "batch larger than the data");
+    hipStream_t s = (hipStream_t)stream;
+    hipLaunchKernelGGL(sem::k_mlp_samples, dim3(grid_of(n)), dim3(256), 0, s, p, x, cls, idx, n,
+                       n_rows, work);
+    HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL(sem::k_mlp_grad, dim3((SEM_MLP_NPARAM + 1 + sem::GRAD_SLOTS - 1) / sem::GRAD_SLOTS),
+                       dim3(sem::GRAD_SLOTS * sem::GRAD_SEGS), 0, s, x, idx, n, n_rows, work, grad, loss);
+    HIPCHK(hipGetLastError());
+    return SEM_OK;
+}
+
+int mlp_backward_noalloc(const float* p, const float* x, int64_t n_rows, const int8_t* cls,
+                         const int32_t* idx, int64_t n, float* grad, float* loss, void* stream) {
+    if (!p || !x || !cls || !grad || !loss) return fail(SEM_ERR_ARG, "null array");
+    if (n < 1) return fail(SEM_ERR_ARG, "empty batch");
+    if (n > SEM_MLP_NOALLOC_MAX)
+        return fail(SEM_ERR_ARG, "batch larger than SEM_MLP_NOALLOC_MAX samples (use mlp_backward "
+                                 "with a caller workspace)");
+    if (n_rows < 1 || (!idx && n > n_rows)) return fail(SEM_ERR_ARG, "batch larger than the data");
+    float* work = nullptr;
+    int rc = scratch_for_current_device(&work);
+    if (rc != SEM_OK) return rc;
+    // the same two kernels as mlp_backward; k_mlp_samples writes every
+    // workspace entry that k_mlp_grad reads (the first n samples), so nothing
+    // left by an earlier call is read and no clearing is needed
     hipStream_t s = (hipStream_t)stream;
     hipLaunchKernelGGL(sem::k_mlp_samples, dim3(grid_of(n)), dim3(256), 0, s, p, x, cls, idx, n,
                        n_rows, work);

@@ -84,6 +84,8 @@ SIGNATURES = {
     "mlp_forward": (c_int, [c_void_p, c_void_p, ctypes.c_int64, c_void_p, c_void_p]),
     "mlp_backward": (c_int, [c_void_p, c_void_p, ctypes.c_int64, c_void_p, c_void_p,
                              ctypes.c_int64, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "mlp_backward_noalloc": (c_int, [c_void_p, c_void_p, ctypes.c_int64, c_void_p, c_void_p,
+                                     ctypes.c_int64, c_void_p, c_void_p, c_void_p]),
     "mlp_adam_step": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int, ctypes.c_float,
                               ctypes.c_float, ctypes.c_float, ctypes.c_float, c_void_p]),
     "sem_last_error": (ctypes.c_char_p, []),
@@ -92,6 +94,7 @@ SIGNATURES = {
 SEM_NFEAT = 16
 SEM_MLP_NPARAM = 5443
 SEM_MLP_WORK = 260
+SEM_MLP_NOALLOC_MAX = 2048
 
 _LIB = None
 
