@@ -84,9 +84,10 @@ def test_transfer_kernel_matches_oracle(seed, N, periodic):
     assert err <= 1e-13 * np.max(np.abs(want))
 
 
-def _oracle_adaptive(c, q, lvl_max, thr, interval, n_steps):
+def _oracle_adaptive(c, q, lvl_max, thr, interval, n_steps, criterion=1):
     """The same adaptive sequence on the oracle: RK3 steps, then every
-    `interval` steps vorticity flags -> new layout -> transfer."""
+    `interval` steps criterion flags (1: vertical vorticity, 0: wind speed)
+    -> new layout -> transfer."""
     cols = np.asarray(c["columns"])
     om = oracle_mesh(c)
     steps = 0
@@ -97,7 +98,7 @@ def _oracle_adaptive(c, q, lvl_max, thr, interval, n_steps):
                                    3 * interval)
         steps += interval
         qL = assembly.scatter(om, q)
-        C = amr.criterion_vorticity(om, qL)
+        C = amr.criterion_vorticity(om, qL) if criterion == 1 else amr.criterion_speed(qL)
         ef = amr.element_flags(C.reshape(om.n_elem, -1), om.e_level, thr, lvl_max)
         cf = amr.column_flags(ef, om.columns, om.n_z)
         new = adapt.adapt_columns(om.columns, cf, c["nx0"], c["ny0"], lvl_max,
@@ -139,6 +140,55 @@ def test_adaptive_run_matches_oracle():
             assert np.min(np.abs(cmax - t)) > 1e-9 * t
     say("  rebuilds", run.n_rebuild, "history", run.history)
     assert run.n_rebuild >= 1
+    got_cols = {tuple(int(t) for t in r) for r in run.mesh.columns}
+    assert got_cols == {tuple(int(t) for t in r) for r in om2.columns}
+    p2 = match(om2.node_xyz, run.mesh.node_xyz(), c2)
+    got = np.empty_like(want)
+    got[:, p2] = run.mesh.pack(run.q)
+    err = metrics.rel_l2(got, want, metrics.STATE_FLOORS)
+    say("  rel", err)
+    assert err.max() <= 1e-12
+
+
+def test_adaptive_run_speed_criterion_matches_oracle():
+    """The paper's criterion, the wind speed |u| at every node against one
+    threshold per level, driving the whole adaptive loop (flags -> layout ->
+    transfer -> stages) on a vortex moved by a steering wind, three levels:
+    the GPU run ends on the oracle's layout with the oracle's state."""
+    import torch
+    from paper_2410_21607_amd import api
+    from paper_2410_21607_amd.adaptive import AdaptiveRun
+    c = cases.get("small_amr2", N=4)
+    c["steer"] = (6.0, -4.0)
+    lvl_max, interval, n_steps = 3, 2, 6
+    say("adaptive run, speed criterion", c["name"])
+    gm = api.Mesh.from_case(c)
+    _, _, z = gm.coords()
+    bg = cases.reference_state(c, z)
+    ref = (bg["rho0"], bg["theta0"], bg["dtheta0dz"])
+    gm.set_reference(*ref)
+    om = oracle_mesh(c)
+    perm = match(om.node_xyz, gm.node_xyz(), c)
+    q_or = cases.initial_state(c, om.node_xyz)
+    # thresholds between the element maxima of |u| of the initial state,
+    # in wide gaps so that the drift of later boundaries cannot reach them
+    C0 = amr.criterion_speed(assembly.scatter(om, q_or)).reshape(om.n_elem, -1).max(axis=1)
+    v = np.sort(C0)
+    gaps = np.diff(v)
+    cand = np.argsort(gaps)[::-1][:8]
+    cuts = sorted(0.5 * (v[i] + v[i + 1]) for i in cand if v[i] > v[0] + 0.25 * (v[-1] - v[0]))
+    thr = [cuts[0], cuts[len(cuts) // 2], cuts[-1]]
+    run = AdaptiveRun(gm, gm.unpack(q_or[:, perm]), c["dt"], ref, api.SEM_CRIT_SPEED, thr,
+                      lvl_max, interval, graph=True)
+    run.run(n_steps)
+    torch.cuda.synchronize()
+    c2, om2, want, layouts = _oracle_adaptive(c, q_or, lvl_max, thr, interval, n_steps, criterion=0)
+    for _, cmax in layouts:
+        for t in thr:
+            assert np.min(np.abs(cmax - t)) > 1e-9 * t
+    say("  thresholds", thr, "rebuilds", run.n_rebuild, "history", run.history)
+    assert run.n_rebuild >= 1
+    assert max(int(r[0]) for r in run.mesh.columns) >= 2
     got_cols = {tuple(int(t) for t in r) for r in run.mesh.columns}
     assert got_cols == {tuple(int(t) for t in r) for r in om2.columns}
     p2 = match(om2.node_xyz, run.mesh.node_xyz(), c2)
