@@ -26,7 +26,9 @@
  *               with the row stride ldz = nzn rounded up to a multiple of 16
  *               (128 bytes), so that each vertical row starts on a cache line.
  *               Entries kz >= nzn are padding: compute calls never read them;
- *               only sem_stage_update (element-wise) writes them.
+ *               only sem_stage_update (element-wise) writes them.  Unique
+ *               horizontal nodes are numbered block by block (2 x 2 column
+ *               blocks, then the other columns, in column order).
  * Hanging     : a hanging point hh in [0, n_hh) is a horizontal position on a
  *               fine column's face that is not a node of the coarser neighbour
  *               (Section 3.1); hanging values are double hv[F][n_hh][ldz].
@@ -78,6 +80,9 @@ extern "C" {
 
 #define SEM_SCATTER 0     /* sem_nc_project: unique nodes -> hanging points  */
 #define SEM_GATHER  1     /* sem_nc_project: hanging points -> unique nodes  */
+
+#define SEM_LAYOUT_COLUMNS 0 /* sem_stage work layouts (sem_stage_set_layout) */
+#define SEM_LAYOUT_BLOCKS  1
 
 #define SEM_ASSEMBLE 0    /* sem_dss phases */
 #define SEM_FINALIZE 1
@@ -216,8 +221,8 @@ int sem_mesh_heights(const sem_mesh *mesh, const double *h_zs, double *h_z);
 
 /* Set-up epoch of a mesh handle: a counter that every call changing what a
  * captured HIP graph of compute calls would read (sem_stage_tune,
- * sem_stage_autotune, sem_mesh_set_reference, sem_mesh_set_terrain,
- * sem_mesh_set_dissipation) increments.  A graph captured at epoch e may be
+ * sem_stage_set_layout, sem_stage_autotune, sem_mesh_set_reference,
+ * sem_mesh_set_terrain, sem_mesh_set_dissipation) increments.  A graph captured at epoch e may be
  * replayed only while the epoch is still e; afterwards it can read freed
  * tables or stale settings, so capture it again. */
 int sem_mesh_get_epoch(const sem_mesh *mesh, int64_t *epoch);
@@ -257,10 +262,11 @@ int sem_stage_update(const sem_mesh *mesh, double a, double b, double c,
 
 /* Fused stage: d_qout = a*d_qn + b*d_qs + c*R(d_qs), with R the full
  * right-hand side (scatter, element RHS, assembly, gather, finalize, lid rule)
- * evaluated without storing element-local data.  Columns are coloured so that
- * columns of one colour share no node; one launch per colour covers the
- * columns of every refinement level of that colour (a workgroup marches up
- * one column in chunks of stacked elements).  The first colour touching a
+ * evaluated without storing element-local data.  Work units (columns, or
+ * 2 x 2 column blocks: sem_stage_set_layout) are coloured so that units of
+ * one colour share no node; the launches of one colour cover the units of
+ * every refinement level of that colour (a workgroup marches up one column
+ * or one block in chunks of stacked elements).  The first colour touching a
  * node writes a*q^n + b*q_s + c*M^-1*(its contribution); later colours add
  * their contributions (plain read-modify-write; the launches order them, so
  * results are deterministic and bit-identical from run to run).  Hanging
@@ -283,10 +289,31 @@ int sem_stage(const sem_mesh *mesh, double a, double b, double c,
 int sem_stage_tune(sem_mesh *mesh, int layers_per_chunk);
 int sem_stage_get_tune(const sem_mesh *mesh, int *layers_per_chunk);
 
-/* Autotuner: times every supported layers_per_chunk on this mesh (reps fused
- * stages each, HIP events on `stream`, d_qout used as scratch), keeps the
- * fastest with sem_stage_tune, and reports it (*best_lpc, *best_ms = mean
- * stage time in ms; either may be NULL).  Synchronises the stream. */
+/* Work layout of sem_stage (the LDS tile layout and workgroup packing):
+ *   SEM_LAYOUT_COLUMNS: a workgroup per column, chunks of `param` layers
+ *     (as sem_stage_tune; 0 = default);
+ *   SEM_LAYOUT_BLOCKS: a workgroup per 2 x 2 block of columns of one level
+ *     (a sibling family, or four level-0 columns), a (2N+1)^2 tile per layer,
+ *     the column in `param` vertical segments (0 = enough segments for about
+ *     1024 workgroups per launch); columns in no block run as in the column
+ *     layout.  Orders 3 to 5 on meshes with blocks (box elements: with
+ *     terrain set, sem_stage runs the column layout).
+ * The faces inside a block are summed in the workgroup; blocks are coloured
+ * like columns, so the results are deterministic in either layout (they
+ * differ between layouts by the order of the sums, within 1e-14).  Meshes
+ * start in the column layout.  Rebuilds the handle's tables and
+ * synchronises the device.  sem_stage_get_layout reports the layout and its
+ * parameter (layers per chunk, or the number of segments). */
+int sem_stage_set_layout(sem_mesh *mesh, int layout, int param);
+int sem_stage_get_layout(const sem_mesh *mesh, int *layout, int *param);
+
+/* Autotuner: times every supported work layout on this mesh (the column
+ * layout at each supported layers_per_chunk, the block layout at 1, 2, 4, ...
+ * vertical segments; reps fused stages each, HIP events on `stream`, d_qout
+ * used as scratch), keeps the fastest with sem_stage_set_layout, and reports
+ * it (*best_lpc = the column layout's layers per chunk, see
+ * sem_stage_get_layout for the layout; *best_ms = mean stage time in ms;
+ * either may be NULL).  Synchronises the stream. */
 int sem_stage_autotune(sem_mesh *mesh, const double *d_qn, const double *d_qs,
                        double *d_qout, int precision, int reps, int *best_lpc,
                        float *best_ms, void *stream);

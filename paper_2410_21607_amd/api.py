@@ -316,6 +316,21 @@ def sem_stage_get_tune(mesh):
     return a.value
 
 
+SEM_LAYOUT_COLUMNS, SEM_LAYOUT_BLOCKS = 0, 1
+
+
+def sem_stage_set_layout(mesh, layout, param=0):
+    native.call("sem_stage_set_layout", mesh.handle, int(layout), int(param))
+
+
+def sem_stage_get_layout(mesh):
+    """(layout, param): layers per chunk of the column layout, or the number
+    of vertical segments of the block layout."""
+    lay, par = ctypes.c_int(), ctypes.c_int()
+    native.call("sem_stage_get_layout", mesh.handle, ctypes.byref(lay), ctypes.byref(par))
+    return lay.value, par.value
+
+
 def sem_stage_autotune(mesh, qn, qs, qout, precision=SEM_FP64, reps=5, stream=None):
     """Pick the fastest chunk depth on this mesh; returns (layers_per_chunk, ms)."""
     n = mesh.n_state

@@ -15,6 +15,8 @@
 // with odd N where coarse edge midpoints are not nodes).
 #include "mesh_build.h"
 
+#include <array>
+
 #include <algorithm>
 #include <cmath>
 #include <map>
@@ -247,6 +249,9 @@ int build_host_mesh(const MeshInput& in, HostMesh& m, std::string& err) {
         if (!(in.z_edges[k + 1] > in.z_edges[k])) { err = "z_edges must increase"; return SEM_ERR_ARG; }
     const int N = in.N, np1 = N + 1, np2 = np1 * np1;
     m.N = N; m.np1 = np1; m.n_z = in.n_z; m.nzn = in.n_z * N + 1;
+    // rows padded to whole 128-byte lines: a chunk of a row then starts on a
+    // line boundary (packed rows, which save the line that holds little more
+    // than the top node, measured 12 % slower in the column kernel)
     m.ldz = (m.nzn + 15) / 16 * 16;
     m.nx0 = in.nx0; m.ny0 = in.ny0; m.periodic_x = in.periodic_x; m.periodic_y = in.periodic_y;
     m.Lx = in.Lx; m.Ly = in.Ly;
@@ -400,6 +405,27 @@ int build_host_mesh(const MeshInput& in, HostMesh& m, std::string& err) {
                 }
             }
     }
+    // ---- column blocks (2 x 2 squares of leaf columns of one level)
+    m.col_block.assign(size_t(in.n_col), -1);
+    for (int c = 0; c < in.n_col; ++c) {
+        if (m.col_block[c] >= 0) continue;
+        const int l = in.lev[c];
+        const int64_t bx = in.ix[c] & ~int64_t(1), by = in.iy[c] & ~int64_t(1);
+        if (bx + 1 >= (int64_t(in.nx0) << l) || by + 1 >= (int64_t(in.ny0) << l)) continue;
+        int32_t ids[4];
+        bool ok = true;
+        for (int q = 0; q < 4 && ok; ++q) {
+            const int32_t id = cmap.find(lkey(l, bx + (q & 1)), by + (q >> 1));
+            if (id < 0 || m.col_block[id] >= 0) ok = false;
+            else ids[q] = id;
+        }
+        if (!ok) continue;
+        const int32_t b = int32_t(m.blk_cols.size() / 4);
+        for (int q = 0; q < 4; ++q) {
+            m.blk_cols.push_back(ids[q]);
+            m.col_block[ids[q]] = b;
+        }
+    }
     // ---- number unique nodes (first touch) and hanging points
     // keys of lattice positions are >= 0; interior LGL keys carry GLL_TAG (also >= 0)
     // Positions strictly inside a column belong to that column alone (never
@@ -411,9 +437,31 @@ int build_host_mesh(const MeshInput& in, HostMesh& m, std::string& err) {
     int32_t n_unique = 0;
     m.gmap.assign(size_t(in.n_col) * np2, 0);
     std::vector<size_t> hh_first;   // (c, pos) slot that defined each hanging point
-    for (int c = 0; c < in.n_col; ++c)
-        for (int j = 0; j < np1; ++j)
-            for (int i = 0; i < np1; ++i) {
+    // visiting order: units (a block, or a column in no block) by their
+    // lowest column id; a block's positions in row order over its
+    // (2N+1) x (2N+1) grid, every column slot at a position in turn
+    std::vector<std::array<int32_t, 3>> visit;   // (column, i, j)
+    visit.reserve(size_t(in.n_col) * np2);
+    for (int c = 0; c < in.n_col; ++c) {
+        const int32_t b = m.col_block[c];
+        if (b < 0) {
+            for (int j = 0; j < np1; ++j)
+                for (int i = 0; i < np1; ++i) visit.push_back({c, i, j});
+            continue;
+        }
+        const int32_t* bc = &m.blk_cols[size_t(b) * 4];
+        if (c != *std::min_element(bc, bc + 4)) continue;
+        for (int J = 0; J <= 2 * N; ++J)
+            for (int I = 0; I <= 2 * N; ++I)
+                for (int q = 0; q < 4; ++q) {
+                    const int qx = q & 1, qy = q >> 1;
+                    const int i = I - qx * N, j = J - qy * N;
+                    if (i < 0 || i > N || j < 0 || j > N) continue;
+                    visit.push_back({bc[q], i, j});
+                }
+    }
+    for (const auto& vt : visit) {
+                const int c = vt[0], i = vt[1], j = vt[2];
                 size_t s = size_t(c) * np2 + i + np1 * j;
                 Key2 k{kx_of(c, i), ky_of(c, j)};
                 double x = m.col_x0[c] + 0.5 * (1.0 + B.x[i]) * m.col_dx[c];

@@ -60,6 +60,14 @@ struct HostMesh {
     // horizontal neighbours: columns sharing at least one unique horizontal
     // node (across faces or corners), CSR over columns, ascending ids
     std::vector<int32_t> nbr_ptr, nbr_col;
+    // column blocks: every 2 x 2 square of leaf columns of one level whose
+    // lower-left member has even indices (a sibling family, or four level-0
+    // columns) forms a block; blk_cols holds its four columns, member
+    // q = qx + 2 qy at (2 bx + qx, 2 by + qy).  col_block[c] is the block of
+    // column c, or -1 for a column in no block.  Unique horizontal nodes are
+    // numbered block by block (positions in row order), so that the rows a
+    // block touches first are consecutive in memory.
+    std::vector<int32_t> blk_cols, col_block;
 };
 
 struct MeshInput {

@@ -728,7 +728,7 @@ int sem_mesh_create(const sem_mesh_desc* desc, sem_mesh** out) {
     HIPCHK(hipMalloc(&M->wind_part, sizeof(double) * 256));
     HIPCHK(hipMalloc(&M->feat_aux, sizeof(double) * 2 * size_t(std::max<int64_t>(1, int64_t(H.n_col) * H.n_z))));
     M->ws_bytes += int64_t(sizeof(double)) * 2 * int64_t(H.n_col) * H.n_z;
-    if ((rc = sem::fused_plan_build(H, 0, M->fused)) != SEM_OK)
+    if ((rc = sem::fused_plan_build(H, SEM_LAYOUT_COLUMNS, 0, M->fused)) != SEM_OK)
         return fail(rc, "could not build the fused-stage tables");
     *out = M.release();
     return SEM_OK;
@@ -1085,13 +1085,17 @@ int sem_mesh_set_dissipation(sem_mesh* M, double cs, double sponge_gamma, double
     return SEM_OK;
 }
 
-int sem_stage_tune(sem_mesh* M, int layers_per_chunk) {
+int sem_stage_set_layout(sem_mesh* M, int layout, int param) {
     if (!M) return fail(SEM_ERR_ARG, "null mesh");
-    if (layers_per_chunk < 0 ||
-        (layers_per_chunk > 0 && !sem::fused_lpc_supported(M->host.N, layers_per_chunk)))
+    if (layout != SEM_LAYOUT_COLUMNS && layout != SEM_LAYOUT_BLOCKS)
+        return fail(SEM_ERR_ARG, "unknown layout");
+    if (param < 0) return fail(SEM_ERR_ARG, "negative layout parameter");
+    if (layout == SEM_LAYOUT_COLUMNS && param > 0 && !sem::fused_lpc_supported(M->host.N, param))
         return fail(SEM_ERR_ARG, "unsupported layers_per_chunk for this order");
+    if (layout == SEM_LAYOUT_BLOCKS && !sem::fused_blocks_supported(M->host))
+        return fail(SEM_ERR_ARG, "no block layout for this mesh (order 3 to 5 with 2 x 2 column blocks)");
     sem::FusedPlan P;
-    int rc = sem::fused_plan_build(M->host, layers_per_chunk, P);
+    int rc = sem::fused_plan_build(M->host, layout, param, P);
     if (rc != SEM_OK) { sem::fused_plan_free(P); return fail(rc, "could not build the fused-stage tables"); }
     HIPCHK(hipDeviceSynchronize());
     sem::fused_plan_free(M->fused);
@@ -1100,10 +1104,19 @@ int sem_stage_tune(sem_mesh* M, int layers_per_chunk) {
     return SEM_OK;
 }
 
-int sem_mesh_get_epoch(const sem_mesh* M, int64_t* epoch) {
-    if (!M || !epoch) return fail(SEM_ERR_ARG, "null argument");
-    *epoch = M->epoch;
+int sem_stage_get_layout(const sem_mesh* M, int* layout, int* param) {
+    if (!M || !layout || !param) return fail(SEM_ERR_ARG, "null argument");
+    *layout = M->fused.layout;
+    *param = M->fused.layout == SEM_LAYOUT_BLOCKS ? M->fused.bt.n_seg : M->fused.t.layers_per_chunk;
     return SEM_OK;
+}
+
+int sem_stage_tune(sem_mesh* M, int layers_per_chunk) {
+    if (!M) return fail(SEM_ERR_ARG, "null mesh");
+    if (layers_per_chunk < 0 ||
+        (layers_per_chunk > 0 && !sem::fused_lpc_supported(M->host.N, layers_per_chunk)))
+        return fail(SEM_ERR_ARG, "unsupported layers_per_chunk for this order");
+    return sem_stage_set_layout(M, SEM_LAYOUT_COLUMNS, layers_per_chunk);
 }
 
 int sem_stage_autotune(sem_mesh* M, const double* qn, const double* qs, double* qout, int prec,
@@ -1118,12 +1131,29 @@ int sem_stage_autotune(sem_mesh* M, const double* qn, const double* qs, double* 
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
+    // candidates: single columns in chunks of 1, 2, 4, 8 layers; column
+    // blocks in 1, 2, 4, ... vertical segments (distinct segment lengths)
+    std::vector<std::pair<int, int>> cand;
+    for (int lpc = 1; lpc <= 16; lpc *= 2)
+        if (sem::fused_lpc_supported(M->host.N, lpc) && lpc <= 2 * M->host.n_z)
+            cand.push_back({SEM_LAYOUT_COLUMNS, lpc});
+    if (sem::fused_blocks_supported(M->host) && !M->d.zs) {
+        int last_ls = -1;
+        for (int S = 1; S <= M->host.n_z; S *= 2) {
+            const int ls = (M->host.n_z + S - 1) / S;
+            if (ls == last_ls) continue;
+            last_ls = ls;
+            cand.push_back({SEM_LAYOUT_BLOCKS, S});
+        }
+    }
     int best = -1;
     float best_t = 0.0f;
-    for (int lpc = 1; lpc <= 16; lpc *= 2) {
-        if (!sem::fused_lpc_supported(M->host.N, lpc) || lpc > 2 * M->host.n_z) continue;
+    for (size_t ci = 0; ci < cand.size(); ++ci) {
         sem::FusedPlan P;
-        if (sem::fused_plan_build(M->host, lpc, P) != SEM_OK) { sem::fused_plan_free(P); continue; }
+        if (sem::fused_plan_build(M->host, cand[ci].first, cand[ci].second, P) != SEM_OK) {
+            sem::fused_plan_free(P);
+            continue;
+        }
         // warm-up, then timed repetitions (the stage coefficients do not
         // change the work; qout is scratch here)
         rc = sem::fused_stage_launch(M->d, P, 0.5, 0.5, 1e-3, qn, qs, qout, prec, s);
@@ -1137,7 +1167,7 @@ int sem_stage_autotune(sem_mesh* M, const double* qn, const double* qs, double* 
         if (rc == SEM_OK && hipEventSynchronize(e1) == hipSuccess &&
             hipEventElapsedTime(&ms, e0, e1) == hipSuccess) {
             ms /= float(reps);
-            if (best < 0 || ms < best_t) { best = lpc; best_t = ms; }
+            if (best < 0 || ms < best_t) { best = int(ci); best_t = ms; }
         }
         (void)hipStreamSynchronize(s);
         sem::fused_plan_free(P);
@@ -1145,8 +1175,8 @@ int sem_stage_autotune(sem_mesh* M, const double* qn, const double* qs, double* 
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (best < 0) return fail(SEM_ERR_HIP, "autotuning found no working configuration");
-    if ((rc = sem_stage_tune(M, best)) != SEM_OK) return rc;
-    if (best_lpc) *best_lpc = best;
+    if ((rc = sem_stage_set_layout(M, cand[best].first, cand[best].second)) != SEM_OK) return rc;
+    if (best_lpc) *best_lpc = M->fused.t.layers_per_chunk;
     if (best_ms) *best_ms = best_t;
     return SEM_OK;
 }
@@ -1154,6 +1184,12 @@ int sem_stage_autotune(sem_mesh* M, const double* qn, const double* qs, double* 
 int sem_stage_get_tune(const sem_mesh* M, int* layers_per_chunk) {
     if (!M || !layers_per_chunk) return fail(SEM_ERR_ARG, "null argument");
     *layers_per_chunk = M->fused.t.layers_per_chunk;
+    return SEM_OK;
+}
+
+int sem_mesh_get_epoch(const sem_mesh* M, int64_t* epoch) {
+    if (!M || !epoch) return fail(SEM_ERR_ARG, "null argument");
+    *epoch = M->epoch;
     return SEM_OK;
 }
 

@@ -27,18 +27,73 @@ struct FusedTables {
     const uint8_t* first;       // per (column, position)
     double* cH;                 // hanging-point contributions [F][n_hh][nzn]
     int layers_per_chunk;       // layers handled together by one workgroup step
+    // Position map and interpolation rows the kernel reads (the mesh's own,
+    // extended when the plan has side columns).  Side columns (the columns
+    // of the small colour classes of an uneven mesh) run in the first
+    // colour's launch; every position of theirs maps to a pseudo hanging
+    // point past the mesh's n_hh, whose row is the unit row of its node (or a
+    // copy of its hanging row), so that the kernel stores the position's
+    // contribution in cH unchanged; the tail launch assembles them.
+    const int32_t* gmap;
+    const int32_t *hang_ptr, *hang_src;
+    const double* hang_w;
+    const int32_t* hreal;       // per (pseudo) hanging point: index into the
+                                // surface and reference rows ([0, n_h + n_hh))
+    int64_t fsh;                // field stride of cH: (hanging + pseudo points) * ldz
+};
+
+// Tail launch: the unique nodes that receive side-slot or hanging-point
+// contributions, each summing them in a fixed order and finishing the node.
+struct TailTables {
+    const int32_t* h;           // n: unique horizontal node
+    const uint8_t* first;       // n: no column launch writes the node first
+    const int32_t *sptr, *sslot;    // side slots of the node
+    const int32_t *hptr, *hh;       // hanging points it gathers (Z^T rows)
+    const double* hw;
+    const int32_t *hh_sptr, *hh_sslot;  // side slots of every hanging point
+    const uint8_t* hh_cvalid;   // n_hh: some column launch writes cH there
+    const double* cH;           // hanging and pseudo hanging points
+    int n;
+    int64_t fsh;                // field stride of cH
+};
+
+// Block layout: the work unit is a 2 x 2 block of columns of one level (a
+// sibling family, or four level-0 columns), split vertically into segments of
+// `Ls` layers.  Blocks are coloured so that blocks of one colour share no
+// node; a segment's planes are its own except the plane it shares with the
+// segment above or below, whose first writer is the even segment (launches
+// run colour by colour, even segments before odd ones).  Columns in no block
+// run through the column kernel in their colour's turn.
+struct BlockTables {
+    const int32_t* order;       // blocks sorted by colour
+    const int32_t* pos_g;       // n_blk * (2N+1)^2: unique node or -(hh+1) per block position
+    const uint8_t* pos_first;   // n_blk * (2N+1)^2: first contributor of its node
+    const int32_t* blk_col;     // n_blk: a member column (all four share the geometry)
+    double* cH;                 // hanging-point contributions (the column layout's buffer)
+    int64_t fsh;                // its field stride
+    int n_seg, Ls;              // vertical segments, layers per segment
 };
 
 // Owns the device memory of the tables.
 struct FusedPlan {
-    FusedTables t{};
+    FusedTables t{};                      // column layout (every column)
     std::vector<int32_t> color_ptr_host;
+    TailTables tail{};                    // column layout with side columns
+    bool has_tail = false;
+    int layout = 0;                       // SEM_LAYOUT_COLUMNS or SEM_LAYOUT_BLOCKS
+    BlockTables bt{};                     // block layout
+    FusedTables ts{};                     // block layout: the columns in no block
+    std::vector<int32_t> blk_ptr_host, single_ptr_host;   // per colour
+    int n_unit_color = 0;
     std::vector<void*> allocs;
     int64_t bytes = 0;
 };
-int fused_plan_build(const HostMesh& H, int layers_per_chunk, FusedPlan& plan);
+// layout SEM_LAYOUT_COLUMNS: param = layers per chunk (0 = default);
+// SEM_LAYOUT_BLOCKS: param = vertical segments (0 = default)
+int fused_plan_build(const HostMesh& H, int layout, int param, FusedPlan& plan);
 void fused_plan_free(FusedPlan& plan);
 bool fused_lpc_supported(int N, int layers_per_chunk);
+bool fused_blocks_supported(const HostMesh& H);
 
 // Launches the column kernel and the shared-node kernel on `stream`.
 int fused_stage_launch(const DevMesh& m, const FusedPlan& plan, double a, double b, double c,

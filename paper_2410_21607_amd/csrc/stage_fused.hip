@@ -32,6 +32,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <string>
 #include <type_traits>
 
@@ -188,8 +189,8 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
     __shared__ double s_ter[TER ? 4 : 1][TER ? NP2 : 1];   // g_s, g_s dzs/dx, g_s dzs/dy, 1/g_s
     if constexpr (TER) {
         for (int t = tid; t < NP2; t += WGT) {
-            const int gz = m.gmap[col * NP2 + t];
-            s_zs[t] = m.zs[gz >= 0 ? gz : m.n_h - gz - 1];
+            const int gz = ft.gmap[col * NP2 + t];
+            s_zs[t] = m.zs[gz >= 0 ? gz : ft.hreal[-gz - 1]];
         }
     }
     const bool lane_ok = (p < NP2) && (item < ncol);
@@ -197,7 +198,7 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
     const int i = pc % NP, j = pc / NP;
     const int nzn = m.nzn;
     const int64_t fs = int64_t(m.n_h) * m.ldz;
-    const int64_t fsh = int64_t(m.n_hh) * m.ldz;
+    const int64_t fsh = ft.fsh;
     const int64_t fsr = int64_t(m.n_h + m.n_hh) * m.ldz;   // terrain reference rows
 
     int g = 0, r_beg = 0, r_end = 0;
@@ -205,11 +206,11 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
     const double dxc = m.col_dx[col], dyc = m.col_dy[col];
     const T sx = T(m.col_sx[col]), sy = T(m.col_sy[col]);
     if (lane_ok) {
-        g = m.gmap[col * NP2 + pc];
+        g = ft.gmap[col * NP2 + pc];
         first = ft.first[col * NP2 + pc] != 0;
         if (g < 0) {
-            r_beg = m.hang_ptr[-g - 1];
-            r_end = m.hang_ptr[-g];
+            r_beg = ft.hang_ptr[-g - 1];
+            r_end = ft.hang_ptr[-g];
         }
     }
     // per-position constants in LDS rather than in every thread's registers:
@@ -222,10 +223,10 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
     // after the unique nodes)
     __shared__ int64_t s_rrow[TER ? NP2 : 1];
     for (int t = tid; t < NP2; t += WGT) {
-        const int gt = m.gmap[col * NP2 + t];
+        const int gt = ft.gmap[col * NP2 + t];
         s_mh[t] = gt >= 0 ? (TER ? m.minv_ht[gt] : m.minv_h[gt]) : 0.0;
         s_row[t] = gt >= 0 ? int64_t(gt) * m.ldz : 0;
-        if constexpr (TER) s_rrow[t] = int64_t(gt >= 0 ? gt : m.n_h - gt - 1) * m.ldz;
+        if constexpr (TER) s_rrow[t] = int64_t(gt >= 0 ? gt : ft.hreal[-gt - 1]) * m.ldz;
     }
     __syncthreads();
     for (int t = tid; t < NP2; t += WGT) s_mij[t] = sW[t % NP] * sW[t / NP] * 0.125 * dxc * dyc;
@@ -272,8 +273,8 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
                 }
             } else {
                 for (int r = r_beg; r < r_end; ++r) {
-                    const double w = m.hang_w[r];
-                    const int64_t o = int64_t(m.hang_src[r]) * m.ldz + kz;
+                    const double w = ft.hang_w[r];
+                    const int64_t o = int64_t(ft.hang_src[r]) * m.ldz + kz;
 #pragma unroll
                     for (int f = 0; f < NF; ++f) qv[f] += w * qs[f * fs + o];
                 }
@@ -557,7 +558,7 @@ __global__ void k_stage_hanging(DevMesh m, FusedTables ft, double c, double* __r
     const int nzn = m.nzn;
     const int64_t n = int64_t(m.n_hT) * nzn;
     const int64_t fs = int64_t(m.n_h) * m.ldz;
-    const int64_t fsh = int64_t(m.n_hh) * m.ldz;
+    const int64_t fsh = ft.fsh;
     for (int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; t < n;
          t += int64_t(gridDim.x) * blockDim.x) {
         const int li = int(t / nzn), kz = int(t - int64_t(li) * nzn);
@@ -588,6 +589,430 @@ __global__ void k_stage_hanging(DevMesh m, FusedTables ft, double c, double* __r
 #pragma unroll
         for (int f = 0; f < NF; ++f)
             if (!(f == 3 && lid)) qo[f * fs + o] += mi * s[f];
+    }
+}
+
+// Block kernel.  A workgroup owns one vertical segment of a 2 x 2 block of
+// columns of one level and marches up through it one layer (one element per
+// column) at a time; one thread per node of the block's (2N+1) x (2N+1)
+// positions and the layer's N+1 planes.  The block's own faces (the plane
+// x = x_mid of its two columns in x, y = y_mid likewise) are summed inside
+// the workgroup: a node there belongs to two (four at the centre) of the
+// block's elements, which differ only in the derivative across that face, so
+// the thread sums the x (y) derivative parts of its elements, weights the
+// other horizontal direction and the pointwise terms by the element count,
+// and takes one z derivative per element of the layer.  Only the block's
+// outer faces are shared with other blocks (read-modify-write across
+// colours), and only the segment's end planes with the neighbouring segments.
+template <int NP>
+constexpr int blk_threads() {
+    return (((2 * NP - 1) * (2 * NP - 1) * NP + 63) / 64) * 64;
+}
+
+template <int NP, typename T>
+__global__ void __launch_bounds__(blk_threads<NP>(), 4)
+k_stage_blocks(DevMesh m, BlockTables bt, int b0, int nblk, int seg_par, int n_iseg, double a,
+               double b, double c, const double* __restrict__ qn, const double* __restrict__ qs,
+               double* __restrict__ qo) {
+    constexpr int N = NP - 1, NK = NP, PX = 2 * N + 1, PP = PX * PX;
+    constexpr int NA = 4 * N * N;                 // positions inside the block's faces
+    constexpr int WGT = blk_threads<NP>();
+    using T2 = typename std::conditional<sizeof(T) == 8, double2, float2>::type;
+    __shared__ T tile[4][PP * NK];                // rho u, rho v, rho w, u: [field][p][kzl]
+    __shared__ T2 tpr[2][PP * NK];                // (v, w), (p', theta')
+    __shared__ double carry[2][NF][PP];
+    __shared__ T sD[NP * NP];
+    __shared__ T2 sDxy[NP * NP * NP];
+    __shared__ double sW[NP];
+    constexpr int SL = 6 * NK + 2;                // rho0, 1/rho0, 1/theta0, p0, dth0, 1/M_v; dz, 2/dz
+    __shared__ double slice[2][SL];
+    __shared__ double s_mh[PP], s_mij[PP];
+    __shared__ int64_t s_row[PP];
+    const int tid = threadIdx.x;
+    for (int t = tid; t < NP * NP; t += WGT) sD[t] = T(m.D[t]);
+    for (int t = tid; t < NP * NP * NP; t += WGT) {
+        const int pp = t / NP, mm = t - pp * NP;
+        sDxy[t].x = T(m.D[(pp % NP) * NP + mm]);
+        sDxy[t].y = T(m.D[(pp / NP) * NP + mm]);
+    }
+    for (int t = tid; t < NP; t += WGT) sW[t] = m.w[t];
+
+    // work item: (block, segment of this launch's parity), blocks of one
+    // XCD contiguous in the colour's (Morton-ordered) list
+    const int G = gridDim.x;
+    const int xcd = blockIdx.x & 7, rr = blockIdx.x >> 3;
+    const int item = xcd * (G >> 3) + min(xcd, G & 7) + rr;
+    const int bi = min(item / n_iseg, nblk - 1);
+    const int seg = 2 * (item - (item / n_iseg) * n_iseg) + seg_par;
+    const int blk = bt.order[b0 + bi];
+    const int Lb = seg * bt.Ls, Le = min(Lb + bt.Ls, m.n_z);
+    const int nl = Le - Lb;                       // layers (chunks) of the segment
+
+    // slice entry of this thread: source table, offset in the layer
+    const double* sl_src = nullptr;
+    int sl_off = 0, sl_lim = 0, sl_step = 0;
+    if (tid < 6 * NK) {
+        const int tab = tid / NK;
+        sl_src = tab == 0 ? m.rho0 : tab == 1 ? m.inv_rho0 : tab == 2 ? m.inv_theta0
+               : tab == 3 ? m.p0 : tab == 4 ? m.dth0 : m.minv_v;
+        sl_off = tid - tab * NK;
+        sl_step = N;
+        sl_lim = m.nzn;
+    } else if (tid < SL) {
+        sl_src = tid == 6 * NK ? m.dz : m.sz;
+        sl_step = 1;
+        sl_lim = m.n_z;
+    }
+    auto slice_value = [&](int L) {
+        const int k = sl_off + L * sl_step;
+        return (sl_src && k < sl_lim) ? sl_src[k] : 0.0;
+    };
+    if (tid < SL) slice[0][tid] = slice_value(Lb);
+
+    // thread -> (position, plane): positions inside the block's own faces
+    // first (one element in x and y), then the face positions (two or four
+    // elements), so that the longer work sits in the last waves
+    const int rank = tid / NK, kzl = tid - rank * NK;
+    int I = 0, J = 0, nx = 1, ny = 1;
+    if (rank < NA) {
+        I = rank % (2 * N);
+        J = rank / (2 * N);
+        I += (I >= N);
+        J += (J >= N);
+    } else if (rank < NA + 2 * N) {
+        const int r = rank - NA;
+        I = N;
+        J = r + (r >= N);
+        nx = 2;
+    } else if (rank < NA + 4 * N) {
+        const int r = rank - NA - 2 * N;
+        J = N;
+        I = r + (r >= N);
+        ny = 2;
+    } else {
+        I = J = N;
+        nx = ny = 2;
+    }
+    const bool lane_ok = rank < PP && item < nblk * n_iseg;
+    const int p = lane_ok ? I + PX * J : 0;
+    const int64_t fs = int64_t(m.n_h) * m.ldz;
+    const int64_t fsh = bt.fsh;
+    const int col = bt.blk_col[blk];
+    const double dxc = m.col_dx[col], dyc = m.col_dy[col];
+    const T sx = T(m.col_sx[col]), sy = T(m.col_sy[col]);
+    int g = 0, r_beg = 0, r_end = 0;
+    bool first_h = false;
+    if (lane_ok) {
+        g = bt.pos_g[int64_t(blk) * PP + p];
+        first_h = bt.pos_first[int64_t(blk) * PP + p] != 0;
+        if (g < 0) {
+            r_beg = m.hang_ptr[-g - 1];
+            r_end = m.hang_ptr[-g];
+        }
+    }
+    for (int t = tid; t < PP; t += WGT) {
+        const int gt = bt.pos_g[int64_t(blk) * PP + t];
+        const int ti = t % PX, tj = t / PX;
+        const int il = ti <= N ? ti : ti - N, jl = tj <= N ? tj : tj - N;
+        s_mh[t] = gt >= 0 ? m.minv_h[gt] : 0.0;
+        s_row[t] = gt >= 0 ? int64_t(gt) * m.ldz : 0;
+        s_mij[t] = m.w[il] * m.w[jl] * 0.125 * dxc * dyc;
+    }
+    __syncthreads();
+    // element-local indices along x and y (the left / lower element at a face)
+    const int il0 = I <= N ? I : I - N, jl0 = J <= N ? J : J - N;
+    const int qx0 = I < N ? 0 : (I > N ? 1 : 0), qy0 = J < N ? 0 : (J > N ? 1 : 0);
+    const T nn = T(nx * ny);
+    const int nt = nx > ny ? nx : ny;
+
+    double pf[NF] = {0, 0, 0, 0, 0};              // q_s of the next layer (direct nodes)
+    for (int ch = 0; ch < nl; ++ch) {
+        const int L = Lb + ch;
+        const int kz = L * N + kzl;
+        const int lidx = p * NK + kzl;
+        double qv[NF] = {0, 0, 0, 0, 0};
+        T rho = T(1);
+        const double* sp = slice[ch & 1];
+        if (lane_ok) {
+            if (g >= 0) {
+                if (ch > 0) {
+#pragma unroll
+                    for (int f = 0; f < NF; ++f) qv[f] = pf[f];
+                } else {
+                    const int64_t o = s_row[p] + kz;
+#pragma unroll
+                    for (int f = 0; f < NF; ++f) qv[f] = qs[f * fs + o];
+                }
+            } else {
+                for (int r = r_beg; r < r_end; ++r) {
+                    const double w = m.hang_w[r];
+                    const int64_t o = int64_t(m.hang_src[r]) * m.ldz + kz;
+#pragma unroll
+                    for (int f = 0; f < NF; ++f) qv[f] += w * qs[f * fs + o];
+                }
+            }
+            const double r0d = sp[kzl], irho0 = sp[NK + kzl], ith0 = sp[2 * NK + kzl],
+                         p0v = sp[3 * NK + kzl];
+            rho = T(r0d) + T(qv[0]);
+            const T u = T(qv[1]), v = T(qv[2]), w = T(qv[3]);
+            tile[0][lidx] = rho * u;
+            tile[1][lidx] = rho * v;
+            tile[2][lidx] = rho * w;
+            tile[3][lidx] = u;
+            {
+                T2 vw;
+                vw.x = v;
+                vw.y = w;
+                tpr[0][lidx] = vw;
+            }
+            {
+                // p' from the FP64 state without cancellation against p0
+                const double ra = qv[0] * irho0, tb = qv[4] * ith0;
+                T2 pt;
+                pt.x = T(p0v * pow1p_minus1(m, ra + tb + ra * tb));
+                pt.y = T(qv[4]);
+                tpr[1][lidx] = pt;
+            }
+        }
+        __syncthreads();
+        // the node is finished in this layer unless it is the top plane of a
+        // layer that is not the segment's last; the segment's end planes are
+        // shared with the neighbouring segments, whose even member writes first
+        const bool top_carry = (kzl == N) && (ch < nl - 1);
+        const bool seg_end = (kzl == 0 && ch == 0 && seg > 0) || (kzl == N && ch == nl - 1 && Le < m.n_z);
+        const bool first = first_h && !((seg & 1) && seg_end);
+        double base[NF] = {0, 0, 0, 0, 0};
+        if (lane_ok && g >= 0 && !top_carry && (!first || a != 0.0)) {
+            const double* bp = first ? qn : qo;
+            const int64_t o = s_row[p] + kz;
+#pragma unroll
+            for (int f = 0; f < NF; ++f) base[f] = bp[f * fs + o];
+        }
+        double sl_next = 0.0;
+        if (tid < SL && ch + 1 < nl) sl_next = slice_value(L + 1);
+        if (lane_ok && g >= 0 && ch + 1 < nl) {
+            const int64_t o = s_row[p] + kz + N;
+#pragma unroll
+            for (int f = 0; f < NF; ++f) pf[f] = qs[f * fs + o];
+        }
+        if (lane_ok) {
+            const T u = T(qv[1]), v = T(qv[2]), w = T(qv[3]);
+            const T inv_rho = T(1) / rho;
+            // derivative parts of the horizontal directions, summed over the
+            // elements of the block holding the node: iteration t takes x
+            // element min(t, nx-1) with weight ny (0 once t >= nx) and y
+            // element min(t, ny-1) with weight nx (0 once t >= ny)
+            T Rh[NF] = {0, 0, 0, 0, 0};
+            for (int t = 0; t < nt; ++t) {
+                const int ex = t < nx ? t : nx - 1, ey = t < ny ? t : ny - 1;
+                const int qx = nx == 2 ? ex : qx0, qy = ny == 2 ? ey : qy0;
+                const int il = nx == 2 ? (ex == 0 ? N : 0) : il0;
+                const int jl = ny == 2 ? (ey == 0 ? N : 0) : jl0;
+                const T wsx = t < nx ? sx * T(ny) : T(0), wsy = t < ny ? sy * T(nx) : T(0);
+                const T2* Dxy = &sDxy[(il + NP * jl) * NP];
+                const int lx0 = (qx * N + PX * J) * NK + kzl, ly0 = (I + PX * qy * N) * NK + kzl;
+                auto dxy = [&](int tx, int ty, int tx2, int ty2, T& ox, T& oy, T& ox2, T& oy2) {
+                    T ax = 0, ay = 0, ax2 = 0, ay2 = 0;
+#pragma unroll
+                    for (int mm = 0; mm < NP; ++mm) {
+                        const T2 cxy = Dxy[mm];
+                        ax += cxy.x * tile[tx][lx0 + mm * NK];
+                        ay += cxy.y * tile[ty][ly0 + mm * PX * NK];
+                        ax2 += cxy.x * tile[tx2][lx0 + mm * NK];
+                        ay2 += cxy.y * tile[ty2][ly0 + mm * PX * NK];
+                    }
+                    asm volatile("" : "+v"(ax), "+v"(ay), "+v"(ax2), "+v"(ay2) : : "memory");
+                    ox = ax * wsx;
+                    oy = ay * wsy;
+                    ox2 = ax2 * wsx;
+                    oy2 = ay2 * wsy;
+                };
+                auto dxyp = [&](int pr, T& ox, T& oy, T& ox2, T& oy2) {
+                    T ax = 0, ay = 0, ax2 = 0, ay2 = 0;
+#pragma unroll
+                    for (int mm = 0; mm < NP; ++mm) {
+                        const T2 cxy = Dxy[mm];
+                        const T2 va = tpr[pr][lx0 + mm * NK], vb = tpr[pr][ly0 + mm * PX * NK];
+                        ax += cxy.x * va.x;
+                        ay += cxy.y * vb.x;
+                        ax2 += cxy.x * va.y;
+                        ay2 += cxy.y * vb.y;
+                    }
+                    asm volatile("" : "+v"(ax), "+v"(ay), "+v"(ax2), "+v"(ay2) : : "memory");
+                    ox = ax * wsx;
+                    oy = ay * wsy;
+                    ox2 = ax2 * wsx;
+                    oy2 = ay2 * wsy;
+                };
+                T ax, ay, bx, by;
+                dxy(0, 1, 3, 3, ax, ay, bx, by);
+                Rh[0] -= ax + ay;
+                Rh[1] -= u * bx + v * by;
+                dxyp(0, ax, ay, bx, by);
+                Rh[2] -= u * ax + v * ay;
+                Rh[3] -= u * bx + v * by;
+                dxyp(1, bx, by, ax, ay);
+                Rh[1] -= bx * inv_rho;
+                Rh[2] -= by * inv_rho;
+                Rh[4] -= u * ax + v * ay;
+            }
+            // pointwise terms, once per element holding the node
+            const T f = T(m.f), gr = T(m.g);
+            Rh[1] += nn * (f * v);
+            Rh[2] -= nn * (f * u);
+            Rh[3] -= nn * (T(qv[0]) * inv_rho * gr);
+            Rh[4] -= nn * (w * T(sp[4 * NK + kzl]));
+            // z derivatives of the layer's element
+            const T sz = T(sp[6 * NK + 1]) * nn;
+            const T* Dz = &sD[kzl * NP];
+            const int lz0 = p * NK;
+            auto ddz = [&](int tz, int tz2, T& oz, T& oz2) {
+                T az = 0, az2 = 0;
+#pragma unroll
+                for (int mm = 0; mm < NP; ++mm) {
+                    const T cz = Dz[mm];
+                    az += cz * tile[tz][lz0 + mm];
+                    az2 += cz * tile[tz2][lz0 + mm];
+                }
+                asm volatile("" : "+v"(az), "+v"(az2) : : "memory");
+                oz = az * sz;
+                oz2 = az2 * sz;
+            };
+            auto ddzp = [&](int pr, T& oz, T& oz2) {
+                T az = 0, az2 = 0;
+#pragma unroll
+                for (int mm = 0; mm < NP; ++mm) {
+                    const T cz = Dz[mm];
+                    const T2 va = tpr[pr][lz0 + mm];
+                    az += cz * va.x;
+                    az2 += cz * va.y;
+                }
+                asm volatile("" : "+v"(az), "+v"(az2) : : "memory");
+                oz = az * sz;
+                oz2 = az2 * sz;
+            };
+            T R[NF], z0, z1, z2, z3;
+            ddz(2, 3, z0, z1);
+            R[0] = Rh[0] - z0;
+            R[1] = Rh[1] - w * z1;
+            ddzp(0, z0, z1);
+            R[2] = Rh[2] - w * z0;
+            ddzp(1, z2, z3);
+            R[3] = Rh[3] - w * z1 - z2 * inv_rho;
+            R[4] = Rh[4] - w * z3;
+            const double mass = s_mij[p] * sW[kzl] * sp[6 * NK];
+            double acc[NF];
+#pragma unroll
+            for (int fl = 0; fl < NF; ++fl) acc[fl] = mass * double(R[fl]);
+            if (top_carry) {
+#pragma unroll
+                for (int fl = 0; fl < NF; ++fl) carry[ch & 1][fl][p] = acc[fl];
+            } else {
+                if (kzl == 0 && ch > 0) {
+#pragma unroll
+                    for (int fl = 0; fl < NF; ++fl) acc[fl] += carry[(ch - 1) & 1][fl][p];
+                }
+                if (g >= 0) {
+                    const bool lid = (kz == 0) || (kz == m.nzn - 1);
+                    const double mi = c * s_mh[p] * sp[5 * NK + kzl];
+                    const int64_t o = s_row[p] + kz;
+                    if (first) {
+                        double rx[NF] = {0, 0, 0, 0, 0};
+                        if (m.rx) {
+#pragma unroll
+                            for (int fl = 0; fl < NF; ++fl) rx[fl] = c * m.rx[fl * fs + o];
+                        }
+#pragma unroll
+                        for (int fl = 0; fl < NF; ++fl) {
+                            const double tend = (fl == 3 && lid) ? 0.0 : mi * acc[fl];
+                            qo[fl * fs + o] = a * base[fl] + b * qv[fl] + tend + rx[fl];
+                        }
+                    } else {
+#pragma unroll
+                        for (int fl = 0; fl < NF; ++fl)
+                            if (!(fl == 3 && lid)) qo[fl * fs + o] = base[fl] + mi * acc[fl];
+                    }
+                } else {
+                    const int64_t o = int64_t(-g - 1) * m.ldz + kz;
+                    if (first) {
+#pragma unroll
+                        for (int fl = 0; fl < NF; ++fl) bt.cH[fl * fsh + o] = acc[fl];
+                    } else {
+#pragma unroll
+                        for (int fl = 0; fl < NF; ++fl) bt.cH[fl * fsh + o] += acc[fl];
+                    }
+                }
+            }
+        }
+        if (tid < SL && ch + 1 < nl) slice[(ch + 1) & 1][tid] = sl_next;
+        __syncthreads();
+    }
+}
+
+// Tail of a column-layout stage with side columns: every unique node that
+// receives side-slot contributions or hanging-point contributions (Z^T) sums
+// them in a fixed order and is finished here: written whole when no column
+// launch wrote it first, else added to.
+__global__ void k_stage_tail(DevMesh m, TailTables tl, double a, double b, double c,
+                             const double* __restrict__ qn, const double* __restrict__ qs,
+                             double* __restrict__ qo) {
+    const int nzn = m.nzn;
+    const int64_t n = int64_t(tl.n) * nzn;
+    const int64_t fs = int64_t(m.n_h) * m.ldz;
+    const int64_t fsh = tl.fsh;
+    for (int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; t < n;
+         t += int64_t(gridDim.x) * blockDim.x) {
+        const int li = int(t / nzn), kz = int(t - int64_t(li) * nzn);
+        const int h = tl.h[li];
+        double s[NF] = {0, 0, 0, 0, 0};
+        for (int r = tl.sptr[li]; r < tl.sptr[li + 1]; ++r) {
+            const int64_t o = int64_t(tl.sslot[r]) * m.ldz + kz;
+#pragma unroll
+            for (int f = 0; f < NF; ++f) s[f] += tl.cH[f * fsh + o];
+        }
+        for (int r = tl.hptr[li]; r < tl.hptr[li + 1]; ++r) {
+            const int hh = tl.hh[r];
+            double v[NF] = {0, 0, 0, 0, 0};
+            if (tl.hh_cvalid[hh]) {
+                const int64_t o = int64_t(hh) * m.ldz + kz;
+#pragma unroll
+                for (int f = 0; f < NF; ++f) v[f] = tl.cH[f * fsh + o];
+            }
+            for (int q = tl.hh_sptr[hh]; q < tl.hh_sptr[hh + 1]; ++q) {
+                const int64_t o = int64_t(tl.hh_sslot[q]) * m.ldz + kz;
+#pragma unroll
+                for (int f = 0; f < NF; ++f) v[f] += tl.cH[f * fsh + o];
+            }
+            const double w = tl.hw[r];
+#pragma unroll
+            for (int f = 0; f < NF; ++f) s[f] += w * v[f];
+        }
+        bool lid = (kz == 0) || (kz == nzn - 1);
+        double mi = c * m.minv_h[h] * m.minv_v[kz];
+        if (m.zs) {
+            mi = c * m.minv_ht[h] * m.minv_v[kz];
+            if (kz == 0) {
+                const double n0 = m.nrm[h], n1 = m.nrm[m.n_h + h], n2 = m.nrm[2 * m.n_h + h];
+                const double dn = s[1] * n0 + s[2] * n1 + s[3] * n2;
+                s[1] -= dn * n0;
+                s[2] -= dn * n1;
+                s[3] -= dn * n2;
+            }
+            lid = (kz == nzn - 1);
+        }
+        const int64_t o = int64_t(h) * m.ldz + kz;
+        if (tl.first[li]) {
+#pragma unroll
+            for (int f = 0; f < NF; ++f) {
+                const double tend = (f == 3 && lid) ? 0.0 : mi * s[f];
+                const double rx = m.rx ? c * m.rx[f * fs + o] : 0.0;
+                qo[f * fs + o] = (a != 0.0 ? a * qn[f * fs + o] : 0.0) + b * qs[f * fs + o] + tend + rx;
+            }
+        } else {
+#pragma unroll
+            for (int f = 0; f < NF; ++f)
+                if (!(f == 3 && lid)) qo[f * fs + o] += mi * s[f];
+        }
     }
 }
 
@@ -630,56 +1055,55 @@ bool fused_lpc_supported(int N, int lpc) {
     }
 }
 
-int fused_plan_build(const HostMesh& H, int lpc, FusedPlan& P) {
+bool fused_blocks_supported(const HostMesh& H) {
+    return H.N >= 3 && H.N <= 5 && !H.blk_cols.empty();
+}
+
+namespace {
+
+// greedy colouring in the given order of units that conflict when they
+// contribute to a common unique node or hanging point; returns the colours
+std::vector<int32_t> colour_units(const HostMesh& H, const std::vector<int32_t>& unit_of_col,
+                                  int n_unit, const std::vector<int32_t>& unit_order, int& n_color) {
     const int np2 = H.np1 * H.np1;
+    std::vector<std::vector<int32_t>> adj(static_cast<size_t>(n_unit));
+    auto link = [&](const std::vector<int32_t>& ptr, const std::vector<int32_t>& slot, int64_t n) {
+        for (int64_t x = 0; x < n; ++x)
+            for (int32_t q = ptr[x]; q < ptr[x + 1]; ++q)
+                for (int32_t r = ptr[x]; r < ptr[x + 1]; ++r) {
+                    const int32_t u1 = unit_of_col[slot[q] / np2], u2 = unit_of_col[slot[r] / np2];
+                    if (u1 != u2) adj[u1].push_back(u2);
+                }
+    };
+    link(H.asm_ptr, H.asm_slot, H.n_h);
+    link(H.asmH_ptr, H.asmH_slot, H.n_hh);
+    std::vector<int32_t> color(size_t(n_unit), -1);
+    n_color = 0;
+    for (int32_t u : unit_order) {
+        std::vector<char> used(size_t(n_color) + 1, 0);
+        for (int32_t o : adj[u])
+            if (color[o] >= 0) used[color[o]] = 1;
+        int k = 0;
+        while (used[k]) ++k;
+        color[u] = k;
+        n_color = std::max(n_color, k + 1);
+    }
+    return color;
+}
+
+}  // namespace
+
+int fused_plan_build(const HostMesh& H, int layout, int param, FusedPlan& P) {
+    const int np2 = H.np1 * H.np1;
+    int lpc = layout == SEM_LAYOUT_COLUMNS ? param : 0;
     if (lpc < 1) {
         // default: the deepest supported chunk of at most 512 threads
         lpc = 1;
         while (fused_lpc_supported(H.N, lpc * 2) && np2 * (2 * lpc * H.N + 1) <= 512) lpc *= 2;
     }
     if (!fused_lpc_supported(H.N, lpc)) return SEM_ERR_ARG;
-    // conflict lists: the columns contributing to each unique node / hanging point
-    std::vector<std::vector<int32_t>> adj(size_t(H.n_col));
-    auto link = [&](const std::vector<int32_t>& ptr, const std::vector<int32_t>& slot, int64_t n) {
-        for (int64_t x = 0; x < n; ++x)
-            for (int32_t q = ptr[x]; q < ptr[x + 1]; ++q)
-                for (int32_t r = ptr[x]; r < ptr[x + 1]; ++r) {
-                    const int32_t c1 = slot[q] / np2, c2 = slot[r] / np2;
-                    if (c1 != c2) adj[c1].push_back(c2);
-                }
-    };
-    link(H.asm_ptr, H.asm_slot, H.n_h);
-    link(H.asmH_ptr, H.asmH_slot, H.n_hh);
-    // greedy colouring in column order (the caller's order; Morton keeps it local)
-    std::vector<int32_t> color(size_t(H.n_col), -1);
-    int n_color = 0;
-    for (int cidx = 0; cidx < H.n_col; ++cidx) {
-        std::vector<char> used(size_t(n_color) + 1, 0);
-        for (int32_t o : adj[cidx])
-            if (color[o] >= 0) used[color[o]] = 1;
-        int k = 0;
-        while (used[k]) ++k;
-        color[cidx] = k;
-        n_color = std::max(n_color, k + 1);
-    }
-    std::vector<int32_t> order, cptr(size_t(n_color) + 1, 0);
-    for (int k = 0; k < n_color; ++k) {
-        for (int cidx = 0; cidx < H.n_col; ++cidx)
-            if (color[cidx] == k) order.push_back(cidx);
-        cptr[k + 1] = int32_t(order.size());
-    }
-    // first contributor of every node: the lowest colour among its columns
-    std::vector<uint8_t> first(H.gmap.size(), 0);
-    auto mark = [&](const std::vector<int32_t>& ptr, const std::vector<int32_t>& slot, int64_t n) {
-        for (int64_t x = 0; x < n; ++x) {
-            int32_t best = -1;
-            for (int32_t q = ptr[x]; q < ptr[x + 1]; ++q)
-                if (best < 0 || color[slot[q] / np2] < color[best / np2]) best = slot[q];
-            if (best >= 0) first[best] = 1;
-        }
-    };
-    mark(H.asm_ptr, H.asm_slot, H.n_h);
-    mark(H.asmH_ptr, H.asmH_slot, H.n_hh);
+    if (layout == SEM_LAYOUT_BLOCKS && !fused_blocks_supported(H)) return SEM_ERR_ARG;
+    if (layout != SEM_LAYOUT_COLUMNS && layout != SEM_LAYOUT_BLOCKS) return SEM_ERR_ARG;
     auto up = [&](const void* src, size_t bytes, void** dst) -> int {
         *dst = nullptr;
         if (bytes == 0) return SEM_OK;
@@ -689,19 +1113,284 @@ int fused_plan_build(const HostMesh& H, int lpc, FusedPlan& P) {
         if (src && hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice) != hipSuccess) return SEM_ERR_HIP;
         return SEM_OK;
     };
+    // first contributor of every node: the lowest colour among its units
+    auto mark_first = [&](const std::vector<int32_t>& unit_of_col, const std::vector<int32_t>& color,
+                          auto&& set_first) {
+        auto mark = [&](const std::vector<int32_t>& ptr, const std::vector<int32_t>& slot, int64_t n) {
+            for (int64_t x = 0; x < n; ++x) {
+                int32_t best = -1;
+                for (int32_t q = ptr[x]; q < ptr[x + 1]; ++q)
+                    if (best < 0 || color[unit_of_col[slot[q] / np2]] < color[unit_of_col[best / np2]])
+                        best = slot[q];
+                if (best >= 0) set_first(best);
+            }
+        };
+        mark(H.asm_ptr, H.asm_slot, H.n_h);
+        mark(H.asmH_ptr, H.asmH_slot, H.n_hh);
+    };
     void* d;
     int rc;
-    if ((rc = up(order.data(), order.size() * 4, &d)) != SEM_OK) return rc;
-    P.t.col_order = static_cast<const int32_t*>(d);
-    if ((rc = up(cptr.data(), cptr.size() * 4, &d)) != SEM_OK) return rc;
-    P.t.color_ptr = static_cast<const int32_t*>(d);
-    if ((rc = up(first.data(), first.size(), &d)) != SEM_OK) return rc;
-    P.t.first = static_cast<const uint8_t*>(d);
-    if ((rc = up(nullptr, size_t(NF) * H.n_hh * H.ldz * 8, &d)) != SEM_OK) return rc;
-    P.t.cH = static_cast<double*>(d);
-    P.t.n_color = n_color;
-    P.t.layers_per_chunk = lpc;
-    P.color_ptr_host = cptr;
+    // ---- column layout over every column (also the terrain path)
+    {
+        std::vector<int32_t> unit_of_col(static_cast<size_t>(H.n_col)), corder(static_cast<size_t>(H.n_col));
+        for (int c = 0; c < H.n_col; ++c) unit_of_col[c] = corder[c] = c;
+        int n_color = 0;
+        // greedy colouring in column order (the caller's order; Morton keeps it local)
+        std::vector<int32_t> color = colour_units(H, unit_of_col, H.n_col, corder, n_color);
+        // side columns: the colour classes beyond the fourth that hold fewer
+        // than a quarter of the largest class's columns.  Their launches
+        // would be short and latency-bound; instead they run in the first
+        // colour's launch (they only read q_s and write their own slots)
+        // and the tail launch assembles their contributions.
+        std::vector<int32_t> csize(size_t(n_color), 0);
+        for (int cidx = 0; cidx < H.n_col; ++cidx) ++csize[color[cidx]];
+        const int32_t cmax = *std::max_element(csize.begin(), csize.end());
+        std::vector<char> small(size_t(n_color), 0);
+        for (int k = 4; k < n_color; ++k) small[k] = 4 * csize[k] < cmax;
+        std::vector<int32_t> side_of_col(static_cast<size_t>(H.n_col), -1), side_cols;
+        for (int cidx = 0; cidx < H.n_col; ++cidx)
+            if (small[color[cidx]]) {
+                side_of_col[cidx] = int32_t(side_cols.size());
+                side_cols.push_back(cidx);
+            }
+        std::vector<int32_t> order, cptr(1, 0);
+        for (int k = 0; k < n_color; ++k) {
+            if (small[k]) continue;
+            for (int cidx = 0; cidx < H.n_col; ++cidx)
+                if (color[cidx] == k) order.push_back(cidx);
+            if (cptr.size() == 1) order.insert(order.end(), side_cols.begin(), side_cols.end());
+            cptr.push_back(int32_t(order.size()));
+        }
+        n_color = int(cptr.size()) - 1;
+        // positions of side columns become pseudo hanging points n_hh + k (N+1)^2 + pos
+        const int64_t n_pseudo = int64_t(side_cols.size()) * np2;
+        auto pseudo = [&](int32_t slot) {
+            return int32_t(H.n_hh + int64_t(side_of_col[slot / np2]) * np2 + slot % np2);
+        };
+        std::vector<int32_t> gmap_x(H.gmap), hptr_x(H.hang_ptr), hsrc_x(H.hang_src);
+        std::vector<double> hw_x(H.hang_w);
+        std::vector<int32_t> hreal(static_cast<size_t>(H.n_hh + n_pseudo));
+        for (int64_t hh = 0; hh < H.n_hh; ++hh) hreal[hh] = int32_t(H.n_h + hh);
+        if (hptr_x.empty()) hptr_x.push_back(0);
+        for (int32_t sc : side_cols)
+            for (int pos = 0; pos < np2; ++pos) {
+                const int32_t slot = sc * np2 + pos, g = H.gmap[slot];
+                if (g >= 0) {
+                    hsrc_x.push_back(g);
+                    hw_x.push_back(1.0);
+                    hreal[pseudo(slot)] = g;
+                } else {
+                    for (int32_t r = H.hang_ptr[-g - 1]; r < H.hang_ptr[-g]; ++r) {
+                        hsrc_x.push_back(H.hang_src[r]);
+                        hw_x.push_back(H.hang_w[r]);
+                    }
+                    hreal[pseudo(slot)] = int32_t(H.n_h - g - 1);
+                }
+                hptr_x.push_back(int32_t(hsrc_x.size()));
+                gmap_x[slot] = -(pseudo(slot) + 1);
+            }
+        // first writers among the columns that write nodes themselves; every
+        // pseudo point has exactly one writer
+        std::vector<int32_t> wcolor(color);
+        for (int32_t sc : side_cols) wcolor[sc] = INT32_MAX;
+        std::vector<uint8_t> first(H.gmap.size(), 0);
+        mark_first(unit_of_col, wcolor, [&](int32_t slot) {
+            if (side_of_col[slot / np2] < 0) first[slot] = 1;
+        });
+        for (int32_t sc : side_cols)
+            for (int pos = 0; pos < np2; ++pos) first[size_t(sc) * np2 + pos] = 1;
+        auto upv = [&](const auto& v, auto** dst) -> int {
+            void* pd = nullptr;
+            const size_t bytes = v.size() * sizeof(v[0]);
+            // an empty table still gets a (never read) 8-byte allocation
+            int r2 = up(bytes ? static_cast<const void*>(v.data()) : nullptr,
+                        std::max<size_t>(bytes, 8), &pd);
+            *dst = static_cast<std::remove_pointer_t<decltype(dst)>>(pd);
+            return r2;
+        };
+        if ((rc = upv(gmap_x, &P.t.gmap)) != SEM_OK) return rc;
+        if ((rc = upv(hptr_x, &P.t.hang_ptr)) != SEM_OK) return rc;
+        if ((rc = upv(hsrc_x, &P.t.hang_src)) != SEM_OK) return rc;
+        if ((rc = upv(hw_x, &P.t.hang_w)) != SEM_OK) return rc;
+        if ((rc = upv(hreal, &P.t.hreal)) != SEM_OK) return rc;
+        P.t.fsh = (H.n_hh + n_pseudo) * H.ldz;
+        if (!side_cols.empty()) {
+            // tail tables: unique nodes with side slots or Z^T rows
+            auto is_side = [&](int32_t slot) { return side_of_col[slot / np2] >= 0; };
+            std::vector<int32_t> hT_row(static_cast<size_t>(H.n_h), -1);
+            for (size_t li = 0; li < H.hT_list.size(); ++li) hT_row[H.hT_list[li]] = int32_t(li);
+            std::vector<int32_t> th, tsptr(1, 0), tsslot, thptr(1, 0), thh;
+            std::vector<double> thw;
+            std::vector<uint8_t> tfirst;
+            for (int64_t h = 0; h < H.n_h; ++h) {
+                bool any_side = false, any_direct = false;
+                for (int32_t q = H.asm_ptr[h]; q < H.asm_ptr[h + 1]; ++q) {
+                    if (is_side(H.asm_slot[q])) any_side = true;
+                    else any_direct = true;
+                }
+                if (!any_side && hT_row[h] < 0) continue;
+                th.push_back(int32_t(h));
+                tfirst.push_back(any_direct ? 0 : 1);
+                for (int32_t q = H.asm_ptr[h]; q < H.asm_ptr[h + 1]; ++q)
+                    if (is_side(H.asm_slot[q])) tsslot.push_back(pseudo(H.asm_slot[q]));
+                tsptr.push_back(int32_t(tsslot.size()));
+                if (hT_row[h] >= 0) {
+                    const int32_t li = hT_row[h];
+                    for (int32_t r = H.hT_ptr[li]; r < H.hT_ptr[li + 1]; ++r) {
+                        thh.push_back(H.hT_hh[r]);
+                        thw.push_back(H.hT_w[r]);
+                    }
+                }
+                thptr.push_back(int32_t(thh.size()));
+            }
+            std::vector<int32_t> hsptr(1, 0), hsslot;
+            std::vector<uint8_t> hvalid(static_cast<size_t>(std::max<int64_t>(H.n_hh, 1)), 0);
+            for (int64_t hh = 0; hh < H.n_hh; ++hh) {
+                for (int32_t q = H.asmH_ptr[hh]; q < H.asmH_ptr[hh + 1]; ++q) {
+                    if (is_side(H.asmH_slot[q])) hsslot.push_back(pseudo(H.asmH_slot[q]));
+                    else hvalid[hh] = 1;
+                }
+                hsptr.push_back(int32_t(hsslot.size()));
+            }
+            if (hsptr.size() == 1) hsptr.push_back(0);
+            TailTables& T = P.tail;
+            if ((rc = upv(th, &T.h)) != SEM_OK) return rc;
+            if ((rc = upv(tfirst, &T.first)) != SEM_OK) return rc;
+            if ((rc = upv(tsptr, &T.sptr)) != SEM_OK) return rc;
+            if ((rc = upv(tsslot, &T.sslot)) != SEM_OK) return rc;
+            if ((rc = upv(thptr, &T.hptr)) != SEM_OK) return rc;
+            if ((rc = upv(thh, &T.hh)) != SEM_OK) return rc;
+            if ((rc = upv(thw, &T.hw)) != SEM_OK) return rc;
+            if ((rc = upv(hsptr, &T.hh_sptr)) != SEM_OK) return rc;
+            if ((rc = upv(hsslot, &T.hh_sslot)) != SEM_OK) return rc;
+            if ((rc = upv(hvalid, &T.hh_cvalid)) != SEM_OK) return rc;
+            T.n = int(th.size());
+            T.fsh = P.t.fsh;
+            P.has_tail = true;
+        }
+        if ((rc = up(order.data(), order.size() * 4, &d)) != SEM_OK) return rc;
+        P.t.col_order = static_cast<const int32_t*>(d);
+        if ((rc = up(cptr.data(), cptr.size() * 4, &d)) != SEM_OK) return rc;
+        P.t.color_ptr = static_cast<const int32_t*>(d);
+        if ((rc = up(first.data(), first.size(), &d)) != SEM_OK) return rc;
+        P.t.first = static_cast<const uint8_t*>(d);
+        if ((rc = up(nullptr, size_t(NF) * P.t.fsh * 8, &d)) != SEM_OK) return rc;
+        P.t.cH = static_cast<double*>(d);
+        P.tail.cH = P.t.cH;
+        P.t.n_color = n_color;
+        P.t.layers_per_chunk = lpc;
+        P.color_ptr_host = cptr;
+    }
+    P.layout = SEM_LAYOUT_COLUMNS;
+    if (layout == SEM_LAYOUT_COLUMNS) return SEM_OK;
+
+    // ---- block layout: units are the 2 x 2 blocks and the columns in no block
+    const int N = H.N, PX = 2 * N + 1, PP = PX * PX;
+    const int nb = int(H.blk_cols.size() / 4);
+    std::vector<int32_t> unit_of_col(static_cast<size_t>(H.n_col)), singles, unit_first_col;
+    for (int c = 0; c < H.n_col; ++c) {
+        if (H.col_block[c] >= 0) unit_of_col[c] = H.col_block[c];
+        else {
+            unit_of_col[c] = nb + int32_t(singles.size());
+            singles.push_back(c);
+        }
+    }
+    const int n_unit = nb + int(singles.size());
+    unit_first_col.assign(size_t(n_unit), H.n_col);
+    for (int c = 0; c < H.n_col; ++c)
+        unit_first_col[unit_of_col[c]] = std::min(unit_first_col[unit_of_col[c]], c);
+    std::vector<int32_t> uorder(static_cast<size_t>(n_unit));
+    for (int u = 0; u < n_unit; ++u) uorder[u] = u;
+    std::stable_sort(uorder.begin(), uorder.end(),
+                     [&](int32_t x, int32_t y) { return unit_first_col[x] < unit_first_col[y]; });
+    int n_color = 0;
+    std::vector<int32_t> color = colour_units(H, unit_of_col, n_unit, uorder, n_color);
+    // block position of every slot of a block's columns
+    auto block_pos = [&](int32_t slot) {
+        const int c = slot / np2, pos = slot - c * np2;
+        const int i = pos % H.np1, j = pos / H.np1;
+        const int32_t* bc = &H.blk_cols[size_t(H.col_block[c]) * 4];
+        int q = 0;
+        while (bc[q] != c) ++q;
+        return (i + (q & 1) * N) + PX * (j + (q >> 1) * N);
+    };
+    std::vector<uint8_t> pos_first(size_t(nb) * PP, 0), first_s(H.gmap.size(), 0);
+    mark_first(unit_of_col, color, [&](int32_t slot) {
+        const int c = slot / np2;
+        if (H.col_block[c] >= 0) pos_first[size_t(H.col_block[c]) * PP + block_pos(slot)] = 1;
+        else first_s[slot] = 1;
+    });
+    std::vector<int32_t> pos_g(static_cast<size_t>(nb) * PP, 0), blk_col(static_cast<size_t>(nb));
+    for (int b = 0; b < nb; ++b) {
+        blk_col[b] = H.blk_cols[size_t(b) * 4];
+        for (int q = 0; q < 4; ++q) {
+            const int c = H.blk_cols[size_t(b) * 4 + q];
+            for (int pos = 0; pos < np2; ++pos) {
+                const int32_t slot = c * np2 + pos;
+                pos_g[size_t(b) * PP + block_pos(slot)] = H.gmap[slot];
+            }
+        }
+    }
+    std::vector<int32_t> border, sorder, bptr(size_t(n_color) + 1, 0), sptr(size_t(n_color) + 1, 0);
+    for (int k = 0; k < n_color; ++k) {
+        for (int32_t u : uorder) {
+            if (color[u] != k) continue;
+            if (u < nb) border.push_back(u);
+            else sorder.push_back(singles[u - nb]);
+        }
+        bptr[k + 1] = int32_t(border.size());
+        sptr[k + 1] = int32_t(sorder.size());
+    }
+    // vertical segments: by default enough for about 1024 workgroups per
+    // launch of the largest colour (two resident per CU on 256 CUs, both
+    // parities), at least one layer each
+    int S = param;
+    if (S < 1) {
+        int nbmax = 1;
+        for (int k = 0; k < n_color; ++k) nbmax = std::max(nbmax, bptr[k + 1] - bptr[k]);
+        S = 1;
+        while (S < H.n_z && nbmax * S < 1024) S *= 2;
+    }
+    S = std::min(S, H.n_z);
+    const int Ls = (H.n_z + S - 1) / S;
+    if ((rc = up(border.data(), border.size() * 4, &d)) != SEM_OK) return rc;
+    P.bt.order = static_cast<const int32_t*>(d);
+    if ((rc = up(pos_g.data(), pos_g.size() * 4, &d)) != SEM_OK) return rc;
+    P.bt.pos_g = static_cast<const int32_t*>(d);
+    if ((rc = up(pos_first.data(), pos_first.size(), &d)) != SEM_OK) return rc;
+    P.bt.pos_first = static_cast<const uint8_t*>(d);
+    if ((rc = up(blk_col.data(), blk_col.size() * 4, &d)) != SEM_OK) return rc;
+    P.bt.blk_col = static_cast<const int32_t*>(d);
+    P.bt.cH = P.t.cH;
+    P.bt.Ls = Ls;
+    P.bt.n_seg = (H.n_z + Ls - 1) / Ls;
+    P.bt.fsh = P.t.fsh;
+    P.ts = P.t;
+    // the columns in no block read the mesh's own position map and rows (the
+    // column layout's pseudo hanging points belong to its side columns only)
+    if ((rc = up(H.gmap.data(), H.gmap.size() * 4, &d)) != SEM_OK) return rc;
+    P.ts.gmap = static_cast<const int32_t*>(d);
+    if (H.n_hh > 0) {
+        if ((rc = up(H.hang_ptr.data(), H.hang_ptr.size() * 4, &d)) != SEM_OK) return rc;
+        P.ts.hang_ptr = static_cast<const int32_t*>(d);
+        if ((rc = up(H.hang_src.data(), H.hang_src.size() * 4, &d)) != SEM_OK) return rc;
+        P.ts.hang_src = static_cast<const int32_t*>(d);
+        if ((rc = up(H.hang_w.data(), H.hang_w.size() * 8, &d)) != SEM_OK) return rc;
+        P.ts.hang_w = static_cast<const double*>(d);
+    }
+    P.ts.col_order = nullptr;
+    if (!sorder.empty()) {
+        if ((rc = up(sorder.data(), sorder.size() * 4, &d)) != SEM_OK) return rc;
+        P.ts.col_order = static_cast<const int32_t*>(d);
+    }
+    if ((rc = up(first_s.data(), first_s.size(), &d)) != SEM_OK) return rc;
+    P.ts.first = static_cast<const uint8_t*>(d);
+    P.ts.color_ptr = nullptr;
+    P.ts.n_color = n_color;
+    P.blk_ptr_host = bptr;
+    P.single_ptr_host = sptr;
+    P.n_unit_color = n_color;
+    P.layout = SEM_LAYOUT_BLOCKS;
     return SEM_OK;
 }
 
@@ -711,27 +1400,72 @@ void fused_plan_free(FusedPlan& P) {
     P.bytes = 0;
 }
 
+template <typename T>
+int launch_blocks(const DevMesh& m, const BlockTables& bt, int b0, int nblk, int par, int n_iseg,
+                  double a, double b, double c, const double* qn, const double* qs, double* qo,
+                  hipStream_t s) {
+    const unsigned grid = unsigned(nblk) * unsigned(n_iseg);
+    switch (m.N) {
+#define CASE(NN)                                                                              \
+    case NN:                                                                                  \
+        hipLaunchKernelGGL((k_stage_blocks<NN + 1, T>), dim3(grid), dim3(blk_threads<NN + 1>()), 0, \
+                           s, m, bt, b0, nblk, par, n_iseg, a, b, c, qn, qs, qo);           \
+        break;
+        CASE(3) CASE(4) CASE(5)
+#undef CASE
+        default: return SEM_ERR_ARG;
+    }
+    return (hipGetLastError() == hipSuccess) ? SEM_OK : SEM_ERR_HIP;
+}
+
 int fused_stage_launch(const DevMesh& m, const FusedPlan& P, double a, double b, double c,
                        const double* qn, const double* qs, double* qo, int prec, hipStream_t s) {
-    const FusedTables& t = P.t;
-    for (int k = 0; k < t.n_color; ++k) {
-        const int col0 = P.color_ptr_host[k];
-        const int ncol = P.color_ptr_host[k + 1] - col0;
-        if (ncol == 0) continue;
-        int rc;
-        if (m.zs) {
-            rc = (prec == SEM_FP32) ? launch_t<float, true>(m, t, col0, ncol, a, b, c, qn, qs, qo, s)
-                                    : launch_t<double, true>(m, t, col0, ncol, a, b, c, qn, qs, qo, s);
-        } else {
-            rc = (prec == SEM_FP32) ? launch_t<float, false>(m, t, col0, ncol, a, b, c, qn, qs, qo, s)
-                                    : launch_t<double, false>(m, t, col0, ncol, a, b, c, qn, qs, qo, s);
+    const bool f32 = prec == SEM_FP32;
+    if (P.layout == SEM_LAYOUT_BLOCKS && !m.zs) {
+        // colour by colour: the colour's blocks, even segments then odd
+        // ones, then its columns in no block
+        const BlockTables& bt = P.bt;
+        for (int k = 0; k < P.n_unit_color; ++k) {
+            const int b0 = P.blk_ptr_host[k], nb = P.blk_ptr_host[k + 1] - b0;
+            for (int par = 0; par < 2 && nb > 0; ++par) {
+                const int n_iseg = par == 0 ? (bt.n_seg + 1) / 2 : bt.n_seg / 2;
+                if (n_iseg == 0) continue;
+                const int rc = f32 ? launch_blocks<float>(m, bt, b0, nb, par, n_iseg, a, b, c, qn, qs, qo, s)
+                                   : launch_blocks<double>(m, bt, b0, nb, par, n_iseg, a, b, c, qn, qs, qo, s);
+                if (rc != SEM_OK) return rc;
+            }
+            const int s0 = P.single_ptr_host[k], ns = P.single_ptr_host[k + 1] - s0;
+            if (ns > 0) {
+                const int rc = f32 ? launch_t<float, false>(m, P.ts, s0, ns, a, b, c, qn, qs, qo, s)
+                                   : launch_t<double, false>(m, P.ts, s0, ns, a, b, c, qn, qs, qo, s);
+                if (rc != SEM_OK) return rc;
+            }
         }
-        if (rc != SEM_OK) return rc;
+    } else {
+        const FusedTables& t = P.t;
+        for (int k = 0; k < t.n_color; ++k) {
+            const int col0 = P.color_ptr_host[k];
+            const int ncol = P.color_ptr_host[k + 1] - col0;
+            if (ncol == 0) continue;
+            int rc;
+            if (m.zs) {
+                rc = f32 ? launch_t<float, true>(m, t, col0, ncol, a, b, c, qn, qs, qo, s)
+                         : launch_t<double, true>(m, t, col0, ncol, a, b, c, qn, qs, qo, s);
+            } else {
+                rc = f32 ? launch_t<float, false>(m, t, col0, ncol, a, b, c, qn, qs, qo, s)
+                         : launch_t<double, false>(m, t, col0, ncol, a, b, c, qn, qs, qo, s);
+            }
+            if (rc != SEM_OK) return rc;
+        }
     }
-    const int64_t n2 = int64_t(m.n_hT) * m.nzn;
+    const bool tail = P.has_tail && !(P.layout == SEM_LAYOUT_BLOCKS && !m.zs);
+    const int64_t n2 = int64_t(tail ? P.tail.n : m.n_hT) * m.nzn;
     if (n2 > 0) {
         const int64_t g = std::min<int64_t>((n2 + 255) / 256, 65536);
-        hipLaunchKernelGGL(k_stage_hanging, dim3(unsigned(g)), dim3(256), 0, s, m, t, c, qo);
+        if (tail)
+            hipLaunchKernelGGL(k_stage_tail, dim3(unsigned(g)), dim3(256), 0, s, m, P.tail, a, b, c, qn, qs, qo);
+        else
+            hipLaunchKernelGGL(k_stage_hanging, dim3(unsigned(g)), dim3(256), 0, s, m, P.t, c, qo);
         if (hipGetLastError() != hipSuccess) return SEM_ERR_HIP;
     }
     return SEM_OK;

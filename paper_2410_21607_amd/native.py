@@ -63,6 +63,8 @@ SIGNATURES = {
                           c_void_p, c_int, c_void_p]),
     "sem_stage_tune": (c_int, [c_void_p, c_int]),
     "sem_stage_get_tune": (c_int, [c_void_p, ctypes.POINTER(c_int)]),
+    "sem_stage_set_layout": (c_int, [c_void_p, c_int, c_int]),
+    "sem_stage_get_layout": (c_int, [c_void_p, ctypes.POINTER(c_int), ctypes.POINTER(c_int)]),
     "sem_stage_autotune": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_int,
                                    ctypes.POINTER(c_int), ctypes.POINTER(ctypes.c_float), c_void_p]),
     "amr_flag": (c_int, [c_void_p, c_void_p, c_int, c_dp, c_int, c_void_p, c_void_p, c_void_p]),

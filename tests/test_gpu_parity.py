@@ -299,23 +299,28 @@ def test_api_rejects_bad_calls():
         api.sem_stage(S.gm, 0.0, 1.0, 1.0, q[:-1], q.clone(), torch.zeros_like(q))
 
 
-TUNES = [1, 2, 4, 8]
+# work layouts of the fused stage: single columns in chunks of 1, 2, 4, 8
+# layers; 2 x 2 column blocks in 1, 2 or 4 vertical segments
+TUNES = [(0, 1), (0, 2), (0, 4), (0, 8), (1, 1), (1, 2), (1, 4)]
+TUNE_IDS = ["col1", "col2", "col4", "col8", "blk1", "blk2", "blk4"]
+DECOMP = [0, 2, 4, 5, 6, 7]
 
 
-@pytest.mark.parametrize("name,kw", [CASES[0], CASES[2], CASES[5], CASES[6]],
-                         ids=[IDS[0], IDS[2], IDS[5], IDS[6]])
-@pytest.mark.parametrize("ipw", TUNES)
-def test_fused_stage_decompositions(name, kw, ipw):
-    """Every work decomposition of the fused stage gives the oracle's stage."""
+@pytest.mark.parametrize("name,kw", [CASES[k] for k in DECOMP], ids=[IDS[k] for k in DECOMP])
+@pytest.mark.parametrize("layout", TUNES, ids=TUNE_IDS)
+def test_fused_stage_decompositions(name, kw, layout):
+    """Every work layout of the fused stage gives the oracle's stage."""
     S = get(name, kw)
     torch, api = S.torch, S.api
     from paper_2410_21607_amd.native import SemError
-    say("fused tune", name, kw, ipw)
+    say("fused layout", name, kw, layout)
+    saved = api.sem_stage_get_layout(S.gm)
     try:
-        api.sem_stage_tune(S.gm, ipw)
+        api.sem_stage_set_layout(S.gm, *layout)
     except SemError:
-        pytest.skip("no kernel instance for this order and packing")
+        pytest.skip("no kernel instance for this order and layout")
     try:
+        assert api.sem_stage_get_layout(S.gm)[0] == layout[0]
         dt = S.c["dt"]
         qn = S.q_g.clone()
         qs = S.q_g.clone()
@@ -326,12 +331,36 @@ def test_fused_stage_decompositions(name, kw, ipw):
             qs, out = out, qs
         torch.cuda.synchronize()
     finally:
-        api.sem_stage_tune(S.gm, 0)
+        api.sem_stage_set_layout(S.gm, *saved)
     rhs = lambda q: assembly.rhs(S.om, q, S.ref, S.c["phys"])
     want, _ = timestep.run_stages(rhs, S.q_or, dt, 3)
     err = metrics.rel_l2(S.to_oracle_order(qs), want, metrics.STATE_FLOORS)
     say("  rel", err)
     assert err.max() <= TOL64
+
+
+def test_layouts_agree_with_each_other():
+    """The block and column layouts sum the same contributions in different
+    orders: on every mesh with blocks their stages agree to 1e-14."""
+    for k in DECOMP:
+        S = get(*CASES[k])
+        torch, api = S.torch, S.api
+        if not (3 <= S.c["N"] <= 5):
+            continue
+        saved = api.sem_stage_get_layout(S.gm)
+        outs = []
+        try:
+            for lay in ((0, 0), (1, 0)):
+                api.sem_stage_set_layout(S.gm, *lay)
+                out = torch.zeros_like(S.q_g)
+                api.sem_stage(S.gm, 0.75, 0.25, 0.25 * S.c["dt"], S.q_g, S.q_g, out, api.SEM_FP64)
+                torch.cuda.synchronize()
+                outs.append(S.gm.pack(out))
+        finally:
+            api.sem_stage_set_layout(S.gm, *saved)
+        err = metrics.rel_l2(outs[1], outs[0], metrics.STATE_FLOORS)
+        say("  layouts", IDS[k], err)
+        assert err.max() <= 1e-14
 
 
 def test_fused_fp32_stage_error():

@@ -100,6 +100,7 @@ def test_autotune_then_parity():
     say("  chosen layers_per_chunk", lpc, "ms", ms)
     assert lpc in (1, 2, 4, 8) and ms > 0
     assert api.sem_stage_get_tune(gm) == lpc
+    say("  layout", api.sem_stage_get_layout(gm))
     out = torch.zeros_like(q_g)
     a, b, cc = timestep.stage_coefficients(0, c["dt"])
     api.sem_stage(gm, a, b, cc, q_g, q_g, out, api.SEM_FP64)
@@ -144,7 +145,8 @@ def test_graph_recaptured_after_mesh_changes():
     eager.step()
     torch.cuda.synchronize()
     assert torch.equal(graph.q, eager.q)
-    for k, change in enumerate((lambda: api.sem_stage_tune(gm, 1), lambda: api.sem_stage_tune(gm, 2),
+    for k, change in enumerate((lambda: api.sem_stage_tune(gm, 1),
+                                lambda: api.sem_stage_set_layout(gm, api.SEM_LAYOUT_BLOCKS, 2),
                                 lambda: gm.set_dissipation(0.0, 0.0))):
         change()
         assert gm.epoch() > e0
@@ -159,4 +161,4 @@ def test_graph_recaptured_after_mesh_changes():
     eager.step()
     torch.cuda.synchronize()
     assert graph.captures == 4 and torch.equal(graph.q, eager.q)
-    api.sem_stage_tune(gm, 0)
+    api.sem_stage_set_layout(gm, api.SEM_LAYOUT_COLUMNS, 0)
