@@ -441,6 +441,9 @@ def main():
                          "absorbing-layer terms on (default off, the inviscid stage)")
     ap.add_argument("--workload", default=WORKLOAD,
                     help="case timed for the main line (default: the 64x64x16 N=4 bench workload)")
+    ap.add_argument("--layout", default="auto",
+                    help="work layout of the timed stage: auto (the autotuner's choice), "
+                         "columns:LAYERS_PER_CHUNK or blocks:SEGMENTS")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
@@ -502,9 +505,16 @@ def main():
     if args.dissipation:
         mesh.set_dissipation(*(float(x) for x in args.dissipation.split(",")))
     n_dof = mesh.n_dof
-    scratch = torch.empty_like(q0)
-    lpc, tune_ms = api.sem_stage_autotune(mesh, q0, q0.clone(), scratch, prec, reps=5)
-    del scratch
+    if args.layout == "auto":
+        scratch = torch.empty_like(q0)
+        api.sem_stage_autotune(mesh, q0, q0.clone(), scratch, prec, reps=5)
+        del scratch
+    else:
+        kind, par = args.layout.split(":")
+        api.sem_stage_set_layout(mesh, {"columns": api.SEM_LAYOUT_COLUMNS,
+                                        "blocks": api.SEM_LAYOUT_BLOCKS}[kind], int(par))
+    layout, layout_par = api.sem_stage_get_layout(mesh)
+    lpc = api.sem_stage_get_tune(mesh)
     st = Stepper(mesh, q0, case["dt"], prec, graph=not args.no_graph)
     n_steps = max(1, -(-args.steps // 3))       # whole RK3 steps
     n_warm = max(1, -(-args.warmup // 3))
@@ -567,7 +577,11 @@ def main():
         "config": {"workload": args.workload, "N": case["N"], "elements": int(mesh.info["n_elem"]),
                    "n_dof": int(n_dof), "local_points": int(mesh.n_local),
                    "step": "one SSP-RK3 stage (timed as HIP-graph replays of whole RK3 steps)",
-                   "graph": not args.no_graph, "layers_per_chunk": lpc, "finite": ok,
+                   "graph": not args.no_graph,
+                   "layout": ("columns" if layout == api.SEM_LAYOUT_COLUMNS else "blocks"),
+                   "layers_per_chunk" if layout == api.SEM_LAYOUT_COLUMNS else "segments":
+                       lpc if layout == api.SEM_LAYOUT_COLUMNS else layout_par,
+                   "finite": ok,
                    "dissipation": args.dissipation or "off"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
