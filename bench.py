@@ -280,6 +280,48 @@ def adaptive_run(case, device, forecaster=None, rebuild_every=1, recorder=None, 
                        on_boundary=recorder, adapt=adapt)
 
 
+def project_to_level0(mesh, q):
+    """The state projected onto the level-0 columns: finest-level sibling
+    families are merged into their parents, one level at a time, with the
+    library's transfer (the merge is the lumped-mass L2 projection of the four
+    children).  Returns (mesh, state) on a Morton-ordered level-0 layout."""
+    import numpy as np
+    from paper_2410_21607_amd import api
+    from synth import columns as sc
+    cols = np.asarray(mesh.columns)
+    while cols[:, 0].max() > 0:
+        lm = int(cols[:, 0].max())
+        keep = cols[cols[:, 0] < lm]
+        fine = cols[cols[:, 0] == lm]
+        parents = np.unique(np.stack([fine[:, 0] - 1, fine[:, 1] // 2, fine[:, 2] // 2], axis=1), axis=0)
+        cols = sc.morton_sort(np.concatenate([keep, parents]), max(lm - 1, 0))
+        new = mesh.with_columns(cols)
+        out = new.state(device=q.device)
+        api.sem_transfer_apply(api.Transfer(mesh, new), q, out)
+        mesh, q = new, out
+    return mesh, q
+
+
+def projected_error(mesh_a, q_a, mesh_ref, q_ref):
+    """Floor-scaled relative L2 per field (rho', u, v, w, theta'; floors 1e-3
+    kg/m3, 1 m/s, 0.1 K) between two states after both are projected onto
+    the level-0 columns (the same layout, so the same numbering)."""
+    import numpy as np
+    ma, pa = project_to_level0(mesh_a, q_a)
+    mr, pr = project_to_level0(mesh_ref, q_ref)
+    assert np.array_equal(np.asarray(ma.columns), np.asarray(mr.columns))
+    a, b = ma.pack(pa), mr.pack(pr)
+    floors = np.array([1e-3, 1.0, 1.0, 1.0, 0.1])
+    return [float(np.linalg.norm(a[f] - b[f]) / max(np.linalg.norm(b[f]), floors[f] * np.sqrt(a.shape[1])))
+            for f in range(5)]
+
+
+def always_refine(run, plain_elem, plain_col):
+    """Ablation of the forecaster: every column asks to be split."""
+    import torch
+    return torch.ones_like(plain_col)
+
+
 def _summary(run, ref_vmax=None):
     import numpy as np
     v = np.array([b["vmax"] for b in run.log])
@@ -347,15 +389,21 @@ def forecaster_experiment(device, case_name="vortex3_64x64x8_n4", sim_seconds=40
         uni.run(n_steps)
         ref_v = np.array([b["vmax"] for b in uni.log])
         r = {"seed": es, "uniform_finest": _summary(uni)}
-        del uni
         torch.cuda.empty_cache()
         for key, kw in (("plain_amr", {}), ("plain_amr_sparse_rebuilds", {"rebuild_every": horizon}),
-                        ("forecaster_amr", {"forecaster": fc, "rebuild_every": horizon})):
+                        ("forecaster_amr", {"forecaster": fc, "rebuild_every": horizon}),
+                        ("always_refine_sparse_rebuilds", {"forecaster": always_refine,
+                                                           "rebuild_every": horizon})):
             run = adaptive_run(ev, device, **kw)
             run.run(n_steps)
             r[key] = _summary(run, ref_v)
+            # under-resolution at the final time: the state against the uniform
+            # finest run, both projected onto the level-0 columns
+            r[key]["final_error_vs_uniform_l0_projection"] = projected_error(run.mesh, run.q, uni.mesh, uni.q)
             del run
             torch.cuda.empty_cache()
+        del uni
+        torch.cuda.empty_cache()
         if k == 0:
             # held-out skill: the seed's plain run, features at t vs classes at t + horizon
             rec = forecast.Recorder()
@@ -373,13 +421,17 @@ def forecaster_experiment(device, case_name="vortex3_64x64x8_n4", sim_seconds=40
               flush=True)
     res["eval"] = per_seed
     agg = lambda key, sub: [r[key][sub] for r in per_seed]
-    for key in ("plain_amr", "plain_amr_sparse_rebuilds", "forecaster_amr", "uniform_finest"):
+    for key in ("plain_amr", "plain_amr_sparse_rebuilds", "forecaster_amr",
+                "always_refine_sparse_rebuilds", "uniform_finest"):
         res[key] = {"wall_s_mean": float(np.mean(agg(key, "wall_s"))),
                     "rebuilds_mean": float(np.mean(agg(key, "rebuilds"))),
                     "mean_n_dof": float(np.mean(agg(key, "mean_n_dof"))),
                     "mean_split_flag_fraction": float(np.mean(agg(key, "mean_split_flag_fraction")))}
         if key != "uniform_finest":
             res[key]["vmax_max_rel_dev_vs_uniform"] = float(np.max(agg(key, "vmax_max_rel_dev_vs_uniform")))
+            errs = np.array(agg(key, "final_error_vs_uniform_l0_projection"))
+            res[key]["final_error_vs_uniform_l0_projection_mean"] = errs.mean(axis=0).tolist()
+            res[key]["final_error_vs_uniform_l0_projection_max"] = errs.max(axis=0).tolist()
     for k2 in ("speedup_forecaster_over_plain", "speedup_plain_amr_over_uniform",
                "speedup_forecaster_amr_over_uniform"):
         v = [r[k2] for r in per_seed]
@@ -390,39 +442,78 @@ def forecaster_experiment(device, case_name="vortex3_64x64x8_n4", sim_seconds=40
     return res
 
 
-def tstar_study(device, sim_seconds=150.0, max_level=3):
+def tstar_study(device, sim_seconds=60.0, max_level=4, full_uniform_level=3, steer=(10.0, 0.0),
+                l4_steps=4):
     """Normalised time-to-solution T* = T / T(uniform level 0) of uniform
-    meshes at levels 0..max_level and of speed-refined AMR up to each level
-    (thresholds 7.5, 15, 22.5 m/s per level), same simulated time; maximum
-    wind of each AMR run against the uniform run at its finest level."""
+    meshes at levels 0..max_level and of AMR refined by wind speed up to each
+    level (thresholds 7.5, 15, 22.5, 30 m/s for levels 1-4, the paper's set),
+    on a vortex translating with a uniform steering wind, same simulated time.
+    Uniform meshes above `full_uniform_level` are too large to initialise and
+    run for the whole window: their T is the measured time of `l4_steps` RK3
+    steps (HIP-graph replays, the same kernels; the rest state, since the
+    kernel time does not depend on the values) times the window's steps.
+    Maximum wind of each AMR run against the uniform run at its finest level
+    (at the finest fully-run uniform level above that)."""
     import numpy as np
     import torch
+    from paper_2410_21607_amd import api
+    from paper_2410_21607_amd.solver import Stepper
     from synth import cases
-    out = {"workload": "tstar_64x64x8_n4", "sim_seconds": sim_seconds, "runs": {}}
+    out = {"workload": "tstar_64x64x8_n4", "sim_seconds": sim_seconds, "steering_wind": list(steer),
+           "thresholds": [7.5, 15.0, 22.5, 30.0][:max_level], "runs": {}}
     vref, base = {}, None
     for amr in (False, True):
         for lv in range(0 if not amr else 1, max_level + 1):
-            c = cases.get("tstar_64x64x8_n4", level=lv, amr=amr)
+            c = cases.get("tstar_64x64x8_n4", level=lv, amr=amr, steer=steer)
             n = int(round(sim_seconds / c["dt"]))
             n -= n % c["amr"]["interval"]
-            run = adaptive_run(c, device, adapt=amr)
-            run.run(n)
-            torch.cuda.synchronize()
-            v = np.array([b["vmax"] for b in run.log])
             key = ("amr" if amr else "uniform") + f"_L{lv}"
-            rec = {"dt": c["dt"], "steps": n, "wall_s": run.wall(), "rebuilds": run.n_rebuild,
-                   "mean_n_dof": float(np.mean([b["n_dof"] for b in run.log])),
-                   "n_col_start": int(len(c["columns"])), "vmax_final": float(v[-1])}
-            if not amr:
-                vref[lv] = v
-                if lv == 0:
-                    base = rec["wall_s"]
+            if not amr and lv > full_uniform_level:
+                t0 = time.perf_counter()
+                mesh = api.Mesh.from_case(c)
+                _, _, z = mesh.coords()
+                bg = cases.reference_state(c, z)
+                mesh.set_reference(bg["rho0"], bg["theta0"], bg["dtheta0dz"])
+                build_s = time.perf_counter() - t0
+                st = Stepper(mesh, mesh.state(device=device), c["dt"], graph=True)
+                st.step(1)
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                st.step(l4_steps)
+                torch.cuda.synchronize()
+                per_step = (time.perf_counter() - t1) / l4_steps
+                rec = {"dt": c["dt"], "steps": n, "wall_s": per_step * n, "estimated": True,
+                       "measured_steps": l4_steps, "s_per_step": per_step, "mesh_build_s": build_s,
+                       "n_dof": int(mesh.n_dof), "n_col_start": int(len(c["columns"]))}
+                del st, mesh
             else:
-                rec["vmax_max_rel_dev_vs_uniform_same_level"] = float(np.max(np.abs(v - vref[lv]) / vref[lv]))
+                run = adaptive_run(c, device, adapt=amr)
+                run.run(n)
+                torch.cuda.synchronize()
+                v = np.array([b["vmax"] for b in run.log])
+                tb = np.array([b["step"] for b in run.log]) * c["dt"]   # boundary times
+                rec = {"dt": c["dt"], "steps": n, "wall_s": run.wall(), "rebuilds": run.n_rebuild,
+                       "mean_n_dof": float(np.mean([b["n_dof"] for b in run.log])),
+                       "n_col_start": int(len(c["columns"])), "vmax_final": float(v[-1]),
+                       "timings_s": dict(run.timings)}
+                if not amr:
+                    vref[lv] = (tb, v)
+                else:
+                    # compare at the boundaries both runs share (equal simulated times)
+                    ref_lv = min(lv, full_uniform_level)
+                    tr, vr = vref[ref_lv]
+                    common = [(i, j) for i in range(tb.size) for j in range(tr.size)
+                              if abs(tb[i] - tr[j]) < 1e-6 * max(1.0, tr[j])]
+                    ia, ir = (np.array(x) for x in zip(*common))
+                    rec["vmax_reference_uniform_level"] = ref_lv
+                    rec["vmax_compared_at_s"] = tr[ir].tolist()
+                    rec["vmax_max_rel_dev_vs_uniform"] = float(np.max(np.abs(v[ia] - vr[ir]) / vr[ir]))
+                del run
+            if not amr and lv == 0:
+                base = rec["wall_s"]
             rec["T_star"] = rec["wall_s"] / base
             out["runs"][key] = rec
             print(f"  {key}: {rec['wall_s']:.2f} s, T* {rec['T_star']:.2f}", file=sys.stderr, flush=True)
-            del run
             torch.cuda.empty_cache()
     for lv in range(1, max_level + 1):
         out[f"speedup_amr_over_uniform_L{lv}"] = out["runs"][f"uniform_L{lv}"]["wall_s"] / \
@@ -459,6 +550,8 @@ def main():
                          "two-level AMR mesh)")
     ap.add_argument("--tstar-only", action="store_true",
                     help="run only the time-to-solution study (uniform vs AMR by level) and print its JSON")
+    ap.add_argument("--tstar-seconds", type=float, default=60.0,
+                    help="simulated seconds of each run of the time-to-solution study")
     ap.add_argument("--fc-case", default="vortex3_64x64x8_n4")
     ap.add_argument("--fc-seconds", type=float, default=405.0,
                     help="simulated seconds of each forecaster-experiment run")
@@ -490,7 +583,7 @@ def main():
         print(json.dumps(out), flush=True)
         return
     if args.tstar_only:
-        print(json.dumps(tstar_study(dev)), flush=True)
+        print(json.dumps(tstar_study(dev, sim_seconds=args.tstar_seconds)), flush=True)
         return
     if args.forecaster_only:
         print(json.dumps(forecaster_experiment(dev, args.fc_case, args.fc_seconds)), flush=True)

@@ -141,7 +141,9 @@ def get(name, **over):
         thr = [7.5, 15.0, 22.5, 30.0][:max(level, 1)]
         c["amr"] = dict(criterion=0, thresholds=thr, lvl_max=level, interval=100)
         # stable step of the finest level present (vertical spacing limits levels 0-1)
-        c["dt"] = {0: 0.43, 1: 0.43, 2: 0.27, 3: 0.135}[level]
+        c["dt"] = {0: 0.43, 1: 0.43, 2: 0.27, 3: 0.135, 4: 0.0675}[level]
+        # optional uniform steering wind (m/s): the vortex translates
+        c["steer"] = tuple(over.pop("steer", (0.0, 0.0)))
         if amr and level > 0:
             vx = vortex_of(c)
 
