@@ -108,6 +108,57 @@ def measured_traffic(workload=WORKLOAD):
     return t.get("hbm_bytes_per_stage")
 
 
+def traffic_from_counters(fetch_csv, write_csv, workload=WORKLOAD, launches_per_stage=4):
+    """Write profiles/traffic_<workload>.json from two rocprofv3 counter runs
+    of ``bench.py --copy-calibration`` on this workload: ``--pmc FETCH_SIZE``
+    then ``--pmc WRITE_SIZE`` (KiB per dispatch).  Each counter is scaled by
+    what it reads for the calibration kernel (torch's elementwise multiply,
+    which reads and writes one state-sized array of known size); the column
+    kernel's figure is the median per dispatch of its most frequent instance
+    (the one the bench times) times the launches of one stage (four colours on
+    a uniform periodic mesh).  Runs on the host only."""
+    import csv
+    import statistics
+    import numpy as np
+    from paper_2410_21607_amd import api
+    from synth import cases
+    case = cases.get(workload)
+    if int(np.asarray(case["columns"])[:, 0].max()) != 0:
+        raise ValueError("the traffic summary covers uniform meshes only")
+    info = api.sem_mesh_plan(case)[0]
+    calib_bytes = 5 * info["n_h"] * info["ldz"] * 8
+
+    def per_kernel(path, counter):
+        vals = {}
+        with open(path) as fh:
+            for r in csv.DictReader(fh):
+                if r["Counter_Name"] == counter:
+                    vals.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+        return vals
+    fetch, write = per_kernel(fetch_csv, "FETCH_SIZE"), per_kernel(write_csv, "WRITE_SIZE")
+    # the multiply is the most frequent elementwise kernel of such a run
+    calib = [k for k in fetch if "elementwise_kernel" in k and "Unary" in k]
+    cols = [k for k in fetch if "k_stage_columns" in k]
+    if not calib or not cols:
+        raise ValueError("counter files hold no calibration kernel or no column kernel")
+    calib_k = max(calib, key=lambda k: len(fetch[k]))
+    main_k = max(cols, key=lambda k: len(fetch[k]))
+    f_fac = calib_bytes / (statistics.median(fetch[calib_k]) * 1024)
+    w_fac = calib_bytes / (statistics.median(write[calib_k]) * 1024)
+    f_kib, w_kib = statistics.median(fetch[main_k]), statistics.median(write[main_k])
+    per_stage = launches_per_stage * 1024 * (f_kib * f_fac + w_kib * w_fac)
+    out = {"kernel_source_hash": kernel_source_hash(), "kernel": main_k,
+           "launches_per_stage": launches_per_stage, "hbm_bytes_per_stage": per_stage,
+           "fetch_kib_per_launch": f_kib, "write_kib_per_launch": w_kib,
+           "fetch_factor": f_fac, "write_factor": w_fac, "calibration_bytes": calib_bytes,
+           "dispatches": len(fetch[main_k]),
+           "source": f"profiles/fused_stage_{workload}.md"}
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    with open(path, "w") as fh:
+        json.dump(out, fh, indent=1)
+    return out
+
+
 def prepare(case_name, device):
     import torch  # noqa: F401
     from paper_2410_21607_amd import api
@@ -557,7 +608,14 @@ def main():
                     help="simulated seconds of each forecaster-experiment run")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run plain device copies of the state size (counter calibration)")
+    ap.add_argument("--traffic-from", default="",
+                    help="FETCH_CSV,WRITE_CSV: write profiles/traffic_<workload>.json from the "
+                         "counter files of two rocprofv3 --pmc runs (host only, no GPU) and exit")
     args = ap.parse_args()
+    if args.traffic_from:
+        fetch_csv, write_csv = args.traffic_from.split(",")
+        print(json.dumps(traffic_from_counters(fetch_csv, write_csv, args.workload)), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU column "
               "partition is a design, not part of this build", file=sys.stderr)

@@ -166,9 +166,12 @@ int sem_mesh_set_reference(sem_mesh *mesh, const double *h_rho0,
  * terms) and assembled with the same direct stiffness summation.  With
  * terrain set (sem_mesh_set_terrain) the derivatives are the physical ones
  * (chain rule of the mapping) and z is each node's physical height.  In
- * sem_stage they run as a pre-pass whose assembled tendency the column pass
- * adds.  Enabling allocates the pre-pass buffers once (5 element-local and 2
- * state arrays); compute calls never allocate.  Synchronises the device.
+ * sem_stage at SEM_FP64 on meshes without terrain in the column layout the
+ * terms are computed inside the column passes (the element stress in LDS);
+ * otherwise (terrain, SEM_FP32, the block layout) they run as a pre-pass
+ * whose assembled tendency the column pass adds.  Enabling allocates the
+ * pre-pass buffers once (5 element-local and 2 state arrays); compute calls
+ * never allocate.  Synchronises the device.
  * Compute calls read the settings when they are enqueued: a HIP graph
  * captured before this call keeps replaying the previous ones. */
 int sem_mesh_set_dissipation(sem_mesh *mesh, double Cs, double sponge_gamma,

@@ -1032,7 +1032,9 @@ int sem_stage(const sem_mesh* M, double a, double b, double c, const double* qn,
     if (!qn || !qs || !qout) return fail(SEM_ERR_ARG, "null array");
     if (qout == qs || qout == qn) return fail(SEM_ERR_ARG, "qout must not alias qs or qn");
     if (prec != SEM_FP64 && prec != SEM_FP32) return fail(SEM_ERR_ARG, "bad precision");
-    if (dissipation_on(M) && (rc = dissip_prepass(M, qs, (hipStream_t)stream)) != SEM_OK) return rc;
+    if (dissipation_on(M) && !sem::fused_dissipation_inline(M->d, M->fused, prec) &&
+        (rc = dissip_prepass(M, qs, (hipStream_t)stream)) != SEM_OK)
+        return rc;
     rc = sem::fused_stage_launch(M->d, M->fused, a, b, c, qn, qs, qout, prec, (hipStream_t)stream);
     if (rc != SEM_OK) return fail(rc, "fused stage launch failed");
     return SEM_OK;

@@ -95,6 +95,10 @@ void fused_plan_free(FusedPlan& plan);
 bool fused_lpc_supported(int N, int layers_per_chunk);
 bool fused_blocks_supported(const HostMesh& H);
 
+// Whether sem_stage evaluates the optional dissipation inside the column
+// kernel (FP64, box elements, column layout) instead of a pre-pass.
+bool fused_dissipation_inline(const DevMesh& m, const FusedPlan& plan, int precision);
+
 // Launches the column kernel and the shared-node kernel on `stream`.
 int fused_stage_launch(const DevMesh& m, const FusedPlan& plan, double a, double b, double c,
                        const double* qn, const double* qs, double* qout, int precision,

@@ -71,7 +71,10 @@ __device__ __forceinline__ double pow1p_minus1(const DevMesh& m, double x) {
 }
 
 // At least four waves per SIMD: two workgroups share a CU, so that one can
-// compute while the other waits on memory.  Within a workgroup the global
+// compute while the other waits on memory.  The instance with the sub-grid
+// stress (DISS) needs about 155 VGPRs: held to 128 it spilled some 40 of them
+// and ran 15% slower than with the bound relaxed to two waves (it then
+// runs at three).  Within a workgroup the global
 // loads of a chunk are issued one phase early: while the derivatives of chunk
 // ch run, the update base of its nodes, the next chunk's q_s (direct nodes)
 // and the next chunk's slice of the per-level tables are already in flight.
@@ -87,8 +90,8 @@ __device__ __forceinline__ double pow1p_minus1(const DevMesh& m, double x) {
 // factor, hanging positions through their rows) and the vertical one.
 // Hanging positions take the coarse face's interpolant of zs and of the
 // reference state (host tables), so the mesh stays watertight.
-template <int NP, int LPC, typename T, bool TER>
-__global__ void __launch_bounds__(((NP * NP * (LPC * (NP - 1) + 1) + 63) / 64) * 64, 4)
+template <int NP, int LPC, typename T, bool TER, bool DISS>
+__global__ void __launch_bounds__(((NP * NP * (LPC * (NP - 1) + 1) + 63) / 64) * 64, DISS ? 2 : 4)
 k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double b, double c,
                 const double* __restrict__ qn, const double* __restrict__ qs,
                 double* __restrict__ qo) {
@@ -111,6 +114,10 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
     // 2/dz of its LPC layers
     constexpr int SL = 6 * NK + 2 * LPC;
     __shared__ double slice[2][SL];
+    // DISS: the sub-grid stress 2 nu (S_xx, S_xy, S_yy, S_xz, S_yz) of every
+    // element of the chunk at its nodes, [component][position][element][k]
+    constexpr int TAU = DISS ? NP2 * LPC * NP : 1;
+    __shared__ double stau[DISS ? 5 : 1][TAU];
     const int tid = threadIdx.x;
     for (int t = tid; t < NP2; t += WGT) sD[t] = T(m.D[t]);
     for (int t = tid; t < NP2 * NP; t += WGT) {
@@ -344,6 +351,8 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
                 for (int f = 0; f < NF; ++f) pf[f] = qs[f * fs + o];
             }
         }
+        double acc[NF] = {0, 0, 0, 0, 0};
+        // derivatives and the node's contribution (acc) from the elements of the chunk
         if (active) {
             // d/dx of tiles tx, tx2 and d/dy of tiles ty, ty2 at this node.  The
             // empty asm pins the results before the next fields' LDS reads may
@@ -393,12 +402,15 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
             const T f = T(m.f), gr = T(m.g);
             // the parts of R without z derivatives
             T Rh[NF], ax, ay, bx, by;
+            double gxy[6] = {0, 0, 0, 0, 0, 0};   // DISS: du/dx, du/dy, dv/dx, dv/dy, dw/dx, dw/dy
             dxy(0, 1, 3, 3, ax, ay, bx, by);
             Rh[0] = -(ax + ay);
             Rh[1] = -(u * bx + v * by) + f * v;
+            if constexpr (DISS) { gxy[0] = bx; gxy[1] = by; }
             dxyp(0, ax, ay, bx, by);
             Rh[2] = -(u * ax + v * ay) - f * u;
             Rh[3] = -(u * bx + v * by) - T(qv[0]) * inv_rho * gr;
+            if constexpr (DISS) { gxy[2] = ax; gxy[3] = ay; gxy[4] = bx; gxy[5] = by; }
             dxyp(1, bx, by, ax, ay);
             Rh[1] -= bx * inv_rho;
             Rh[2] -= by * inv_rho;
@@ -415,7 +427,6 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
                 a_y = T(-tf * s_ter[2][pc]);
                 wt = u * a_x + v * a_y + w * gs;
             }
-            double acc[NF] = {0, 0, 0, 0, 0};
             // elements of this chunk holding the node: (element, local k)
             const bool inner_plane = (kzl % N == 0) && kzl > 0 && kzl < nk - 1;
             const int e_first = (kzl == nk - 1) ? (kzl - 1) / N : (inner_plane ? kzl / N - 1 : kzl / N);
@@ -470,8 +481,29 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
                     ddz(2, 3, z0, z1);
                     R[0] = Rh[0] - z0;
                     R[1] = Rh[1] - w * z1;
+                    double guz = 0.0;
+                    if constexpr (DISS) guz = z1;
                     ddzp(0, z0, z1);
                     R[2] = Rh[2] - w * z0;
+                    if constexpr (DISS) {
+                        // the element's strain (Section 5, sub-grid model):
+                        // S = (grad u + grad u^T)/2, nu = (Cs Delta)^2 sqrt(2 S:S),
+                        // Delta = (dx + dy)/(2N); the stress 2 nu S goes to LDS
+                        const double sxx = gxy[0], syy = gxy[3], szz = z1;
+                        const double sxy = 0.5 * (gxy[1] + gxy[2]);
+                        const double sxz = 0.5 * (guz + gxy[4]);
+                        const double syz = 0.5 * (double(z0) + gxy[5]);
+                        const double ss = sxx * sxx + syy * syy + szz * szz +
+                                          2.0 * (sxy * sxy + sxz * sxz + syz * syz);
+                        const double cd = m.cs * (dxc + dyc) / (2.0 * N);
+                        const double two_nu = 2.0 * cd * cd * sqrt(2.0 * ss);
+                        const int ti = pc * (LPC * NP) + el * NP + kk;
+                        stau[0][ti] = two_nu * sxx;
+                        stau[1][ti] = two_nu * sxy;
+                        stau[2][ti] = two_nu * syy;
+                        stau[3][ti] = two_nu * sxz;
+                        stau[4][ti] = two_nu * syz;
+                    }
                     T z2, z3;
                     ddzp(1, z2, z3);
                     R[3] = Rh[3] - w * z1 - z2 * inv_rho;
@@ -480,7 +512,51 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
                 const double mass = s_mij[pc] * sW[kk] * dzl;
 #pragma unroll
                 for (int fl = 0; fl < NF; ++fl) acc[fl] += mass * double(R[fl]);
+                if constexpr (DISS) {
+                    // absorbing layer: -R(z) q' for every field
+                    if (m.sponge) {
+                        const double rz = m.sponge[kz] * mass;
+#pragma unroll
+                        for (int fl = 0; fl < NF; ++fl) acc[fl] -= rz * qv[fl];
+                    }
+                }
             }
+        }
+        // DISS: horizontal divergence of each element's stress at the node,
+        // once every node has written its elements' entries of the stress tile
+        if constexpr (DISS) {
+            __syncthreads();
+            if (active && m.cs > 0.0) {
+                const bool inner_plane = (kzl % N == 0) && kzl > 0 && kzl < nk - 1;
+                const int e_first = (kzl == nk - 1) ? (kzl - 1) / N : (inner_plane ? kzl / N - 1 : kzl / N);
+                const int n_el = inner_plane ? 2 : 1;
+                for (int s2 = 0; s2 < n_el; ++s2) {
+                    const int el = e_first + s2;
+                    const int kk = kzl - el * N;
+                    const double mass = s_mij[pc] * sW[kk] * sb[6 * NK + el];
+                    const int tx0 = (j * NP) * (LPC * NP) + el * NP + kk;
+                    const int ty0 = i * (LPC * NP) + el * NP + kk;
+                    double dx[3] = {0, 0, 0}, dy[3] = {0, 0, 0};
+#pragma unroll
+                    for (int mm = 0; mm < NP; ++mm) {
+                        const T2 cxy = Dxy[mm];
+                        const int ox = tx0 + mm * (LPC * NP), oy = ty0 + mm * NP * (LPC * NP);
+                        dx[0] += double(cxy.x) * stau[0][ox];   // d/dx S_xx
+                        dx[1] += double(cxy.x) * stau[1][ox];   // d/dx S_xy
+                        dx[2] += double(cxy.x) * stau[3][ox];   // d/dx S_xz
+                        dy[0] += double(cxy.y) * stau[1][oy];   // d/dy S_xy
+                        dy[1] += double(cxy.y) * stau[2][oy];   // d/dy S_yy
+                        dy[2] += double(cxy.y) * stau[4][oy];   // d/dy S_yz
+                    }
+                    const double sxd = double(sx), syd = double(sy);
+                    acc[1] += mass * (dx[0] * sxd + dy[0] * syd);
+                    acc[2] += mass * (dx[1] * sxd + dy[1] * syd);
+                    acc[3] += mass * (dx[2] * sxd + dy[2] * syd);
+                }
+            }
+        }
+        // the carry of the chunk's top plane, or the node's update
+        if (active) {
             if (kzl == nk - 1 && L1 < m.n_z) {
                 // top plane of the chunk: finished by the next chunk
 #pragma unroll
@@ -1027,13 +1103,13 @@ __global__ void k_stage_tail(DevMesh m, TailTables tl, double a, double b, doubl
     X(7, 1) X(7, 2)                 \
     X(8, 1)
 
-template <typename T, bool TER>
+template <typename T, bool TER, bool DISS = false>
 int launch_t(const DevMesh& m, const FusedTables& t, int col0, int ncol, double a, double b,
              double c, const double* qn, const double* qs, double* qo, hipStream_t s) {
     switch (m.N * 32 + t.layers_per_chunk) {
 #define CASE(NN, LP)                                                                    \
     case NN * 32 + LP:                                                                  \
-        hipLaunchKernelGGL((k_stage_columns<NN + 1, LP, T, TER>), dim3(ncol),           \
+        hipLaunchKernelGGL((k_stage_columns<NN + 1, LP, T, TER, DISS>), dim3(ncol),     \
                            dim3(wg_threads<NN + 1, LP>()), 0, s, m, t, col0, ncol, a, b, \
                            c, qn, qs, qo);                                              \
         break;
@@ -1418,9 +1494,18 @@ int launch_blocks(const DevMesh& m, const BlockTables& bt, int b0, int nblk, int
     return (hipGetLastError() == hipSuccess) ? SEM_OK : SEM_ERR_HIP;
 }
 
-int fused_stage_launch(const DevMesh& m, const FusedPlan& P, double a, double b, double c,
+bool fused_dissipation_inline(const DevMesh& m, const FusedPlan& P, int prec) {
+    return (m.cs > 0.0 || m.sponge) && !m.zs && prec == SEM_FP64 && P.layout == SEM_LAYOUT_COLUMNS;
+}
+
+int fused_stage_launch(const DevMesh& m_in, const FusedPlan& P, double a, double b, double c,
                        const double* qn, const double* qs, double* qo, int prec, hipStream_t s) {
     const bool f32 = prec == SEM_FP32;
+    // the optional dissipation inside the column kernel (FP64, box
+    // elements): no pre-pass tendency is added
+    const bool diss = fused_dissipation_inline(m_in, P, prec);
+    DevMesh m = m_in;
+    if (diss) m.rx = nullptr;
     if (P.layout == SEM_LAYOUT_BLOCKS && !m.zs) {
         // colour by colour: the colour's blocks, even segments then odd
         // ones, then its columns in no block
@@ -1451,6 +1536,8 @@ int fused_stage_launch(const DevMesh& m, const FusedPlan& P, double a, double b,
             if (m.zs) {
                 rc = f32 ? launch_t<float, true>(m, t, col0, ncol, a, b, c, qn, qs, qo, s)
                          : launch_t<double, true>(m, t, col0, ncol, a, b, c, qn, qs, qo, s);
+            } else if (diss) {
+                rc = launch_t<double, false, true>(m, t, col0, ncol, a, b, c, qn, qs, qo, s);
             } else {
                 rc = f32 ? launch_t<float, false>(m, t, col0, ncol, a, b, c, qn, qs, qo, s)
                          : launch_t<double, false>(m, t, col0, ncol, a, b, c, qn, qs, qo, s);

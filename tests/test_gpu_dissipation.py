@@ -1,7 +1,9 @@
 """GPU parity of the optional dissipation (horizontal Smagorinsky-Lilly and
 the Rayleigh absorbing layer) against the oracle: the unfused right-hand
-side (sem_rhs + sem_dss), the fused stage over three stages, and switching
-the terms off again."""
+side (sem_rhs + sem_dss), the fused stage over three stages and its
+right-hand side alone in the column layout (the terms inside the column
+kernel) and the block layout (a separate pre-pass), and switching the terms
+off again."""
 
 import sys
 
@@ -59,7 +61,7 @@ def gpu_rhs(gm, qg):
                                      ("small_amr2", {"N": 7})])
 def test_dissipation_matches_oracle(name, kw):
     import torch
-    from paper_2410_21607_amd import api
+    from paper_2410_21607_amd import api, native
     c, gm, om, perm, q = setup(name, **kw)
     say("dissipation", name, kw)
     ref = oracle_reference_local(c, om)
@@ -82,20 +84,48 @@ def test_dissipation_matches_oracle(name, kw):
     say("  rhs rel", err, "dissipation part rel", err_d, "scale", np.abs(dd).max(axis=1))
     assert np.abs(dd[1]).max() > 0 and np.abs(dd[0]).max() > 0
     assert err.max() <= 1e-12 and err_d.max() <= 1e-9
-    # fused stage, three stages
+    # fused stage, three stages, in each work layout the mesh supports: the
+    # column layout computes the terms inside the column kernel, the block
+    # layout adds the tendency of a separate pre-pass
     f = lambda s: assembly.rhs(om, s, ref, phys)
     want, _ = timestep.run_stages(f, q, c["dt"], 3)
-    qs, o = qg.clone(), torch.zeros_like(qg)
-    for s in range(3):
-        a, b, cc = timestep.stage_coefficients(s, c["dt"])
-        api.sem_stage(gm, a, b, cc, qg, qs, o, api.SEM_FP64)
-        qs, o = o, qs
-    torch.cuda.synchronize()
-    got = np.empty_like(q)
-    got[:, perm] = gm.pack(qs)
-    err = metrics.rel_l2(got, want, metrics.STATE_FLOORS)
-    say("  3 stages rel", err)
-    assert err.max() <= 1e-12
-    # switched off again: the inviscid right-hand side, bit for bit
+    fused_on = {}
+    for lay in ((api.SEM_LAYOUT_COLUMNS, 2), (api.SEM_LAYOUT_BLOCKS, 1)):
+        try:
+            api.sem_stage_set_layout(gm, *lay)
+        except native.SemError:
+            say("  layout", lay, "not supported on this mesh")
+            continue
+        qs, o = qg.clone(), torch.zeros_like(qg)
+        for s in range(3):
+            a, b, cc = timestep.stage_coefficients(s, c["dt"])
+            api.sem_stage(gm, a, b, cc, qg, qs, o, api.SEM_FP64)
+            qs, o = o, qs
+        torch.cuda.synchronize()
+        got = np.empty_like(q)
+        got[:, perm] = gm.pack(qs)
+        err = metrics.rel_l2(got, want, metrics.STATE_FLOORS)
+        say("  layout", lay, "3 stages rel", err)
+        assert err.max() <= 1e-12
+        # the fused right-hand side alone (a = b = 0, c = 1)
+        o = torch.zeros_like(qg)
+        api.sem_stage(gm, 0.0, 0.0, 1.0, qg, qg, o, api.SEM_FP64)
+        torch.cuda.synchronize()
+        fused_on[lay] = o
+    # the dissipation part of the fused right-hand side (on minus off)
     gm.set_dissipation(0.0, 0.0, DEPTH)
+    for lay, o_on in fused_on.items():
+        api.sem_stage_set_layout(gm, *lay)
+        o_off = torch.zeros_like(qg)
+        api.sem_stage(gm, 0.0, 0.0, 1.0, qg, qg, o_off, api.SEM_FP64)
+        torch.cuda.synchronize()
+        g_on = np.empty_like(q)
+        g_on[:, perm] = gm.pack(o_on)
+        g_off = np.empty_like(q)
+        g_off[:, perm] = gm.pack(o_off)
+        e_on = metrics.rel_l2(g_on, want_on, metrics.RHS_FLOORS)
+        e_d = metrics.rel_l2(g_on - g_off, dd, floors)
+        say("  layout", lay, "fused rhs rel", e_on, "dissipation part rel", e_d)
+        assert e_on.max() <= 1e-12 and e_d.max() <= 1e-9
+    # switched off again: the inviscid right-hand side, bit for bit
     assert torch.equal(gpu_rhs(gm, qg), r_off)
