@@ -34,6 +34,15 @@ from . import api
 from .solver import Stepper
 
 
+def _same_layout(a, b):
+    """True when two column layouts hold the same (level, ix, iy) set."""
+    a, b = np.asarray(a, np.int64), np.asarray(b, np.int64)
+    if a.shape != b.shape:
+        return False
+    rows = lambda c: c[np.lexsort((c[:, 2], c[:, 1], c[:, 0]))]
+    return bool(np.array_equal(rows(a), rows(b)))
+
+
 class AdaptiveRun:
     def __init__(self, mesh, q0, dt, reference, criterion, thresholds, lvl_max,
                  interval, precision=api.SEM_FP64, graph=True, layers_per_chunk=0,
@@ -133,8 +142,7 @@ class AdaptiveRun:
         cols = api.sem_adapt_columns(self.mesh, self.mesh.columns, flags, self.lvl_max)
         t2 = time.perf_counter()
         self.timings["layout"] += t2 - t1
-        if len(cols) == len(self.mesh.columns) and \
-                {tuple(c) for c in cols.tolist()} == {tuple(c) for c in self.mesh.columns.tolist()}:
+        if _same_layout(cols, self.mesh.columns):
             return False
         new = self.mesh.with_columns(cols)
         new.set_reference(*self.reference)

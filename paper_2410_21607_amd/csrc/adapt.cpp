@@ -251,10 +251,14 @@ struct RowAcc {
         if (w != 0.0) e.push_back({s, w});
     }
     void finish(double scale, TransferRows& T) {
-        std::stable_sort(e.begin(), e.end(),
-                         [](const std::pair<int32_t, double>& a, const std::pair<int32_t, double>& b) {
-                             return a.first < b.first;
-                         });
+        // stable insertion sort by source (rows hold a few dozen entries at
+        // most; most rows of an unchanged column hold one)
+        for (size_t k = 1; k < e.size(); ++k) {
+            const std::pair<int32_t, double> v = e[k];
+            size_t q = k;
+            for (; q > 0 && e[q - 1].first > v.first; --q) e[q] = e[q - 1];
+            e[q] = v;
+        }
         size_t i = 0;
         while (i < e.size()) {
             double s = 0.0;
@@ -339,8 +343,11 @@ int build_transfer(const HostMesh& A, const HostMesh& B, TransferRows& T, std::s
         for (int r = A.hang_ptr[hh]; r < A.hang_ptr[hh + 1]; ++r) acc.add(A.hang_src[r], wt * A.hang_w[r]);
     };
     T.ptr.assign(1, 0);
+    T.ptr.reserve(size_t(B.n_h) + 1);
     T.src.clear();
     T.w.clear();
+    T.src.reserve(size_t(B.n_h) * 2);
+    T.w.reserve(size_t(B.n_h) * 2);
     RowAcc acc;
     for (int64_t h = 0; h < B.n_h; ++h) {
         int pick = -1;   // a SAME slot first, else a CHILD slot

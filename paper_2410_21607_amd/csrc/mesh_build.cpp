@@ -180,12 +180,13 @@ using Row = std::vector<std::pair<int32_t, double>>;
 
 // Open-addressing table from a pair of non-negative 64-bit keys to int32
 // (linear probing, load factor at most 1/2, no erase, one entry per probe):
-// the numbering of ~10^5 positions needs no node allocation per entry.
+// the numbering of ~10^6 positions needs no node allocation per entry.  The
+// table starts at twice the expected size and doubles when half full.
 class PairTable {
   public:
-    explicit PairTable(size_t n_max) {
+    explicit PairTable(size_t n_expected) {
         size_t cap = 16;
-        while (cap < 2 * n_max + 2) cap <<= 1;
+        while (cap < 2 * n_expected + 2) cap <<= 1;
         e_.assign(cap, Entry{-1, 0, 0});
         mask_ = cap - 1;
     }
@@ -199,6 +200,7 @@ class PairTable {
     }
     // value of (a, b); inserts v (and sets inserted) when absent
     int32_t find_or_insert(int64_t a, int64_t b, int32_t v, bool& inserted) {
+        if (2 * (size_ + 1) > mask_ + 1) grow();
         for (size_t i = slot(a, b);; i = (i + 1) & mask_) {
             Entry& e = e_[i];
             if (e.a < 0) {
@@ -225,6 +227,17 @@ class PairTable {
         int64_t a, b;
         int32_t v;
     };
+    void grow() {
+        std::vector<Entry> old(2 * (mask_ + 1), Entry{-1, 0, 0});
+        old.swap(e_);
+        mask_ = e_.size() - 1;
+        for (const Entry& e : old) {
+            if (e.a < 0) continue;
+            size_t i = slot(e.a, e.b);
+            while (e_[i].a >= 0) i = (i + 1) & mask_;
+            e_[i] = e;
+        }
+    }
     size_t slot(int64_t a, int64_t b) const {
         uint64_t h = uint64_t(a) * 0x9E3779B97F4A7C15ull;
         h ^= uint64_t(b) + 0x632BE59BD9B4E019ull + (h << 6) + (h >> 2);
@@ -292,6 +305,10 @@ int build_host_mesh(const MeshInput& in, HostMesh& m, std::string& err) {
     }
     for (auto o : owner)
         if (o < 0) { err = "columns do not cover the domain"; return SEM_ERR_MESH; }
+    // the finest cells around each column (edges and corners): 2:1 balance,
+    // and whether a coarser column touches the column at all (only then can
+    // one of its boundary nodes hang)
+    std::vector<char> has_coarser(size_t(in.n_col), 0);
     for (int c = 0; c < in.n_col; ++c) {
         int l = in.lev[c];
         int64_t s = int64_t(1) << (L - l);
@@ -305,6 +322,7 @@ int build_host_mesh(const MeshInput& in, HostMesh& m, std::string& err) {
                 else if (fy < 0 || fy >= nyf) continue;
                 int lo = in.lev[owner[size_t(fx * nyf + fy)]];
                 if (std::abs(lo - l) > 1) { err = "2:1 balance violated"; return SEM_ERR_MESH; }
+                if (lo < l) has_coarser[c] = 1;
             }
     }
     // ---- column geometry
@@ -371,13 +389,15 @@ int build_host_mesh(const MeshInput& in, HostMesh& m, std::string& err) {
     std::vector<double> src_sx(size_t(in.n_col) * np2, 0.0), src_sy(size_t(in.n_col) * np2, 0.0);
     for (int c = 0; c < in.n_col; ++c) {
         int l = in.lev[c];
-        if (l == 0) continue;
+        // a coarser column holding one of c's boundary nodes owns a finest
+        // cell next to c; by the 2:1 balance it is one level coarser
+        if (l == 0 || !has_coarser[c]) continue;
         for (int j = 0; j < np1; ++j)
             for (int i = 0; i < np1; ++i) {
                 if (i != 0 && i != N && j != 0 && j != N) continue;
                 int64_t kx = kx_of(c, i), ky = ky_of(c, j);
                 bool found = false;
-                for (int lc = 0; lc < l && !found; ++lc) {
+                for (int lc = l - 1; lc < l && !found; ++lc) {
                     int64_t cxs[2], cys[2];
                     int nxc = ax.candidates(kx, lc, cxs), nyc = ay.candidates(ky, lc, cys);
                     for (int a = 0; a < nxc && !found; ++a)
@@ -433,7 +453,9 @@ int build_host_mesh(const MeshInput& in, HostMesh& m, std::string& err) {
     // (4N per column) go through the table.
     size_t n_hang_slots = 0;
     for (int32_t sc : src_col) n_hang_slots += sc >= 0;
-    PairTable hid(size_t(in.n_col) * size_t(4 * N)), hhid(n_hang_slots);
+    // boundary positions are shared by two or more columns on conforming
+    // faces: expect about half as many as column slots on the boundary
+    PairTable hid(size_t(in.n_col) * size_t(2 * N)), hhid(n_hang_slots);
     int32_t n_unique = 0;
     m.gmap.assign(size_t(in.n_col) * np2, 0);
     std::vector<size_t> hh_first;   // (c, pos) slot that defined each hanging point
