@@ -108,7 +108,7 @@ def measured_traffic(workload=WORKLOAD):
     return t.get("hbm_bytes_per_stage")
 
 
-def traffic_from_counters(fetch_csv, write_csv, workload=WORKLOAD, launches_per_stage=4):
+def traffic_from_counters(fetch_csv, write_csv, workload=WORKLOAD, launches_per_stage=4, out_dir=None):
     """Write profiles/traffic_<workload>.json from two rocprofv3 counter runs
     of ``bench.py --copy-calibration`` on this workload: ``--pmc FETCH_SIZE``
     then ``--pmc WRITE_SIZE`` (KiB per dispatch).  Each counter is scaled by
@@ -153,7 +153,7 @@ def traffic_from_counters(fetch_csv, write_csv, workload=WORKLOAD, launches_per_
            "fetch_factor": f_fac, "write_factor": w_fac, "calibration_bytes": calib_bytes,
            "dispatches": len(fetch[main_k]),
            "source": f"profiles/fused_stage_{workload}.md"}
-    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    path = os.path.join(out_dir or os.path.join(ROOT, "profiles"), f"traffic_{workload}.json")
     with open(path, "w") as fh:
         json.dump(out, fh, indent=1)
     return out

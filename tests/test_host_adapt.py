@@ -185,3 +185,21 @@ def test_forecast_labels_reject_mismatched_layouts():
     q = dict(p, nx0=5)
     with pytest.raises(native.SemError):
         api.sem_forecast_labels(q, sc.uniform(5, 4), a, np.zeros(len(a) * 2, np.int8))
+
+
+def test_same_layout_compares_column_sets():
+    """The adaptive loop's unchanged-layout check: the same (level, ix, iy)
+    set in any order is the same layout; one column more, or one index
+    changed, is not."""
+    from paper_2410_21607_amd.adaptive import _same_layout
+    a = np.asarray(random_layout(5, 4, 4, 3), dtype=np.int32)
+    perm = np.random.default_rng(1).permutation(len(a))
+    assert _same_layout(a, a[perm])
+    assert not _same_layout(a, a[:-1])
+    b = a.copy()
+    b[len(b) // 2, 2] += 1
+    assert not _same_layout(a, b)
+    c = a.copy()
+    c[[0, 1]] = c[[1, 0]]
+    c[0, 0], c[1, 0] = c[1, 0], c[0, 0]   # swap levels only: a different set unless equal
+    assert _same_layout(a, c) == (set(map(tuple, a.tolist())) == set(map(tuple, c.tolist())))
