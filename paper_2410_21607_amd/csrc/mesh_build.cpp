@@ -19,7 +19,9 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <map>
+#include <thread>
 #include <unordered_map>
 #include <utility>
 
@@ -248,6 +250,50 @@ class PairTable {
     size_t mask_ = 0, size_ = 0;
 };
 
+// Worker threads for the host build: SEM_HOST_THREADS when set (for any
+// mesh size); else the process's CPU share as the OpenMP convention states
+// it (OMP_NUM_THREADS) when set, else the hardware count, at most 32, and
+// one thread for small meshes.  The tables do not depend on the count.
+int host_threads(size_t work) {
+    if (const char* e = std::getenv("SEM_HOST_THREADS")) {
+        const int v = std::atoi(e);
+        if (v > 0) return std::min(v, 32);
+    }
+    if (work < (size_t(1) << 16)) return 1;
+    int n = int(std::thread::hardware_concurrency());
+    if (const char* e = std::getenv("OMP_NUM_THREADS")) {
+        const int v = std::atoi(e);
+        if (v > 0) n = v;
+    }
+    return std::max(1, std::min(n, 32));
+}
+
+// f(begin, end, t) over T contiguous ranges of [0, n), one thread each
+template <typename F>
+void parallel_ranges(size_t n, int T, F f) {
+    if (T <= 1) {
+        f(size_t(0), n, 0);
+        return;
+    }
+    std::vector<std::thread> th;
+    th.reserve(size_t(T));
+    for (int t = 0; t < T; ++t) {
+        const size_t b = n * size_t(t) / size_t(T), e = n * size_t(t + 1) / size_t(T);
+        th.emplace_back([b, e, t, &f] { f(b, e, t); });
+    }
+    for (auto& x : th) x.join();
+}
+
+// bucket of a position key (a mix independent of the tables' slot hash)
+inline int key_bucket(int64_t a, int64_t b, int P) {
+    uint64_t h = uint64_t(a) ^ ((uint64_t(b) << 32) | (uint64_t(b) >> 32));
+    h += 0x9E3779B97F4A7C15ull;
+    h = (h ^ (h >> 30)) * 0xBF58476D1CE4E5B9ull;
+    h = (h ^ (h >> 27)) * 0x94D049BB133111EBull;
+    h ^= h >> 31;
+    return int((h >> 32) % uint64_t(P));
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------ build
@@ -309,22 +355,32 @@ int build_host_mesh(const MeshInput& in, HostMesh& m, std::string& err) {
     // and whether a coarser column touches the column at all (only then can
     // one of its boundary nodes hang)
     std::vector<char> has_coarser(size_t(in.n_col), 0);
-    for (int c = 0; c < in.n_col; ++c) {
-        int l = in.lev[c];
-        int64_t s = int64_t(1) << (L - l);
-        for (int64_t a = -1; a <= s; ++a)
-            for (int64_t b = -1; b <= s; ++b) {
-                if (a >= 0 && a < s && b >= 0 && b < s) continue;
+    std::vector<char> unbalanced(size_t(in.n_col), 0);
+    parallel_ranges(size_t(in.n_col), host_threads(owner.size()), [&](size_t c0, size_t c1, int) {
+        for (size_t c = c0; c < c1; ++c) {
+            const int l = in.lev[c];
+            const int64_t s = int64_t(1) << (L - l);
+            // the ring of finest cells just outside the column, side by side
+            for (int64_t r = 0; r < 4 * (s + 1); ++r) {
+                const int64_t side = r / (s + 1), k = r % (s + 1);
+                int64_t a, b;
+                if (side == 0) { a = k - 1; b = -1; }          // south, from the corner (-1, -1)
+                else if (side == 1) { a = s; b = k - 1; }     // east
+                else if (side == 2) { a = s - k; b = s; }      // north
+                else { a = -1; b = s - k; }                    // west
                 int64_t fx = in.ix[c] * s + a, fy = in.iy[c] * s + b;
                 if (in.periodic_x) fx = ((fx % nxf) + nxf) % nxf;
                 else if (fx < 0 || fx >= nxf) continue;
                 if (in.periodic_y) fy = ((fy % nyf) + nyf) % nyf;
                 else if (fy < 0 || fy >= nyf) continue;
-                int lo = in.lev[owner[size_t(fx * nyf + fy)]];
-                if (std::abs(lo - l) > 1) { err = "2:1 balance violated"; return SEM_ERR_MESH; }
+                const int lo = in.lev[owner[size_t(fx * nyf + fy)]];
+                if (std::abs(lo - l) > 1) unbalanced[c] = 1;
                 if (lo < l) has_coarser[c] = 1;
             }
-    }
+        }
+    });
+    for (char u : unbalanced)
+        if (u) { err = "2:1 balance violated"; return SEM_ERR_MESH; }
     // ---- column geometry
     m.col_dx.resize(in.n_col); m.col_dy.resize(in.n_col);
     m.col_x0.resize(in.n_col); m.col_y0.resize(in.n_col);
@@ -387,7 +443,9 @@ int build_host_mesh(const MeshInput& in, HostMesh& m, std::string& err) {
     // source column (or -1) and reference coords for every (c, pos)
     std::vector<int32_t> src_col(size_t(in.n_col) * np2, -1);
     std::vector<double> src_sx(size_t(in.n_col) * np2, 0.0), src_sy(size_t(in.n_col) * np2, 0.0);
-    for (int c = 0; c < in.n_col; ++c) {
+    // columns are independent here (each writes its own slots)
+    parallel_ranges(size_t(in.n_col), host_threads(size_t(in.n_col) * np2), [&](size_t c0, size_t c1, int) {
+    for (int c = int(c0); c < int(c1); ++c) {
         int l = in.lev[c];
         // a coarser column holding one of c's boundary nodes owns a finest
         // cell next to c; by the 2:1 balance it is one level coarser
@@ -425,6 +483,7 @@ int build_host_mesh(const MeshInput& in, HostMesh& m, std::string& err) {
                 }
             }
     }
+    });
     // ---- column blocks (2 x 2 squares of leaf columns of one level)
     m.col_block.assign(size_t(in.n_col), -1);
     for (int c = 0; c < in.n_col; ++c) {
@@ -451,66 +510,153 @@ int build_host_mesh(const MeshInput& in, HostMesh& m, std::string& err) {
     // Positions strictly inside a column belong to that column alone (never
     // shared, never hanging): they take the next id directly.  The others
     // (4N per column) go through the table.
-    size_t n_hang_slots = 0;
-    for (int32_t sc : src_col) n_hang_slots += sc >= 0;
-    // boundary positions are shared by two or more columns on conforming
-    // faces: expect about half as many as column slots on the boundary
-    PairTable hid(size_t(in.n_col) * size_t(2 * N)), hhid(n_hang_slots);
-    int32_t n_unique = 0;
-    m.gmap.assign(size_t(in.n_col) * np2, 0);
+    if (int64_t(in.n_col) * np2 >= (int64_t(1) << 31)) {
+        err = "mesh too large for 32-bit node indices"; return SEM_ERR_MESH;
+    }
     std::vector<size_t> hh_first;   // (c, pos) slot that defined each hanging point
     // visiting order: units (a block, or a column in no block) by their
     // lowest column id; a block's positions in row order over its
     // (2N+1) x (2N+1) grid, every column slot at a position in turn
-    std::vector<std::array<int32_t, 3>> visit;   // (column, i, j)
-    visit.reserve(size_t(in.n_col) * np2);
+    std::vector<int64_t> visit_at(size_t(in.n_col) + 1, 0);   // first visit of each column's unit
     for (int c = 0; c < in.n_col; ++c) {
         const int32_t b = m.col_block[c];
-        if (b < 0) {
-            for (int j = 0; j < np1; ++j)
-                for (int i = 0; i < np1; ++i) visit.push_back({c, i, j});
-            continue;
+        int64_t n = np2;
+        if (b >= 0) {
+            const int32_t* bc = &m.blk_cols[size_t(b) * 4];
+            n = c == *std::min_element(bc, bc + 4) ? 4 * np2 : 0;
         }
-        const int32_t* bc = &m.blk_cols[size_t(b) * 4];
-        if (c != *std::min_element(bc, bc + 4)) continue;
-        for (int J = 0; J <= 2 * N; ++J)
-            for (int I = 0; I <= 2 * N; ++I)
-                for (int q = 0; q < 4; ++q) {
-                    const int qx = q & 1, qy = q >> 1;
-                    const int i = I - qx * N, j = J - qy * N;
-                    if (i < 0 || i > N || j < 0 || j > N) continue;
-                    visit.push_back({bc[q], i, j});
-                }
+        visit_at[size_t(c) + 1] = visit_at[size_t(c)] + n;
     }
-    for (const auto& vt : visit) {
-                const int c = vt[0], i = vt[1], j = vt[2];
-                size_t s = size_t(c) * np2 + i + np1 * j;
-                Key2 k{kx_of(c, i), ky_of(c, j)};
-                double x = m.col_x0[c] + 0.5 * (1.0 + B.x[i]) * m.col_dx[c];
-                double y = m.col_y0[c] + 0.5 * (1.0 + B.x[j]) * m.col_dy[c];
-                bool ins = true;
-                if (src_col[s] < 0) {
-                    const bool inside = i > 0 && i < N && j > 0 && j < N;
-                    const int32_t id = inside ? n_unique : hid.find_or_insert(k.kx, k.ky, n_unique, ins);
-                    if (ins) {
-                        ++n_unique;
-                        m.h_xy.push_back(x); m.h_xy.push_back(y);
-                    }
-                    m.gmap[s] = id;
-                } else {
-                    const int32_t id = hhid.find_or_insert(k.kx, k.ky, int32_t(hhid.size()), ins);
-                    if (ins) {
-                        m.hh_xy.push_back(x); m.hh_xy.push_back(y);
-                        hh_first.push_back(s);
-                    }
-                    m.gmap[s] = -(id + 1);
-                }
+    std::vector<std::array<int32_t, 3>> visit(size_t(visit_at.back()));   // (column, i, j)
+    parallel_ranges(size_t(in.n_col), host_threads(visit.size()), [&](size_t c0, size_t c1, int) {
+        for (size_t c = c0; c < c1; ++c) {
+            size_t v = size_t(visit_at[c]);
+            if (visit_at[c + 1] == visit_at[c]) continue;
+            const int32_t b = m.col_block[c];
+            if (b < 0) {
+                for (int j = 0; j < np1; ++j)
+                    for (int i = 0; i < np1; ++i) visit[v++] = {int32_t(c), i, j};
+                continue;
             }
+            const int32_t* bc = &m.blk_cols[size_t(b) * 4];
+            for (int J = 0; J <= 2 * N; ++J)
+                for (int I = 0; I <= 2 * N; ++I)
+                    for (int q = 0; q < 4; ++q) {
+                        const int qx = q & 1, qy = q >> 1;
+                        const int i = I - qx * N, j = J - qy * N;
+                        if (i < 0 || i > N || j < 0 || j > N) continue;
+                        visit[v++] = {bc[q], i, j};
+                    }
+        }
+    });
+    // First-touch numbering in visiting order.  A visit is a position
+    // strictly inside its column (class 0: never shared, never hanging, it
+    // takes the next id), a conforming boundary position (1) or a hanging
+    // one (2); the id of a keyed position is given at its first visit (its
+    // leader).  Leaders are found in parallel: keys go to buckets by hash,
+    // each bucket keeps visiting order and finds first occurrences with its
+    // own table; one ordered pass then hands out the ids.
+    const size_t nv = visit.size();
+    const int T = host_threads(nv);
+    std::vector<int8_t> cls(nv);
+    std::vector<int64_t> kxs(nv, 0), kys(nv, 0);
+    parallel_ranges(nv, T, [&](size_t b, size_t e, int) {
+        for (size_t v = b; v < e; ++v) {
+            const int c = visit[v][0], i = visit[v][1], j = visit[v][2];
+            const size_t s = size_t(c) * np2 + i + np1 * j;
+            if (src_col[s] >= 0) cls[v] = 2;
+            else cls[v] = (i > 0 && i < N && j > 0 && j < N) ? 0 : 1;
+            if (cls[v]) {
+                kxs[v] = kx_of(c, i);
+                kys[v] = ky_of(c, j);
+            }
+        }
+    });
+    const int P = T;
+    std::vector<std::vector<std::vector<int32_t>>> part(static_cast<size_t>(T),
+                                                        std::vector<std::vector<int32_t>>(static_cast<size_t>(P)));
+    parallel_ranges(nv, T, [&](size_t b, size_t e, int t) {
+        for (size_t v = b; v < e; ++v)
+            if (cls[v]) part[size_t(t)][size_t(key_bucket(kxs[v], kys[v], P))].push_back(int32_t(v));
+    });
+    std::vector<int32_t> lead(nv, -1);
+    std::vector<char> bucket_clash(size_t(P), 0);
+    parallel_ranges(size_t(P), P, [&](size_t q0, size_t q1, int) {
+        for (size_t q = q0; q < q1; ++q) {
+            size_t cnt = 0;
+            for (int t = 0; t < T; ++t) cnt += part[size_t(t)][q].size();
+            PairTable conf(cnt / 2 + 16), hang(16);
+            for (int t = 0; t < T; ++t)
+                for (int32_t v : part[size_t(t)][q]) {
+                    bool ins;
+                    PairTable& tab = cls[size_t(v)] == 1 ? conf : hang;
+                    lead[size_t(v)] = tab.find_or_insert(kxs[size_t(v)], kys[size_t(v)], v, ins);
+                }
+            hang.for_each([&](int64_t a2, int64_t b2, int32_t) {
+                if (conf.find(a2, b2) >= 0) bucket_clash[q] = 1;
+            });
+        }
+    });
+    part.clear();
+    // ids in visiting order: the new ids of a range of visits start after
+    // those of the ranges before it (a prefix sum over the ranges)
+    auto is_new = [&](size_t v) { return cls[v] == 0 || lead[v] == int32_t(v); };
+    std::vector<int64_t> base_u(size_t(T) + 1, 0), base_h(size_t(T) + 1, 0);
+    parallel_ranges(nv, T, [&](size_t b, size_t e, int t) {
+        int64_t u = 0, h = 0;
+        for (size_t v = b; v < e; ++v)
+            if (is_new(v)) (cls[v] == 2 ? h : u) += 1;
+        base_u[size_t(t) + 1] = u;
+        base_h[size_t(t) + 1] = h;
+    });
+    for (int t = 0; t < T; ++t) {
+        base_u[size_t(t) + 1] += base_u[size_t(t)];
+        base_h[size_t(t) + 1] += base_h[size_t(t)];
+    }
+    const int32_t n_unique = int32_t(base_u[size_t(T)]), n_hh = int32_t(base_h[size_t(T)]);
+    m.gmap.assign(size_t(in.n_col) * np2, 0);
+    m.h_xy.assign(2 * size_t(n_unique), 0.0);
+    m.hh_xy.assign(2 * size_t(n_hh), 0.0);
+    hh_first.assign(size_t(n_hh), 0);
+    std::vector<int32_t> idof(nv, -1);
+    parallel_ranges(nv, T, [&](size_t b, size_t e, int t) {
+        int32_t u = int32_t(base_u[size_t(t)]), h = int32_t(base_h[size_t(t)]);
+        for (size_t v = b; v < e; ++v) {
+            if (!is_new(v)) continue;
+            const int c = visit[v][0], i = visit[v][1], j = visit[v][2];
+            const size_t s = size_t(c) * np2 + i + np1 * j;
+            const double x = m.col_x0[c] + 0.5 * (1.0 + B.x[i]) * m.col_dx[c];
+            const double y = m.col_y0[c] + 0.5 * (1.0 + B.x[j]) * m.col_dy[c];
+            if (cls[v] == 2) {
+                idof[v] = h;
+                m.hh_xy[2 * size_t(h)] = x;
+                m.hh_xy[2 * size_t(h) + 1] = y;
+                hh_first[size_t(h)] = s;
+                m.gmap[s] = -(h + 1);
+                ++h;
+            } else {
+                idof[v] = u;
+                m.h_xy[2 * size_t(u)] = x;
+                m.h_xy[2 * size_t(u) + 1] = y;
+                m.gmap[s] = u;
+                ++u;
+            }
+        }
+    });
+    parallel_ranges(nv, T, [&](size_t b, size_t e, int) {
+        for (size_t v = b; v < e; ++v) {
+            if (is_new(v)) continue;
+            const int c = visit[v][0], i = visit[v][1], j = visit[v][2];
+            const size_t s = size_t(c) * np2 + i + np1 * j;
+            const int32_t id = idof[size_t(lead[v])];
+            m.gmap[s] = cls[v] == 2 ? -(id + 1) : id;
+        }
+    });
     bool clash = false;
-    hhid.for_each([&](int64_t a, int64_t b, int32_t) { clash = clash || hid.find(a, b) >= 0; });
+    for (char cb : bucket_clash) clash = clash || cb;
     if (clash) { err = "a hanging point is also a conforming node"; return SEM_ERR_MESH; }
     m.n_h = int64_t(n_unique);
-    m.n_hh = int64_t(hhid.size());
+    m.n_hh = int64_t(n_hh);
     if (m.n_h * int64_t(m.ldz) >= (int64_t(1) << 31) || m.n_hh * int64_t(m.ldz) >= (int64_t(1) << 31) ||
         int64_t(in.n_col) * in.n_z * np1 * np2 >= (int64_t(1) << 31)) {
         err = "mesh too large for 32-bit node indices"; return SEM_ERR_MESH;
@@ -555,17 +701,28 @@ int build_host_mesh(const MeshInput& in, HostMesh& m, std::string& err) {
         for (auto& e : r) { m.hang_src.push_back(e.first); m.hang_w.push_back(e.second); }
         m.hang_ptr[hh + 1] = int32_t(m.hang_src.size());
     }
-    // transposed rows
+    // transposed rows (a counting sort by source, stable in hanging-point order)
     {
-        std::vector<std::vector<std::pair<int32_t, double>>> t(size_t(m.n_h));
+        std::vector<int32_t> tp(size_t(m.n_h) + 1, 0);
+        for (int32_t q = 0; q < m.hang_ptr[size_t(m.n_hh)]; ++q) ++tp[size_t(m.hang_src[q]) + 1];
+        for (int64_t h = 0; h < m.n_h; ++h) tp[h + 1] += tp[h];
+        std::vector<int32_t> thh(size_t(tp.back()));
+        std::vector<double> tw(size_t(tp.back()));
+        std::vector<int32_t> fill(tp.begin(), tp.end() - 1);
         for (int64_t hh = 0; hh < m.n_hh; ++hh)
-            for (int32_t q = m.hang_ptr[hh]; q < m.hang_ptr[hh + 1]; ++q)
-                t[m.hang_src[q]].push_back({int32_t(hh), m.hang_w[q]});
+            for (int32_t q = m.hang_ptr[hh]; q < m.hang_ptr[hh + 1]; ++q) {
+                const int32_t at = fill[size_t(m.hang_src[q])]++;
+                thh[size_t(at)] = int32_t(hh);
+                tw[size_t(at)] = m.hang_w[q];
+            }
         m.hT_ptr.push_back(0);
         for (int64_t h = 0; h < m.n_h; ++h) {
-            if (t[h].empty()) continue;
+            if (tp[h + 1] == tp[h]) continue;
             m.hT_list.push_back(int32_t(h));
-            for (auto& e : t[h]) { m.hT_hh.push_back(e.first); m.hT_w.push_back(e.second); }
+            for (int32_t q = tp[h]; q < tp[h + 1]; ++q) {
+                m.hT_hh.push_back(thh[size_t(q)]);
+                m.hT_w.push_back(tw[size_t(q)]);
+            }
             m.hT_ptr.push_back(int32_t(m.hT_hh.size()));
         }
     }
@@ -605,7 +762,8 @@ int build_host_mesh(const MeshInput& in, HostMesh& m, std::string& err) {
     }
     // sibling families
     m.sib.assign(size_t(in.n_col) * 4, -1);
-    for (int c = 0; c < in.n_col; ++c) {
+    parallel_ranges(size_t(in.n_col), host_threads(size_t(in.n_col) * np2), [&](size_t c0, size_t c1, int) {
+    for (int c = int(c0); c < int(c1); ++c) {
         int l = in.lev[c];
         if (l == 0) continue;
         int64_t bx = in.ix[c] & ~int64_t(1), by = in.iy[c] & ~int64_t(1);
@@ -617,33 +775,37 @@ int build_host_mesh(const MeshInput& in, HostMesh& m, std::string& err) {
         }
         if (ok) for (int q = 0; q < 4; ++q) m.sib[size_t(c) * 4 + q] = ids[q];
     }
-    // horizontal neighbours through shared unique horizontal nodes
+    });
+    // horizontal neighbours through shared unique horizontal nodes: the
+    // assembly CSR lists the slots (hence columns) at every node; each range
+    // of columns collects its lists, then the ranges are joined in order
     {
-        const int np2 = m.np1 * m.np1;
-        std::vector<int32_t> hp(size_t(m.n_h) + 1, 0), hc;
-        for (size_t s = 0; s < m.gmap.size(); ++s)
-            if (m.gmap[s] >= 0) ++hp[size_t(m.gmap[s]) + 1];
-        for (int64_t h = 0; h < m.n_h; ++h) hp[h + 1] += hp[h];
-        hc.assign(hp.back(), 0);
-        std::vector<int32_t> fill(hp.begin(), hp.end() - 1);
-        for (size_t s = 0; s < m.gmap.size(); ++s)
-            if (m.gmap[s] >= 0) hc[fill[m.gmap[s]]++] = int32_t(s / np2);
-        m.nbr_ptr.assign(size_t(in.n_col) + 1, 0);
-        m.nbr_col.clear();
-        std::vector<int32_t> list;
-        for (int c = 0; c < in.n_col; ++c) {
-            list.clear();
-            for (int pos = 0; pos < np2; ++pos) {
-                const int32_t g = m.gmap[size_t(c) * np2 + pos];
-                if (g < 0) continue;
-                for (int r = hp[g]; r < hp[g + 1]; ++r)
-                    if (hc[r] != c) list.push_back(hc[r]);
+        const int TN = host_threads(size_t(in.n_col) * np2);
+        std::vector<std::vector<int32_t>> lists(static_cast<size_t>(TN));
+        std::vector<int32_t> count(size_t(in.n_col), 0);
+        parallel_ranges(size_t(in.n_col), TN, [&](size_t c0, size_t c1, int t) {
+            std::vector<int32_t> list;
+            for (size_t c = c0; c < c1; ++c) {
+                list.clear();
+                for (int pos = 0; pos < np2; ++pos) {
+                    const int32_t g = m.gmap[c * np2 + pos];
+                    if (g < 0) continue;
+                    for (int r = m.asm_ptr[size_t(g)]; r < m.asm_ptr[size_t(g) + 1]; ++r) {
+                        const int32_t cc = m.asm_slot[size_t(r)] / np2;
+                        if (cc != int32_t(c)) list.push_back(cc);
+                    }
+                }
+                std::sort(list.begin(), list.end());
+                list.erase(std::unique(list.begin(), list.end()), list.end());
+                count[c] = int32_t(list.size());
+                lists[size_t(t)].insert(lists[size_t(t)].end(), list.begin(), list.end());
             }
-            std::sort(list.begin(), list.end());
-            list.erase(std::unique(list.begin(), list.end()), list.end());
-            m.nbr_col.insert(m.nbr_col.end(), list.begin(), list.end());
-            m.nbr_ptr[size_t(c) + 1] = int32_t(m.nbr_col.size());
-        }
+        });
+        m.nbr_ptr.assign(size_t(in.n_col) + 1, 0);
+        for (int c = 0; c < in.n_col; ++c) m.nbr_ptr[size_t(c) + 1] = m.nbr_ptr[size_t(c)] + count[size_t(c)];
+        m.nbr_col.clear();
+        m.nbr_col.reserve(size_t(m.nbr_ptr.back()));
+        for (auto& l : lists) m.nbr_col.insert(m.nbr_col.end(), l.begin(), l.end());
     }
     return SEM_OK;
 }
