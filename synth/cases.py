@@ -19,6 +19,9 @@ theta_s=300 K):
                             400 x 400 x 20 km domain, columns refined once where
                             the surface vertical vorticity of the vortex exceeds
                             2e-4 1/s; dt 0.48 s (N=4) / 0.18 s (N=7).
+* ``share{2,4,8}_64x{32,16,8}x16_n4`` : one GPU's share of ``vortex_64x64x16_n4``
+                            split 2, 4 or 8 ways along y (a strip, periodic in
+                            x only).
 * small meshes for tests (``small_*``).
 
 The time steps follow dt = 0.4 h_min / (c_s + |u|_max) with h_min the
@@ -67,6 +70,16 @@ def get(name, **over):
         c = _case(4, 64, 64, 1000e3, 1000e3, 25e3, 16, columns.uniform(64, 64),
                   v_max=25.0, r_max=40e3, noise_amp=0.5, noise_ztop=2e3, dt=0.29,
                   stages=100, name=name)
+    elif name in ("share2_64x32x16_n4", "share4_64x16x16_n4", "share8_64x8x16_n4"):
+        # one GPU's share of the 64 x 64 x 16 workload split k ways along y:
+        # a 64 x (64/k) x 16 strip, periodic in x only (its y faces would
+        # border the neighbouring GPUs' strips)
+        k = int(name[5])
+        ny = 64 // k
+        c = _case(4, 64, ny, 1000e3, 1000e3 / k, 25e3, 16, columns.uniform(64, ny),
+                  v_max=25.0, r_max=40e3, noise_amp=0.5, noise_ztop=2e3, dt=0.29,
+                  stages=100, name=name)
+        c["periodic_y"] = False
     elif name in ("amr2_64x64x8_n4", "amr2_64x64x8_n7"):
         N = 4 if name.endswith("n4") else 7
         c = _case(N, 64, 64, 400e3, 400e3, 20e3, 8, columns.uniform(64, 64),
