@@ -124,8 +124,11 @@ typedef struct {
  * hanging nodes, build the interpolation rows of hanging points (composed
  * until every source is a non-hanging node), the lumped mass
  * M_G = Z^T m_L and the assembly tables, and upload them.  *out receives a
- * handle to destroy with sem_mesh_destroy.  Errors: SEM_ERR_ARG, SEM_ERR_N,
- * SEM_ERR_MESH, SEM_ERR_HIP. */
+ * handle to destroy with sem_mesh_destroy.  The host build runs on
+ * SEM_HOST_THREADS threads when that variable is set, else on
+ * OMP_NUM_THREADS, else on the hardware count (at most 32; one thread for
+ * small meshes); the tables do not depend on the count.
+ * Errors: SEM_ERR_ARG, SEM_ERR_N, SEM_ERR_MESH, SEM_ERR_HIP. */
 int sem_mesh_create(const sem_mesh_desc *desc, sem_mesh **out);
 int sem_mesh_destroy(sem_mesh *mesh);
 
