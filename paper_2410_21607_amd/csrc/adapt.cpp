@@ -318,17 +318,10 @@ int build_transfer(const HostMesh& A, const HostMesh& B, TransferRows& T, std::s
                 src[c][a + 2 * b] = k->second;
             }
     }
-    // (column, position) pairs of every new unique horizontal node
-    std::vector<int32_t> hp(B.n_h + 1, 0), hcp;
-    for (int64_t s = 0; s < int64_t(B.n_col) * n2; ++s)
-        if (B.gmap[s] >= 0) ++hp[B.gmap[s] + 1];
-    for (int64_t h = 0; h < B.n_h; ++h) hp[h + 1] += hp[h];
-    hcp.assign(hp[B.n_h], 0);
-    {
-        std::vector<int32_t> fill(hp.begin(), hp.end() - 1);
-        for (int64_t s = 0; s < int64_t(B.n_col) * n2; ++s)
-            if (B.gmap[s] >= 0) hcp[fill[B.gmap[s]]++] = int32_t(s);
-    }
+    // (column, position) slots of every new unique horizontal node, in
+    // increasing slot order: the assembly CSR of the new mesh
+    const std::vector<int32_t>& hp = B.asm_ptr;
+    const std::vector<int32_t>& hcp = B.asm_slot;
     std::vector<double> P[2];
     projection_1d(A.basis, P);
     std::vector<double> lx(n), ly(n);

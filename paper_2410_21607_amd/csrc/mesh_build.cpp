@@ -14,14 +14,13 @@
 // source is a non-hanging node (chains appear with three or more levels, or
 // with odd N where coarse edge midpoints are not nodes).
 #include "mesh_build.h"
+#include "host_par.h"
 
 #include <array>
 
 #include <algorithm>
 #include <cmath>
-#include <cstdlib>
 #include <map>
-#include <thread>
 #include <unordered_map>
 #include <utility>
 
@@ -249,40 +248,6 @@ class PairTable {
     std::vector<Entry> e_;
     size_t mask_ = 0, size_ = 0;
 };
-
-// Worker threads for the host build: SEM_HOST_THREADS when set (for any
-// mesh size); else the process's CPU share as the OpenMP convention states
-// it (OMP_NUM_THREADS) when set, else the hardware count, at most 32, and
-// one thread for small meshes.  The tables do not depend on the count.
-int host_threads(size_t work) {
-    if (const char* e = std::getenv("SEM_HOST_THREADS")) {
-        const int v = std::atoi(e);
-        if (v > 0) return std::min(v, 32);
-    }
-    if (work < (size_t(1) << 16)) return 1;
-    int n = int(std::thread::hardware_concurrency());
-    if (const char* e = std::getenv("OMP_NUM_THREADS")) {
-        const int v = std::atoi(e);
-        if (v > 0) n = v;
-    }
-    return std::max(1, std::min(n, 32));
-}
-
-// f(begin, end, t) over T contiguous ranges of [0, n), one thread each
-template <typename F>
-void parallel_ranges(size_t n, int T, F f) {
-    if (T <= 1) {
-        f(size_t(0), n, 0);
-        return;
-    }
-    std::vector<std::thread> th;
-    th.reserve(size_t(T));
-    for (int t = 0; t < T; ++t) {
-        const size_t b = n * size_t(t) / size_t(T), e = n * size_t(t + 1) / size_t(T);
-        th.emplace_back([b, e, t, &f] { f(b, e, t); });
-    }
-    for (auto& x : th) x.join();
-}
 
 // bucket of a position key (a mix independent of the tables' slot hash)
 inline int key_bucket(int64_t a, int64_t b, int P) {
