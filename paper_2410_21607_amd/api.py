@@ -360,15 +360,21 @@ def sem_adapt_columns(mesh_or_params, columns, adapt_col, lvl_max):
         raise ValueError("one flag per column")
     n = ctypes.c_int32()
     L = native.lib()
-    rc = L.sem_adapt_columns(ctypes.byref(d), fl.ctypes.data_as(ctypes.c_void_p), int(lvl_max), 0,
-                             None, None, None, ctypes.byref(n))
-    if rc != native.SEM_OK and n.value == 0:
-        raise native.SemError("sem_adapt_columns", rc, L.sem_last_error().decode())
-    lev, ix, iy = (np.zeros(n.value, np.int32) for _ in range(3))
     i32 = lambda a: a.ctypes.data_as(native.c_i32p)
-    native.call("sem_adapt_columns", ctypes.byref(d), fl.ctypes.data_as(ctypes.c_void_p),
-                int(lvl_max), n.value, i32(lev), i32(ix), i32(iy), ctypes.byref(n))
-    return np.stack([lev, ix, iy], axis=1)
+    # room for every column split once (the usual case); the call reports the
+    # size needed when that is not enough, and runs again with it
+    cap = 4 * fl.size + 1024
+    for _ in range(2):
+        lev, ix, iy = (np.zeros(cap, np.int32) for _ in range(3))
+        rc = L.sem_adapt_columns(ctypes.byref(d), fl.ctypes.data_as(ctypes.c_void_p), int(lvl_max), cap,
+                                 i32(lev), i32(ix), i32(iy), ctypes.byref(n))
+        if rc == native.SEM_OK:
+            k = n.value
+            return np.stack([lev[:k], ix[:k], iy[:k]], axis=1)
+        if n.value <= cap:
+            raise native.SemError("sem_adapt_columns", rc, L.sem_last_error().decode())
+        cap = n.value
+    raise native.SemError("sem_adapt_columns", rc, L.sem_last_error().decode())
 
 
 def sem_transfer_plan(params, columns_from, columns_to):
