@@ -140,10 +140,11 @@ def get(name, **over):
         pred = _vorticity_refiner(c, c["amr"]["thresholds"])
         c["columns"] = columns.refine_where(nb, nb, 400e3, 400e3, 2, pred)
     elif name.startswith("tstar_64x64x8_n4"):
-        # time-to-solution study: the smooth 40 m/s vortex at rest on the
-        # 400 km domain, refined by wind speed with the paper's thresholds
-        # (7.5 m/s per level); `level` picks the layout: uniform at that
-        # level, or the speed-refined layout up to that level (`amr`)
+        # time-to-solution study: the smooth 40 m/s vortex on the 400 km
+        # domain (at rest unless `steer` is given), refined by wind speed
+        # with the paper's thresholds (7.5 m/s per level); `level` picks the
+        # layout: uniform at that level, or the speed-refined layout up to
+        # that level (`amr`)
         seed = int(over.pop("seed", 0))
         level = int(over.pop("level", 0))
         amr = bool(over.pop("amr", False))
