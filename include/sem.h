@@ -68,6 +68,7 @@ extern "C" {
 #define SEM_ERR_MESH -3   /* invalid layout: overlap, gap, 2:1 violation    */
 #define SEM_ERR_HIP  -4   /* HIP runtime error (allocation, launch, copy)   */
 #define SEM_ERR_STATE -5  /* call made before a required set-up call        */
+#define SEM_ERR_HOST -6   /* host-side failure: memory or threads exhausted */
 
 #define SEM_MAX_N 8       /* polynomial orders 1..8 are supported           */
 #define SEM_MAX_LEVEL 12

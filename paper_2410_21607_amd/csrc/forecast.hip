@@ -355,7 +355,7 @@ int sem_max_wind(const sem_mesh* M, const double* q, double x0, double x1, doubl
     return SEM_OK;
 }
 
-int sem_forecast_labels(const sem_mesh_desc* at, const sem_mesh_desc* later, const int8_t* dem_later,
+static int sem_forecast_labels_impl(const sem_mesh_desc* at, const sem_mesh_desc* later, const int8_t* dem_later,
                         int8_t* cls) {
     if (!at || !later || !dem_later || !cls) return fail(SEM_ERR_ARG, "null argument");
     if (at->n_z != later->n_z || at->nx0 != later->nx0 || at->ny0 != later->ny0 || at->n_z < 1)
@@ -397,6 +397,11 @@ int sem_forecast_labels(const sem_mesh_desc* at, const sem_mesh_desc* later, con
         }
     }
     return SEM_OK;
+}
+
+int sem_forecast_labels(const sem_mesh_desc* at, const sem_mesh_desc* later, const int8_t* dem_later,
+                        int8_t* cls) {
+    return sem::guarded("sem_forecast_labels", [&] { return sem_forecast_labels_impl(at, later, dem_later, cls); });
 }
 
 }  // extern "C"

@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <exception>
 #include <string>
 #include <vector>
 
@@ -20,6 +21,20 @@ std::string& last_error();
 inline int fail(int code, const std::string& msg) {
     last_error() = msg;
     return code;
+}
+
+// Entry points with host-side work run through this: a C++ exception (host
+// memory or threads exhausted) becomes SEM_ERR_HOST with its message instead
+// of crossing the C boundary.
+template <typename F>
+int guarded(const char* name, F&& f) {
+    try {
+        return f();
+    } catch (const std::exception& e) {
+        return fail(SEM_ERR_HOST, std::string(name) + ": " + e.what());
+    } catch (...) {
+        return fail(SEM_ERR_HOST, std::string(name) + ": host-side failure");
+    }
 }
 
 }  // namespace sem

@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cstddef>
 #include <cstdlib>
+#include <exception>
 #include <thread>
 #include <vector>
 
@@ -27,20 +28,36 @@ inline int host_threads(size_t work) {
     return std::max(1, std::min(n, 32));
 }
 
-// f(begin, end, t) over T contiguous ranges of [0, n), one thread each
+// f(begin, end, t) over T contiguous ranges of [0, n), one thread each.  A
+// range whose thread cannot be started runs on the calling thread; the first
+// exception of any range is rethrown once every thread has joined.
 template <typename F>
 inline void parallel_ranges(size_t n, int T, F f) {
     if (T <= 1) {
         f(size_t(0), n, 0);
         return;
     }
+    std::vector<std::exception_ptr> err(static_cast<size_t>(T));
+    auto run = [&f, &err](size_t b, size_t e, int t) {
+        try {
+            f(b, e, t);
+        } catch (...) {
+            err[size_t(t)] = std::current_exception();
+        }
+    };
     std::vector<std::thread> th;
     th.reserve(size_t(T));
     for (int t = 0; t < T; ++t) {
         const size_t b = n * size_t(t) / size_t(T), e = n * size_t(t + 1) / size_t(T);
-        th.emplace_back([b, e, t, &f] { f(b, e, t); });
+        try {
+            th.emplace_back(run, b, e, t);
+        } catch (...) {
+            run(b, e, t);
+        }
     }
     for (auto& x : th) x.join();
+    for (auto& x : err)
+        if (x) std::rethrow_exception(x);
 }
 
 }  // namespace sem

@@ -687,7 +687,7 @@ extern "C" {
 
 const char* sem_last_error(void) { return sem::last_error().c_str(); }
 
-int sem_mesh_create(const sem_mesh_desc* desc, sem_mesh** out) {
+static int sem_mesh_create_impl(const sem_mesh_desc* desc, sem_mesh** out) {
     if (!desc || !out) return fail(SEM_ERR_ARG, "null argument");
     *out = nullptr;
     sem::MeshInput in{desc->N, desc->nx0, desc->ny0, desc->n_z, desc->n_col,
@@ -734,7 +734,11 @@ int sem_mesh_create(const sem_mesh_desc* desc, sem_mesh** out) {
     return SEM_OK;
 }
 
-int sem_mesh_plan(const sem_mesh_desc* desc, sem_mesh_info* o, double* hxy, double* hhxy, double* z,
+int sem_mesh_create(const sem_mesh_desc* desc, sem_mesh** out) {
+    return sem::guarded("sem_mesh_create", [&] { return sem_mesh_create_impl(desc, out); });
+}
+
+static int sem_mesh_plan_impl(const sem_mesh_desc* desc, sem_mesh_info* o, double* hxy, double* hhxy, double* z,
                   double* mass) {
     if (!desc || !o) return fail(SEM_ERR_ARG, "null argument");
     sem::MeshInput in{desc->N, desc->nx0, desc->ny0, desc->n_z, desc->n_col,
@@ -759,6 +763,11 @@ int sem_mesh_plan(const sem_mesh_desc* desc, sem_mesh_info* o, double* hxy, doub
             for (int kz = 0; kz < H.nzn; ++kz)
                 mass[h * H.nzn + kz] = 1.0 / (H.minv_h[h] * H.minv_v[kz]);
     return SEM_OK;
+}
+
+int sem_mesh_plan(const sem_mesh_desc* desc, sem_mesh_info* o, double* hxy, double* hhxy, double* z,
+                  double* mass) {
+    return sem::guarded("sem_mesh_plan", [&] { return sem_mesh_plan_impl(desc, o, hxy, hhxy, z, mass); });
 }
 
 int sem_mesh_destroy(sem_mesh* mesh) {
@@ -817,7 +826,7 @@ int sem_mesh_set_reference(sem_mesh* M, const double* rho0, const double* theta0
     return SEM_OK;
 }
 
-int sem_mesh_set_terrain(sem_mesh* M, const double* zs, const double* rho0, const double* theta0,
+static int sem_mesh_set_terrain_impl(sem_mesh* M, const double* zs, const double* rho0, const double* theta0,
                          const double* dth0) {
     if (!M) return fail(SEM_ERR_ARG, "null mesh");
     const sem::HostMesh& H = M->host;
@@ -951,6 +960,11 @@ int sem_mesh_set_terrain(sem_mesh* M, const double* zs, const double* rho0, cons
     M->zs_host.assign(zs, zs + nh);
     ++M->epoch;
     return SEM_OK;
+}
+
+int sem_mesh_set_terrain(sem_mesh* M, const double* zs, const double* rho0, const double* theta0,
+                         const double* dth0) {
+    return sem::guarded("sem_mesh_set_terrain", [&] { return sem_mesh_set_terrain_impl(M, zs, rho0, theta0, dth0); });
 }
 
 int sem_mesh_heights(const sem_mesh* M, const double* zs, double* z) {
@@ -1087,7 +1101,7 @@ int sem_mesh_set_dissipation(sem_mesh* M, double cs, double sponge_gamma, double
     return SEM_OK;
 }
 
-int sem_stage_set_layout(sem_mesh* M, int layout, int param) {
+static int sem_stage_set_layout_impl(sem_mesh* M, int layout, int param) {
     if (!M) return fail(SEM_ERR_ARG, "null mesh");
     if (layout != SEM_LAYOUT_COLUMNS && layout != SEM_LAYOUT_BLOCKS)
         return fail(SEM_ERR_ARG, "unknown layout");
@@ -1106,6 +1120,10 @@ int sem_stage_set_layout(sem_mesh* M, int layout, int param) {
     return SEM_OK;
 }
 
+int sem_stage_set_layout(sem_mesh* M, int layout, int param) {
+    return sem::guarded("sem_stage_set_layout", [&] { return sem_stage_set_layout_impl(M, layout, param); });
+}
+
 int sem_stage_get_layout(const sem_mesh* M, int* layout, int* param) {
     if (!M || !layout || !param) return fail(SEM_ERR_ARG, "null argument");
     *layout = M->fused.layout;
@@ -1113,7 +1131,7 @@ int sem_stage_get_layout(const sem_mesh* M, int* layout, int* param) {
     return SEM_OK;
 }
 
-int sem_stage_tune(sem_mesh* M, int layers_per_chunk) {
+static int sem_stage_tune_impl(sem_mesh* M, int layers_per_chunk) {
     if (!M) return fail(SEM_ERR_ARG, "null mesh");
     if (layers_per_chunk < 0 ||
         (layers_per_chunk > 0 && !sem::fused_lpc_supported(M->host.N, layers_per_chunk)))
@@ -1121,7 +1139,11 @@ int sem_stage_tune(sem_mesh* M, int layers_per_chunk) {
     return sem_stage_set_layout(M, SEM_LAYOUT_COLUMNS, layers_per_chunk);
 }
 
-int sem_stage_autotune(sem_mesh* M, const double* qn, const double* qs, double* qout, int prec,
+int sem_stage_tune(sem_mesh* M, int layers_per_chunk) {
+    return sem::guarded("sem_stage_tune", [&] { return sem_stage_tune_impl(M, layers_per_chunk); });
+}
+
+static int sem_stage_autotune_impl(sem_mesh* M, const double* qn, const double* qs, double* qout, int prec,
                        int reps, int* best_lpc, float* best_ms, void* stream) {
     int rc = check_mesh(M);
     if (rc != SEM_OK) return rc;
@@ -1183,6 +1205,11 @@ int sem_stage_autotune(sem_mesh* M, const double* qn, const double* qs, double* 
     return SEM_OK;
 }
 
+int sem_stage_autotune(sem_mesh* M, const double* qn, const double* qs, double* qout, int prec,
+                       int reps, int* best_lpc, float* best_ms, void* stream) {
+    return sem::guarded("sem_stage_autotune", [&] { return sem_stage_autotune_impl(M, qn, qs, qout, prec, reps, best_lpc, best_ms, stream); });
+}
+
 int sem_stage_get_tune(const sem_mesh* M, int* layers_per_chunk) {
     if (!M || !layers_per_chunk) return fail(SEM_ERR_ARG, "null argument");
     *layers_per_chunk = M->fused.t.layers_per_chunk;
@@ -1231,7 +1258,7 @@ static sem::MeshInput input_of(const sem_mesh_desc* d) {
                           d->periodic_y != 0, d->f, d->g, d->R_d, d->c_p, d->p00};
 }
 
-int sem_adapt_columns(const sem_mesh_desc* desc, const int8_t* flags, int lvl_max, int32_t cap,
+static int sem_adapt_columns_impl(const sem_mesh_desc* desc, const int8_t* flags, int lvl_max, int32_t cap,
                       int32_t* lev, int32_t* ix, int32_t* iy, int32_t* n_out) {
     if (!desc || !flags || !n_out) return fail(SEM_ERR_ARG, "null argument");
     if (cap < 0 || (cap > 0 && (!lev || !ix || !iy))) return fail(SEM_ERR_ARG, "bad output arrays");
@@ -1253,7 +1280,12 @@ int sem_adapt_columns(const sem_mesh_desc* desc, const int8_t* flags, int lvl_ma
     return SEM_OK;
 }
 
-int sem_transfer_plan(const sem_mesh_desc* from, const sem_mesh_desc* to, int64_t* nnz,
+int sem_adapt_columns(const sem_mesh_desc* desc, const int8_t* flags, int lvl_max, int32_t cap,
+                      int32_t* lev, int32_t* ix, int32_t* iy, int32_t* n_out) {
+    return sem::guarded("sem_adapt_columns", [&] { return sem_adapt_columns_impl(desc, flags, lvl_max, cap, lev, ix, iy, n_out); });
+}
+
+static int sem_transfer_plan_impl(const sem_mesh_desc* from, const sem_mesh_desc* to, int64_t* nnz,
                       int32_t* ptr, int32_t* src, double* w) {
     if (!from || !to || !nnz) return fail(SEM_ERR_ARG, "null argument");
     sem::HostMesh A, B;
@@ -1270,7 +1302,12 @@ int sem_transfer_plan(const sem_mesh_desc* from, const sem_mesh_desc* to, int64_
     return SEM_OK;
 }
 
-int sem_transfer_create(const sem_mesh* from, const sem_mesh* to, sem_transfer** out) {
+int sem_transfer_plan(const sem_mesh_desc* from, const sem_mesh_desc* to, int64_t* nnz,
+                      int32_t* ptr, int32_t* src, double* w) {
+    return sem::guarded("sem_transfer_plan", [&] { return sem_transfer_plan_impl(from, to, nnz, ptr, src, w); });
+}
+
+static int sem_transfer_create_impl(const sem_mesh* from, const sem_mesh* to, sem_transfer** out) {
     if (!from || !to || !out) return fail(SEM_ERR_ARG, "null argument");
     *out = nullptr;
     sem::TransferRows T;
@@ -1295,6 +1332,10 @@ int sem_transfer_create(const sem_mesh* from, const sem_mesh* to, sem_transfer**
     }
     *out = X.release();
     return SEM_OK;
+}
+
+int sem_transfer_create(const sem_mesh* from, const sem_mesh* to, sem_transfer** out) {
+    return sem::guarded("sem_transfer_create", [&] { return sem_transfer_create_impl(from, to, out); });
 }
 
 int sem_transfer_apply(const sem_transfer* X, const double* q_from, double* q_to, void* stream) {
