@@ -285,7 +285,7 @@ inline uint64_t ckey(int l, int64_t x, int64_t y) {
 
 extern "C" {
 
-int amr_features(const sem_mesh* M, const double* q, const double* q_prev, const int8_t* plain,
+static int amr_features_impl(const sem_mesh* M, const double* q, const double* q_prev, const int8_t* plain,
                  int criterion, const double* thr, int lvl_max, const float* scale, float* feat,
                  int8_t* dem, void* stream) {
     if (!M) return fail(SEM_ERR_ARG, "null mesh");
@@ -323,7 +323,13 @@ int amr_features(const sem_mesh* M, const double* q, const double* q_prev, const
     return SEM_OK;
 }
 
-int amr_forecast_flags(const sem_mesh* M, const float* logits, const int8_t* plain, int lvl_max,
+int amr_features(const sem_mesh* M, const double* q, const double* q_prev, const int8_t* plain,
+                 int criterion, const double* thr, int lvl_max, const float* scale, float* feat,
+                 int8_t* dem, void* stream) {
+    return sem::guarded("amr_features", [&] { return amr_features_impl(M, q, q_prev, plain, criterion, thr, lvl_max, scale, feat, dem, stream); });
+}
+
+static int amr_forecast_flags_impl(const sem_mesh* M, const float* logits, const int8_t* plain, int lvl_max,
                        int8_t* ae, int8_t* ac, void* stream) {
     if (!M) return fail(SEM_ERR_ARG, "null mesh");
     if (!logits || !plain || !ae || !ac) return fail(SEM_ERR_ARG, "null array");
@@ -340,7 +346,12 @@ int amr_forecast_flags(const sem_mesh* M, const float* logits, const int8_t* pla
     return SEM_OK;
 }
 
-int sem_max_wind(const sem_mesh* M, const double* q, double x0, double x1, double y0, double y1,
+int amr_forecast_flags(const sem_mesh* M, const float* logits, const int8_t* plain, int lvl_max,
+                       int8_t* ae, int8_t* ac, void* stream) {
+    return sem::guarded("amr_forecast_flags", [&] { return amr_forecast_flags_impl(M, logits, plain, lvl_max, ae, ac, stream); });
+}
+
+static int sem_max_wind_impl(const sem_mesh* M, const double* q, double x0, double x1, double y0, double y1,
                  double* vmax, void* stream) {
     if (!M) return fail(SEM_ERR_ARG, "null mesh");
     if (!q || !vmax) return fail(SEM_ERR_ARG, "null array");
@@ -353,6 +364,11 @@ int sem_max_wind(const sem_mesh* M, const double* q, double x0, double x1, doubl
                        sem::WIND_BLOCKS, vmax);
     HIPCHK(hipGetLastError());
     return SEM_OK;
+}
+
+int sem_max_wind(const sem_mesh* M, const double* q, double x0, double x1, double y0, double y1,
+                 double* vmax, void* stream) {
+    return sem::guarded("sem_max_wind", [&] { return sem_max_wind_impl(M, q, x0, x1, y0, y1, vmax, stream); });
 }
 
 static int sem_forecast_labels_impl(const sem_mesh_desc* at, const sem_mesh_desc* later, const int8_t* dem_later,

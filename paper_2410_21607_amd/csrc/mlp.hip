@@ -233,7 +233,7 @@ int grid_of(int64_t n) {
 
 extern "C" {
 
-int mlp_forward(const float* p, const float* x, int64_t n, float* logits, void* stream) {
+static int mlp_forward_impl(const float* p, const float* x, int64_t n, float* logits, void* stream) {
     if (!p || !logits || (n > 0 && !x)) return fail(SEM_ERR_ARG, "null array");
     if (n < 0) return fail(SEM_ERR_ARG, "negative sample count");
     if (n == 0) return SEM_OK;
@@ -243,7 +243,11 @@ int mlp_forward(const float* p, const float* x, int64_t n, float* logits, void* 
     return SEM_OK;
 }
 
-int mlp_backward(const float* p, const float* x, int64_t n_rows, const int8_t* cls,
+int mlp_forward(const float* p, const float* x, int64_t n, float* logits, void* stream) {
+    return sem::guarded("mlp_forward", [&] { return mlp_forward_impl(p, x, n, logits, stream); });
+}
+
+static int mlp_backward_impl(const float* p, const float* x, int64_t n_rows, const int8_t* cls,
                  const int32_t* idx, int64_t n, float* work, float* grad, float* loss, void* stream) {
     if (!p || !x || !cls || !work || !grad || !loss) return fail(SEM_ERR_ARG, "null array");
     if (n < 1) return fail(SEM_ERR_ARG, "empty batch");
@@ -258,7 +262,12 @@ int mlp_backward(const float* p, const float* x, int64_t n_rows, const int8_t* c
     return SEM_OK;
 }
 
-int mlp_backward_noalloc(const float* p, const float* x, int64_t n_rows, const int8_t* cls,
+int mlp_backward(const float* p, const float* x, int64_t n_rows, const int8_t* cls,
+                 const int32_t* idx, int64_t n, float* work, float* grad, float* loss, void* stream) {
+    return sem::guarded("mlp_backward", [&] { return mlp_backward_impl(p, x, n_rows, cls, idx, n, work, grad, loss, stream); });
+}
+
+static int mlp_backward_noalloc_impl(const float* p, const float* x, int64_t n_rows, const int8_t* cls,
                          const int32_t* idx, int64_t n, float* grad, float* loss, void* stream) {
     if (!p || !x || !cls || !grad || !loss) return fail(SEM_ERR_ARG, "null array");
     if (n < 1) return fail(SEM_ERR_ARG, "empty batch");
@@ -282,7 +291,12 @@ int mlp_backward_noalloc(const float* p, const float* x, int64_t n_rows, const i
     return SEM_OK;
 }
 
-int mlp_adam_step(float* p, const float* g, float* m, float* v, int t, float lr, float beta1,
+int mlp_backward_noalloc(const float* p, const float* x, int64_t n_rows, const int8_t* cls,
+                         const int32_t* idx, int64_t n, float* grad, float* loss, void* stream) {
+    return sem::guarded("mlp_backward_noalloc", [&] { return mlp_backward_noalloc_impl(p, x, n_rows, cls, idx, n, grad, loss, stream); });
+}
+
+static int mlp_adam_step_impl(float* p, const float* g, float* m, float* v, int t, float lr, float beta1,
                   float beta2, float eps, void* stream) {
     if (!p || !g || !m || !v) return fail(SEM_ERR_ARG, "null array");
     if (t < 1) return fail(SEM_ERR_ARG, "Adam step count starts at 1");
@@ -294,6 +308,11 @@ int mlp_adam_step(float* p, const float* g, float* m, float* v, int t, float lr,
                        (hipStream_t)stream, p, g, m, v, lr, beta1, beta2, eps, c1, c2);
     HIPCHK(hipGetLastError());
     return SEM_OK;
+}
+
+int mlp_adam_step(float* p, const float* g, float* m, float* v, int t, float lr, float beta1,
+                  float beta2, float eps, void* stream) {
+    return sem::guarded("mlp_adam_step", [&] { return mlp_adam_step_impl(p, g, m, v, t, lr, beta1, beta2, eps, stream); });
 }
 
 }  // extern "C"

@@ -788,7 +788,7 @@ int sem_mesh_get_info(const sem_mesh* M, sem_mesh_info* o) {
     return SEM_OK;
 }
 
-int sem_mesh_coords(const sem_mesh* M, double* hxy, double* hhxy, double* z) {
+static int sem_mesh_coords_impl(const sem_mesh* M, double* hxy, double* hhxy, double* z) {
     if (!M) return fail(SEM_ERR_ARG, "null mesh");
     const sem::HostMesh& H = M->host;
     if (hxy) std::memcpy(hxy, H.h_xy.data(), H.h_xy.size() * sizeof(double));
@@ -797,7 +797,11 @@ int sem_mesh_coords(const sem_mesh* M, double* hxy, double* hhxy, double* z) {
     return SEM_OK;
 }
 
-int sem_mesh_set_reference(sem_mesh* M, const double* rho0, const double* theta0,
+int sem_mesh_coords(const sem_mesh* M, double* hxy, double* hhxy, double* z) {
+    return sem::guarded("sem_mesh_coords", [&] { return sem_mesh_coords_impl(M, hxy, hhxy, z); });
+}
+
+static int sem_mesh_set_reference_impl(sem_mesh* M, const double* rho0, const double* theta0,
                            const double* dth0) {
     if (!M || !rho0 || !theta0 || !dth0) return fail(SEM_ERR_ARG, "null argument");
     const sem::HostMesh& H = M->host;
@@ -824,6 +828,11 @@ int sem_mesh_set_reference(sem_mesh* M, const double* rho0, const double* theta0
     M->have_ref = true;
     ++M->epoch;
     return SEM_OK;
+}
+
+int sem_mesh_set_reference(sem_mesh* M, const double* rho0, const double* theta0,
+                           const double* dth0) {
+    return sem::guarded("sem_mesh_set_reference", [&] { return sem_mesh_set_reference_impl(M, rho0, theta0, dth0); });
 }
 
 static int sem_mesh_set_terrain_impl(sem_mesh* M, const double* zs, const double* rho0, const double* theta0,
@@ -967,7 +976,7 @@ int sem_mesh_set_terrain(sem_mesh* M, const double* zs, const double* rho0, cons
     return sem::guarded("sem_mesh_set_terrain", [&] { return sem_mesh_set_terrain_impl(M, zs, rho0, theta0, dth0); });
 }
 
-int sem_mesh_heights(const sem_mesh* M, const double* zs, double* z) {
+static int sem_mesh_heights_impl(const sem_mesh* M, const double* zs, double* z) {
     if (!M || !z) return fail(SEM_ERR_ARG, "null argument");
     const sem::HostMesh& H = M->host;
     const double z0 = H.z_edges.front(), top = H.z_edges.back(), depth = top - z0;
@@ -984,7 +993,11 @@ int sem_mesh_heights(const sem_mesh* M, const double* zs, double* z) {
     return SEM_OK;
 }
 
-int sem_nc_project(const sem_mesh* M, int dir, const double* src, double* dst, void* stream) {
+int sem_mesh_heights(const sem_mesh* M, const double* zs, double* z) {
+    return sem::guarded("sem_mesh_heights", [&] { return sem_mesh_heights_impl(M, zs, z); });
+}
+
+static int sem_nc_project_impl(const sem_mesh* M, int dir, const double* src, double* dst, void* stream) {
     if (!M) return fail(SEM_ERR_ARG, "null mesh");
     if (dir != SEM_SCATTER && dir != SEM_GATHER) return fail(SEM_ERR_ARG, "bad direction");
     const DevMesh& d = M->d;
@@ -999,14 +1012,22 @@ int sem_nc_project(const sem_mesh* M, int dir, const double* src, double* dst, v
     return SEM_OK;
 }
 
-int sem_rhs(const sem_mesh* M, const double* q, const double* hv, double* rE, int prec, void* stream) {
+int sem_nc_project(const sem_mesh* M, int dir, const double* src, double* dst, void* stream) {
+    return sem::guarded("sem_nc_project", [&] { return sem_nc_project_impl(M, dir, src, dst, stream); });
+}
+
+static int sem_rhs_impl(const sem_mesh* M, const double* q, const double* hv, double* rE, int prec, void* stream) {
     int rc = check_mesh(M);
     if (rc != SEM_OK) return rc;
     if (!q || !rE || (M->d.n_hh > 0 && !hv)) return fail(SEM_ERR_ARG, "null array");
     return sem_launch_rhs(M, q, hv, rE, prec, (hipStream_t)stream);
 }
 
-int sem_dss(const sem_mesh* M, int phase, const double* rE, double* acc, double* c, double* r,
+int sem_rhs(const sem_mesh* M, const double* q, const double* hv, double* rE, int prec, void* stream) {
+    return sem::guarded("sem_rhs", [&] { return sem_rhs_impl(M, q, hv, rE, prec, stream); });
+}
+
+static int sem_dss_impl(const sem_mesh* M, int phase, const double* rE, double* acc, double* c, double* r,
             void* stream) {
     if (!M) return fail(SEM_ERR_ARG, "null mesh");
     const DevMesh& d = M->d;
@@ -1028,7 +1049,12 @@ int sem_dss(const sem_mesh* M, int phase, const double* rE, double* acc, double*
     return SEM_OK;
 }
 
-int sem_stage_update(const sem_mesh* M, double a, double b, double c, const double* qn,
+int sem_dss(const sem_mesh* M, int phase, const double* rE, double* acc, double* c, double* r,
+            void* stream) {
+    return sem::guarded("sem_dss", [&] { return sem_dss_impl(M, phase, rE, acc, c, r, stream); });
+}
+
+static int sem_stage_update_impl(const sem_mesh* M, double a, double b, double c, const double* qn,
                      const double* qs, const double* r, double* qout, void* stream) {
     if (!M) return fail(SEM_ERR_ARG, "null mesh");
     if (!qn || !qs || !r || !qout) return fail(SEM_ERR_ARG, "null array");
@@ -1039,7 +1065,12 @@ int sem_stage_update(const sem_mesh* M, double a, double b, double c, const doub
     return SEM_OK;
 }
 
-int sem_stage(const sem_mesh* M, double a, double b, double c, const double* qn, const double* qs,
+int sem_stage_update(const sem_mesh* M, double a, double b, double c, const double* qn,
+                     const double* qs, const double* r, double* qout, void* stream) {
+    return sem::guarded("sem_stage_update", [&] { return sem_stage_update_impl(M, a, b, c, qn, qs, r, qout, stream); });
+}
+
+static int sem_stage_impl(const sem_mesh* M, double a, double b, double c, const double* qn, const double* qs,
               double* qout, int prec, void* stream) {
     int rc = check_mesh(M);
     if (rc != SEM_OK) return rc;
@@ -1054,7 +1085,12 @@ int sem_stage(const sem_mesh* M, double a, double b, double c, const double* qn,
     return SEM_OK;
 }
 
-int sem_mesh_set_dissipation(sem_mesh* M, double cs, double sponge_gamma, double sponge_depth) {
+int sem_stage(const sem_mesh* M, double a, double b, double c, const double* qn, const double* qs,
+              double* qout, int prec, void* stream) {
+    return sem::guarded("sem_stage", [&] { return sem_stage_impl(M, a, b, c, qn, qs, qout, prec, stream); });
+}
+
+static int sem_mesh_set_dissipation_impl(sem_mesh* M, double cs, double sponge_gamma, double sponge_depth) {
     if (!M) return fail(SEM_ERR_ARG, "null mesh");
     if (!(cs >= 0.0) || !(sponge_gamma >= 0.0) || (sponge_gamma > 0.0 && !(sponge_depth > 0.0)))
         return fail(SEM_ERR_ARG, "need Cs >= 0, sponge_gamma >= 0 and sponge_depth > 0");
@@ -1099,6 +1135,10 @@ int sem_mesh_set_dissipation(sem_mesh* M, double cs, double sponge_gamma, double
     d.rx = M->diss_r;
     ++M->epoch;
     return SEM_OK;
+}
+
+int sem_mesh_set_dissipation(sem_mesh* M, double cs, double sponge_gamma, double sponge_depth) {
+    return sem::guarded("sem_mesh_set_dissipation", [&] { return sem_mesh_set_dissipation_impl(M, cs, sponge_gamma, sponge_depth); });
 }
 
 static int sem_stage_set_layout_impl(sem_mesh* M, int layout, int param) {
@@ -1222,7 +1262,7 @@ int sem_mesh_get_epoch(const sem_mesh* M, int64_t* epoch) {
     return SEM_OK;
 }
 
-int amr_flag(const sem_mesh* M, const double* q, int criterion, const double* thr, int lvl_max,
+static int amr_flag_impl(const sem_mesh* M, const double* q, int criterion, const double* thr, int lvl_max,
              int8_t* ae, int8_t* ac, void* stream) {
     if (!M) return fail(SEM_ERR_ARG, "null mesh");
     if (!q || !ae || !ac) return fail(SEM_ERR_ARG, "null array");
@@ -1249,6 +1289,11 @@ int amr_flag(const sem_mesh* M, const double* q, int criterion, const double* th
     hipLaunchKernelGGL(sem::k_amr_col, dim3((d.n_col + 255) / 256), dim3(256), 0, s, d, ae, ac);
     HIPCHK(hipGetLastError());
     return SEM_OK;
+}
+
+int amr_flag(const sem_mesh* M, const double* q, int criterion, const double* thr, int lvl_max,
+             int8_t* ae, int8_t* ac, void* stream) {
+    return sem::guarded("amr_flag", [&] { return amr_flag_impl(M, q, criterion, thr, lvl_max, ae, ac, stream); });
 }
 
 // ------------------------------------------------------------ adaptation
@@ -1338,7 +1383,7 @@ int sem_transfer_create(const sem_mesh* from, const sem_mesh* to, sem_transfer**
     return sem::guarded("sem_transfer_create", [&] { return sem_transfer_create_impl(from, to, out); });
 }
 
-int sem_transfer_apply(const sem_transfer* X, const double* q_from, double* q_to, void* stream) {
+static int sem_transfer_apply_impl(const sem_transfer* X, const double* q_from, double* q_to, void* stream) {
     if (!X) return fail(SEM_ERR_ARG, "null transfer");
     if (!q_from || !q_to) return fail(SEM_ERR_ARG, "null array");
     if (q_from == q_to) return fail(SEM_ERR_ARG, "q_to must not alias q_from");
@@ -1350,6 +1395,10 @@ int sem_transfer_apply(const sem_transfer* X, const double* q_from, double* q_to
                        X->n_from, X->nzn, X->ldz, q_from, q_to);
     HIPCHK(hipGetLastError());
     return SEM_OK;
+}
+
+int sem_transfer_apply(const sem_transfer* X, const double* q_from, double* q_to, void* stream) {
+    return sem::guarded("sem_transfer_apply", [&] { return sem_transfer_apply_impl(X, q_from, q_to, stream); });
 }
 
 int sem_transfer_destroy(sem_transfer* X) {
