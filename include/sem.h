@@ -289,8 +289,9 @@ int sem_stage(const sem_mesh *mesh, double a, double b, double c,
 /* Work decomposition of sem_stage (chosen by the autotuner, or by hand):
  * layers_per_chunk = stacked elements handled by one workgroup, one thread per
  * unique node of the chunk ((N+1)^2 (layers_per_chunk N + 1) threads).
- * 0 = default (the deepest chunk of at most 512 threads).  Supported: 1, 2, 4,
- * 8 where the workgroup stays within 1024 threads and 64 KB of LDS.  Rebuilds
+ * 0 = default (the deepest chunk of at most 512 threads).  Supported: 1, 2, 4
+ * and 8 at N <= 4, 1, 2 and 4 at N = 5, 1 and 2 at N = 6, 7, and 1 at N = 8
+ * (workgroups within 1024 threads and a CU's 160 KB of LDS).  Rebuilds
  * the handle's fused tables and synchronises the device.  sem_stage_get_tune
  * reports the current value. */
 int sem_stage_tune(sem_mesh *mesh, int layers_per_chunk);

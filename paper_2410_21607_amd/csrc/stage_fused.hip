@@ -1092,7 +1092,9 @@ __global__ void k_stage_tail(DevMesh m, TailTables tl, double a, double b, doubl
     }
 }
 
-// (order, layers per chunk) instances with <= 1024 threads and <= 64 KB LDS
+// (order, layers per chunk) instances: at most 1024 threads and 117 KB of LDS
+// per workgroup (the largest: N = 7, two layers, with the sub-grid stress; a CU
+// has 160 KB)
 #define SEM_FUSED_INSTANCES(X) \
     X(1, 1) X(1, 2) X(1, 4) X(1, 8) \
     X(2, 1) X(2, 2) X(2, 4) X(2, 8) \
