@@ -113,3 +113,22 @@ def test_plan_rejects_bad_layouts(bad, code):
     msg = {"overlap": "overlap", "gap": "cover", "balance": "2:1", "order": "N must",
            "index": "out of range"}[bad]
     assert msg in str(ei.value)
+
+
+@pytest.mark.parametrize("name,kw", [("small_amr3", {}), ("small_amr3", {"periodic": False, "N": 5}),
+                                     ("small_amr2", {"N": 7}),
+                                     ("tstar_64x64x8_n4", {"level": 2, "amr": True})])
+def test_plan_independent_of_host_threads(name, kw, monkeypatch):
+    """The host build runs on several threads: numbering, hanging points and
+    assembled masses come out bit for bit the same at any thread count."""
+    _lib()
+    from paper_2410_21607_amd.api import sem_mesh_plan
+    c = cases.get(name, **kw)
+    outs = []
+    for t in ("1", "3", "8"):
+        monkeypatch.setenv("SEM_HOST_THREADS", t)
+        outs.append(sem_mesh_plan(c))
+    for o in outs[1:]:
+        assert o[0] == outs[0][0]
+        for a, b in zip(o[1:], outs[0][1:]):
+            assert np.array_equal(a, b)
