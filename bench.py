@@ -31,6 +31,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 WORKLOAD = "vortex_64x64x16_n4"
+# names of the sem_stage work layouts (SEM_LAYOUT_COLUMNS, _BLOCKS, _COLUMNS_KZ)
+LAYOUT_NAMES = {0: "columns", 1: "blocks", 2: "columns_kz"}
 METRIC = "GLL DOF-stage updates/s + AMR wall-time speedup at matched max-wind error"
 
 
@@ -585,7 +587,8 @@ def main():
                     help="case timed for the main line (default: the 64x64x16 N=4 bench workload)")
     ap.add_argument("--layout", default="auto",
                     help="work layout of the timed stage: auto (the autotuner's choice), "
-                         "columns:LAYERS_PER_CHUNK or blocks:SEGMENTS")
+                         "columns:LAYERS_PER_CHUNK, columns_kz:LAYERS_PER_CHUNK (FP64 threads in "
+                         "vertical-index order) or blocks:SEGMENTS")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
@@ -663,6 +666,7 @@ def main():
     else:
         kind, par = args.layout.split(":")
         api.sem_stage_set_layout(mesh, {"columns": api.SEM_LAYOUT_COLUMNS,
+                                        "columns_kz": api.SEM_LAYOUT_COLUMNS_KZ,
                                         "blocks": api.SEM_LAYOUT_BLOCKS}[kind], int(par))
     layout, layout_par = api.sem_stage_get_layout(mesh)
     lpc = api.sem_stage_get_tune(mesh)
@@ -729,9 +733,9 @@ def main():
                    "n_dof": int(n_dof), "local_points": int(mesh.n_local),
                    "step": "one SSP-RK3 stage (timed as HIP-graph replays of whole RK3 steps)",
                    "graph": not args.no_graph,
-                   "layout": ("columns" if layout == api.SEM_LAYOUT_COLUMNS else "blocks"),
-                   "layers_per_chunk" if layout == api.SEM_LAYOUT_COLUMNS else "segments":
-                       lpc if layout == api.SEM_LAYOUT_COLUMNS else layout_par,
+                   "layout": LAYOUT_NAMES[layout],
+                   "layers_per_chunk" if layout != api.SEM_LAYOUT_BLOCKS else "segments":
+                       lpc if layout != api.SEM_LAYOUT_BLOCKS else layout_par,
                    "finite": ok,
                    "dissipation": args.dissipation or "off"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

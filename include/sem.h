@@ -82,8 +82,9 @@ extern "C" {
 #define SEM_SCATTER 0     /* sem_nc_project: unique nodes -> hanging points  */
 #define SEM_GATHER  1     /* sem_nc_project: hanging points -> unique nodes  */
 
-#define SEM_LAYOUT_COLUMNS 0 /* sem_stage work layouts (sem_stage_set_layout) */
-#define SEM_LAYOUT_BLOCKS  1
+#define SEM_LAYOUT_COLUMNS    0 /* sem_stage work layouts (sem_stage_set_layout) */
+#define SEM_LAYOUT_BLOCKS     1
+#define SEM_LAYOUT_COLUMNS_KZ 2
 
 #define SEM_ASSEMBLE 0    /* sem_dss phases */
 #define SEM_FINALIZE 1
@@ -299,7 +300,12 @@ int sem_stage_get_tune(const sem_mesh *mesh, int *layers_per_chunk);
 
 /* Work layout of sem_stage (the LDS tile layout and workgroup packing):
  *   SEM_LAYOUT_COLUMNS: a workgroup per column, chunks of `param` layers
- *     (as sem_stage_tune; 0 = default);
+ *     (as sem_stage_tune; 0 = default); in FP64 the threads of the nodes on
+ *     the planes between stacked elements come first (they take two z
+ *     derivatives), in float the vertical index runs fastest;
+ *   SEM_LAYOUT_COLUMNS_KZ: the same with the vertical index fastest in FP64
+ *     too (fewer rows per wave in the global loads and stores, the second z
+ *     derivative spread over every wave); bit-identical results;
  *   SEM_LAYOUT_BLOCKS: a workgroup per 2 x 2 block of columns of one level
  *     (a sibling family, or four level-0 columns), a (2N+1)^2 tile per layer,
  *     the column in `param` vertical segments (0 = enough segments for about
@@ -316,9 +322,10 @@ int sem_stage_set_layout(sem_mesh *mesh, int layout, int param);
 int sem_stage_get_layout(const sem_mesh *mesh, int *layout, int *param);
 
 /* Autotuner: times every supported work layout on this mesh (the column
- * layout at each supported layers_per_chunk, the block layout at 1, 2, 4, ...
- * vertical segments; reps fused stages each, HIP events on `stream`, d_qout
- * used as scratch), keeps the fastest with sem_stage_set_layout, and reports
+ * layout at each supported layers_per_chunk, in FP64 in both thread orders,
+ * the block layout at 1, 2, 4, ... vertical segments; reps fused stages
+ * each, HIP events on `stream`, d_qout used as scratch), keeps the fastest
+ * with sem_stage_set_layout, and reports
  * it (*best_lpc = the column layout's layers per chunk, see
  * sem_stage_get_layout for the layout; *best_ms = mean stage time in ms;
  * either may be NULL).  Synchronises the stream. */

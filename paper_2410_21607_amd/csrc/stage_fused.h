@@ -27,6 +27,8 @@ struct FusedTables {
     const uint8_t* first;       // per (column, position)
     double* cH;                 // hanging-point contributions [F][n_hh][nzn]
     int layers_per_chunk;       // layers handled together by one workgroup step
+    int kz_order;               // FP64 thread order: 1 = vertical index fastest,
+                                // 0 = nodes of the planes between elements first
     // Position map and interpolation rows the kernel reads (the mesh's own,
     // extended when the plan has side columns).  Side columns (the columns
     // of the small colour classes of an uneven mesh) run in the first
@@ -80,7 +82,7 @@ struct FusedPlan {
     std::vector<int32_t> color_ptr_host;
     TailTables tail{};                    // column layout with side columns
     bool has_tail = false;
-    int layout = 0;                       // SEM_LAYOUT_COLUMNS or SEM_LAYOUT_BLOCKS
+    int layout = 0;                       // SEM_LAYOUT_COLUMNS, _COLUMNS_KZ or _BLOCKS
     BlockTables bt{};                     // block layout
     FusedTables ts{};                     // block layout: the columns in no block
     std::vector<int32_t> blk_ptr_host, single_ptr_host;   // per colour
@@ -88,7 +90,8 @@ struct FusedPlan {
     std::vector<void*> allocs;
     int64_t bytes = 0;
 };
-// layout SEM_LAYOUT_COLUMNS: param = layers per chunk (0 = default);
+// layout SEM_LAYOUT_COLUMNS / SEM_LAYOUT_COLUMNS_KZ: param = layers per chunk
+// (0 = default);
 // SEM_LAYOUT_BLOCKS: param = vertical segments (0 = default)
 int fused_plan_build(const HostMesh& H, int layout, int param, FusedPlan& plan);
 void fused_plan_free(FusedPlan& plan);

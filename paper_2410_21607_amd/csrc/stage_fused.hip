@@ -90,7 +90,7 @@ __device__ __forceinline__ double pow1p_minus1(const DevMesh& m, double x) {
 // factor, hanging positions through their rows) and the vertical one.
 // Hanging positions take the coarse face's interpolant of zs and of the
 // reference state (host tables), so the mesh stays watertight.
-template <int NP, int LPC, typename T, bool TER, bool DISS>
+template <int NP, int LPC, typename T, bool TER, bool DISS, bool KZ>
 __global__ void __launch_bounds__(((NP * NP * (LPC * (NP - 1) + 1) + 63) / 64) * 64, DISS ? 2 : 4)
 k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double b, double c,
                 const double* __restrict__ qn, const double* __restrict__ qs,
@@ -160,18 +160,20 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
     const int item = xcd * (G >> 3) + min(xcd, G & 7) + rr;
     const int col = ft.col_order[col0 + min(item, ncol - 1)];
 
-    // Thread -> node of the chunk.  FP64: nodes on the planes between two
+    // Thread -> node of the chunk.  KZ (and always in float): the natural
+    // order, kzl fastest within a position, so that the global loads and
+    // stores of a wave cover few rows and lines; every wave then carries the
+    // same LDS load.  Otherwise (FP64): nodes on the planes between two
     // stacked elements (LPC-1 per position, two z derivatives each) come
     // first, so that they fill waves of their own instead of making every
     // wave run a second pass of FP64 z derivatives with most lanes masked,
     // and so that these longest waves are the oldest, which issue first;
     // nodes inside an element or on the chunk's bottom/top follow (RG per
-    // position).  Float: the natural order (kzl fastest within a position); the
-    // masked second pass is cheap at the float rate, and every wave then
-    // carries the same LDS load, so no wave waits long at the barriers.
+    // position).  Which order is faster depends on the order, the chunk depth
+    // and the terms (the autotuner times both).
     constexpr int RG = LPC * (N - 1) + 2;
     int kzl, p;
-    if constexpr (sizeof(T) == 4) {
+    if constexpr (sizeof(T) == 4 || KZ) {
         p = tid < NP2 * NK ? tid / NK : NP2;
         kzl = tid < NP2 * NK ? tid - p * NK : 0;
     } else {
@@ -1105,21 +1107,33 @@ __global__ void k_stage_tail(DevMesh m, TailTables tl, double a, double b, doubl
     X(7, 1) X(7, 2)                 \
     X(8, 1)
 
-template <typename T, bool TER, bool DISS = false>
-int launch_t(const DevMesh& m, const FusedTables& t, int col0, int ncol, double a, double b,
+template <typename T, bool TER, bool DISS, bool KZ>
+int launch_k(const DevMesh& m, const FusedTables& t, int col0, int ncol, double a, double b,
              double c, const double* qn, const double* qs, double* qo, hipStream_t s) {
     switch (m.N * 32 + t.layers_per_chunk) {
-#define CASE(NN, LP)                                                                    \
-    case NN * 32 + LP:                                                                  \
-        hipLaunchKernelGGL((k_stage_columns<NN + 1, LP, T, TER, DISS>), dim3(ncol),     \
-                           dim3(wg_threads<NN + 1, LP>()), 0, s, m, t, col0, ncol, a, b, \
-                           c, qn, qs, qo);                                              \
+#define CASE(NN, LP)                                                                      \
+    case NN * 32 + LP:                                                                    \
+        hipLaunchKernelGGL((k_stage_columns<NN + 1, LP, T, TER, DISS, KZ>), dim3(ncol),   \
+                           dim3(wg_threads<NN + 1, LP>()), 0, s, m, t, col0, ncol, a, b,   \
+                           c, qn, qs, qo);                                                \
         break;
         SEM_FUSED_INSTANCES(CASE)
 #undef CASE
         default: return SEM_ERR_ARG;
     }
     return (hipGetLastError() == hipSuccess) ? SEM_OK : SEM_ERR_HIP;
+}
+
+// the float instances always take the natural thread order
+template <typename T, bool TER, bool DISS = false>
+int launch_t(const DevMesh& m, const FusedTables& t, int col0, int ncol, double a, double b,
+             double c, const double* qn, const double* qs, double* qo, hipStream_t s) {
+    if constexpr (sizeof(T) == 4)
+        return launch_k<T, TER, DISS, true>(m, t, col0, ncol, a, b, c, qn, qs, qo, s);
+    else if (t.kz_order)
+        return launch_k<T, TER, DISS, true>(m, t, col0, ncol, a, b, c, qn, qs, qo, s);
+    else
+        return launch_k<T, TER, DISS, false>(m, t, col0, ncol, a, b, c, qn, qs, qo, s);
 }
 
 }  // namespace
@@ -1173,7 +1187,8 @@ std::vector<int32_t> colour_units(const HostMesh& H, const std::vector<int32_t>&
 
 int fused_plan_build(const HostMesh& H, int layout, int param, FusedPlan& P) {
     const int np2 = H.np1 * H.np1;
-    int lpc = layout == SEM_LAYOUT_COLUMNS ? param : 0;
+    const bool columns = layout == SEM_LAYOUT_COLUMNS || layout == SEM_LAYOUT_COLUMNS_KZ;
+    int lpc = columns ? param : 0;
     if (lpc < 1) {
         // default: the deepest supported chunk of at most 512 threads
         lpc = 1;
@@ -1181,7 +1196,7 @@ int fused_plan_build(const HostMesh& H, int layout, int param, FusedPlan& P) {
     }
     if (!fused_lpc_supported(H.N, lpc)) return SEM_ERR_ARG;
     if (layout == SEM_LAYOUT_BLOCKS && !fused_blocks_supported(H)) return SEM_ERR_ARG;
-    if (layout != SEM_LAYOUT_COLUMNS && layout != SEM_LAYOUT_BLOCKS) return SEM_ERR_ARG;
+    if (!columns && layout != SEM_LAYOUT_BLOCKS) return SEM_ERR_ARG;
     auto up = [&](const void* src, size_t bytes, void** dst) -> int {
         *dst = nullptr;
         if (bytes == 0) return SEM_OK;
@@ -1357,10 +1372,11 @@ int fused_plan_build(const HostMesh& H, int layout, int param, FusedPlan& P) {
         P.tail.cH = P.t.cH;
         P.t.n_color = n_color;
         P.t.layers_per_chunk = lpc;
+        P.t.kz_order = layout == SEM_LAYOUT_COLUMNS_KZ ? 1 : 0;
         P.color_ptr_host = cptr;
     }
-    P.layout = SEM_LAYOUT_COLUMNS;
-    if (layout == SEM_LAYOUT_COLUMNS) return SEM_OK;
+    P.layout = layout == SEM_LAYOUT_COLUMNS_KZ ? SEM_LAYOUT_COLUMNS_KZ : SEM_LAYOUT_COLUMNS;
+    if (columns) return SEM_OK;
 
     // ---- block layout: units are the 2 x 2 blocks and the columns in no block
     const int N = H.N, PX = 2 * N + 1, PP = PX * PX;
@@ -1465,6 +1481,7 @@ int fused_plan_build(const HostMesh& H, int layout, int param, FusedPlan& P) {
     P.ts.first = static_cast<const uint8_t*>(d);
     P.ts.color_ptr = nullptr;
     P.ts.n_color = n_color;
+    P.ts.kz_order = 0;
     P.blk_ptr_host = bptr;
     P.single_ptr_host = sptr;
     P.n_unit_color = n_color;
@@ -1497,7 +1514,7 @@ int launch_blocks(const DevMesh& m, const BlockTables& bt, int b0, int nblk, int
 }
 
 bool fused_dissipation_inline(const DevMesh& m, const FusedPlan& P, int prec) {
-    return (m.cs > 0.0 || m.sponge) && !m.zs && prec == SEM_FP64 && P.layout == SEM_LAYOUT_COLUMNS;
+    return (m.cs > 0.0 || m.sponge) && !m.zs && prec == SEM_FP64 && P.layout != SEM_LAYOUT_BLOCKS;
 }
 
 int fused_stage_launch(const DevMesh& m_in, const FusedPlan& P, double a, double b, double c,

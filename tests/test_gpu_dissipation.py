@@ -90,7 +90,8 @@ def test_dissipation_matches_oracle(name, kw):
     f = lambda s: assembly.rhs(om, s, ref, phys)
     want, _ = timestep.run_stages(f, q, c["dt"], 3)
     fused_on = {}
-    for lay in ((api.SEM_LAYOUT_COLUMNS, 2), (api.SEM_LAYOUT_BLOCKS, 1)):
+    for lay in ((api.SEM_LAYOUT_COLUMNS, 2), (api.SEM_LAYOUT_COLUMNS_KZ, 2),
+                (api.SEM_LAYOUT_BLOCKS, 1)):
         try:
             api.sem_stage_set_layout(gm, *lay)
         except native.SemError:

@@ -119,9 +119,13 @@ def test_terrain_rhs_matches_oracle_every_chunk_depth(name, kw, shape, periodic)
         except Exception:
             continue                               # no instance at this order
         say("terrain rhs", name, kw, shape, "lpc", lpc)
-        err = metrics.rel_l2(S.gpu_rhs(), want, metrics.RHS_FLOORS)
+        got = S.gpu_rhs()
+        err = metrics.rel_l2(got, want, metrics.RHS_FLOORS)
         say("  rel", err)
         assert err.max() <= TOL64
+        # the other FP64 thread order: the same values, bit for bit
+        S.api.sem_stage_set_layout(S.gm, S.api.SEM_LAYOUT_COLUMNS_KZ, lpc)
+        assert np.array_equal(S.gpu_rhs(), got)
         tried += 1
     assert tried >= 2
 
