@@ -31,8 +31,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 WORKLOAD = "vortex_64x64x16_n4"
-# names of the sem_stage work layouts (SEM_LAYOUT_COLUMNS, _BLOCKS, _COLUMNS_KZ)
-LAYOUT_NAMES = {0: "columns", 1: "blocks", 2: "columns_kz"}
+# names of the sem_stage work layouts (SEM_LAYOUT_COLUMNS, _BLOCKS, _COLUMNS_KZ, _COLUMNS_SPLIT)
+LAYOUT_NAMES = {0: "columns", 1: "blocks", 2: "columns_kz", 3: "columns_split"}
 METRIC = "GLL DOF-stage updates/s + AMR wall-time speedup at matched max-wind error"
 
 
@@ -588,7 +588,8 @@ def main():
     ap.add_argument("--layout", default="auto",
                     help="work layout of the timed stage: auto (the autotuner's choice), "
                          "columns:LAYERS_PER_CHUNK, columns_kz:LAYERS_PER_CHUNK (FP64 threads in "
-                         "vertical-index order) or blocks:SEGMENTS")
+                         "vertical-index order), columns_split:LAYERS_PER_CHUNK (a thread per element "
+                         "and local node) or blocks:SEGMENTS")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
@@ -667,6 +668,7 @@ def main():
         kind, par = args.layout.split(":")
         api.sem_stage_set_layout(mesh, {"columns": api.SEM_LAYOUT_COLUMNS,
                                         "columns_kz": api.SEM_LAYOUT_COLUMNS_KZ,
+                                        "columns_split": api.SEM_LAYOUT_COLUMNS_SPLIT,
                                         "blocks": api.SEM_LAYOUT_BLOCKS}[kind], int(par))
     layout, layout_par = api.sem_stage_get_layout(mesh)
     lpc = api.sem_stage_get_tune(mesh)

@@ -85,6 +85,7 @@ extern "C" {
 #define SEM_LAYOUT_COLUMNS    0 /* sem_stage work layouts (sem_stage_set_layout) */
 #define SEM_LAYOUT_BLOCKS     1
 #define SEM_LAYOUT_COLUMNS_KZ 2
+#define SEM_LAYOUT_COLUMNS_SPLIT 3
 
 #define SEM_ASSEMBLE 0    /* sem_dss phases */
 #define SEM_FINALIZE 1
@@ -305,7 +306,15 @@ int sem_stage_get_tune(const sem_mesh *mesh, int *layers_per_chunk);
  *     derivatives), in float the vertical index runs fastest;
  *   SEM_LAYOUT_COLUMNS_KZ: the same with the vertical index fastest in FP64
  *     too (fewer rows per wave in the global loads and stores, the second z
- *     derivative spread over every wave); bit-identical results;
+ *     derivative spread over every wave);
+ *   SEM_LAYOUT_COLUMNS_SPLIT: in FP64 a thread per (element, local node) of
+ *     each position, so that each thread takes one element's z derivatives
+ *     and a node between two elements has two threads (the lower hands its
+ *     part to the upper by a wave shuffle); needs param >= 2 and every such
+ *     pair in one wave (otherwise SEM_ERR_ARG); float runs the natural order.
+ *   The three column orders give bit-identical results without the optional
+ *   dissipation (with it, the split order sums the absorbing-layer and stress
+ *   parts of a plane node in another order, within 1e-14);
  *   SEM_LAYOUT_BLOCKS: a workgroup per 2 x 2 block of columns of one level
  *     (a sibling family, or four level-0 columns), a (2N+1)^2 tile per layer,
  *     the column in `param` vertical segments (0 = enough segments for about
@@ -322,7 +331,7 @@ int sem_stage_set_layout(sem_mesh *mesh, int layout, int param);
 int sem_stage_get_layout(const sem_mesh *mesh, int *layout, int *param);
 
 /* Autotuner: times every supported work layout on this mesh (the column
- * layout at each supported layers_per_chunk, in FP64 in both thread orders,
+ * layout at each supported layers_per_chunk, in FP64 in each thread order,
  * the block layout at 1, 2, 4, ... vertical segments; reps fused stages
  * each, HIP events on `stream`, d_qout used as scratch), keeps the fastest
  * with sem_stage_set_layout, and reports

@@ -316,7 +316,7 @@ def sem_stage_get_tune(mesh):
     return a.value
 
 
-SEM_LAYOUT_COLUMNS, SEM_LAYOUT_BLOCKS, SEM_LAYOUT_COLUMNS_KZ = 0, 1, 2
+SEM_LAYOUT_COLUMNS, SEM_LAYOUT_BLOCKS, SEM_LAYOUT_COLUMNS_KZ, SEM_LAYOUT_COLUMNS_SPLIT = 0, 1, 2, 3
 
 
 def sem_stage_set_layout(mesh, layout, param=0):

@@ -1143,12 +1143,15 @@ int sem_mesh_set_dissipation(sem_mesh* M, double cs, double sponge_gamma, double
 
 static int sem_stage_set_layout_impl(sem_mesh* M, int layout, int param) {
     if (!M) return fail(SEM_ERR_ARG, "null mesh");
-    const bool columns = layout == SEM_LAYOUT_COLUMNS || layout == SEM_LAYOUT_COLUMNS_KZ;
+    const bool columns = layout == SEM_LAYOUT_COLUMNS || layout == SEM_LAYOUT_COLUMNS_KZ ||
+                         layout == SEM_LAYOUT_COLUMNS_SPLIT;
     if (!columns && layout != SEM_LAYOUT_BLOCKS)
         return fail(SEM_ERR_ARG, "unknown layout");
     if (param < 0) return fail(SEM_ERR_ARG, "negative layout parameter");
     if (columns && param > 0 && !sem::fused_lpc_supported(M->host.N, param))
         return fail(SEM_ERR_ARG, "unsupported layers_per_chunk for this order");
+    if (layout == SEM_LAYOUT_COLUMNS_SPLIT && param > 0 && !sem::fused_split_supported(M->host.N, param))
+        return fail(SEM_ERR_ARG, "the split-element order needs two or more layers per chunk");
     if (layout == SEM_LAYOUT_BLOCKS && !sem::fused_blocks_supported(M->host))
         return fail(SEM_ERR_ARG, "no block layout for this mesh (order 3 to 5 with 2 x 2 column blocks)");
     sem::FusedPlan P;
@@ -1197,13 +1200,17 @@ static int sem_stage_autotune_impl(sem_mesh* M, const double* qn, const double* 
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
     // candidates: single columns in chunks of 1, 2, 4, 8 layers, in FP64 in
-    // both thread orders (float runs the natural order in either); column
+    // each thread order (float runs the natural order in any); column
     // blocks in 1, 2, 4, ... vertical segments (distinct segment lengths)
     std::vector<std::pair<int, int>> cand;
     for (int lpc = 1; lpc <= 16; lpc *= 2)
         if (sem::fused_lpc_supported(M->host.N, lpc) && lpc <= 2 * M->host.n_z) {
             cand.push_back({SEM_LAYOUT_COLUMNS, lpc});
-            if (prec == SEM_FP64) cand.push_back({SEM_LAYOUT_COLUMNS_KZ, lpc});
+            if (prec == SEM_FP64) {
+                cand.push_back({SEM_LAYOUT_COLUMNS_KZ, lpc});
+                if (sem::fused_split_supported(M->host.N, lpc))
+                    cand.push_back({SEM_LAYOUT_COLUMNS_SPLIT, lpc});
+            }
         }
     if (sem::fused_blocks_supported(M->host) && !M->d.zs) {
         int last_ls = -1;

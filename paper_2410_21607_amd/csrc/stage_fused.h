@@ -27,8 +27,9 @@ struct FusedTables {
     const uint8_t* first;       // per (column, position)
     double* cH;                 // hanging-point contributions [F][n_hh][nzn]
     int layers_per_chunk;       // layers handled together by one workgroup step
-    int kz_order;               // FP64 thread order: 1 = vertical index fastest,
-                                // 0 = nodes of the planes between elements first
+    int thread_order;           // FP64 thread order: 0 = nodes of the planes between
+                                // elements first, 1 = vertical index fastest,
+                                // 2 = split element
     // Position map and interpolation rows the kernel reads (the mesh's own,
     // extended when the plan has side columns).  Side columns (the columns
     // of the small colour classes of an uneven mesh) run in the first
@@ -82,7 +83,7 @@ struct FusedPlan {
     std::vector<int32_t> color_ptr_host;
     TailTables tail{};                    // column layout with side columns
     bool has_tail = false;
-    int layout = 0;                       // SEM_LAYOUT_COLUMNS, _COLUMNS_KZ or _BLOCKS
+    int layout = 0;                       // SEM_LAYOUT_COLUMNS, _COLUMNS_KZ, _COLUMNS_SPLIT or _BLOCKS
     BlockTables bt{};                     // block layout
     FusedTables ts{};                     // block layout: the columns in no block
     std::vector<int32_t> blk_ptr_host, single_ptr_host;   // per colour
@@ -90,12 +91,15 @@ struct FusedPlan {
     std::vector<void*> allocs;
     int64_t bytes = 0;
 };
-// layout SEM_LAYOUT_COLUMNS / SEM_LAYOUT_COLUMNS_KZ: param = layers per chunk
-// (0 = default);
+// layout SEM_LAYOUT_COLUMNS / _COLUMNS_KZ / _COLUMNS_SPLIT: param = layers per
+// chunk (0 = default);
 // SEM_LAYOUT_BLOCKS: param = vertical segments (0 = default)
 int fused_plan_build(const HostMesh& H, int layout, int param, FusedPlan& plan);
 void fused_plan_free(FusedPlan& plan);
 bool fused_lpc_supported(int N, int layers_per_chunk);
+// whether the split-element thread order applies (two or more layers per
+// chunk, every pair of threads of a plane node in one wave)
+bool fused_split_supported(int N, int layers_per_chunk);
 bool fused_blocks_supported(const HostMesh& H);
 
 // Whether sem_stage evaluates the optional dissipation inside the column

@@ -46,9 +46,38 @@ namespace {
 constexpr int NF = SEM_NFIELDS;
 // LDS tiles: rho u, rho v, rho w and u singly; (v, w) and (p', theta') as pairs
 
-template <int NP, int LPC>
+template <int NP, int LPC, bool SE = false>
 constexpr int wg_threads() {
-    return ((NP * NP * (LPC * (NP - 1) + 1) + 63) / 64) * 64;
+    return ((NP * NP * (SE ? LPC * NP : LPC * (NP - 1) + 1) + 63) / 64) * 64;
+}
+
+// Split-element thread order: a thread per (element, local node) of each
+// position, so that a node on the plane between two stacked elements has two
+// threads, each taking one element's z derivatives.  The lower one hands its
+// part to the upper one (the next lane) by a shuffle, so every such pair must
+// sit in one wave.
+template <int NP, int LPC>
+constexpr bool se_pairs_in_wave() {
+    for (int p = 0; p < NP * NP; ++p)
+        for (int el = 1; el < LPC; ++el)
+            if ((p * LPC * NP + el * NP) % 64 == 0) return false;
+    return true;
+}
+// Thread orders of the column kernel: 0 = the nodes of the planes between
+// stacked elements first, 1 = natural (vertical index fastest), 2 = split
+// element.  The order an instance actually runs: float always takes the
+// natural one, and so does the split order where it does not apply (one
+// layer per chunk, or a pair across two waves).
+template <int NP, int LPC, typename T, int ORD>
+constexpr int eff_order() {
+    if (sizeof(T) == 4) return 1;
+    if (ORD == 2 && !(LPC > 1 && se_pairs_in_wave<NP, LPC>())) return 1;
+    return ORD;
+}
+// threads of a column-kernel workgroup
+template <int NP, int LPC, int ORD>
+constexpr int col_threads() {
+    return wg_threads<NP, LPC, ORD == 2>();
 }
 
 // (1+x)^gamma - 1 for the ideal-gas pressure ratio.  For |x| <= 1/64 the
@@ -90,14 +119,15 @@ __device__ __forceinline__ double pow1p_minus1(const DevMesh& m, double x) {
 // factor, hanging positions through their rows) and the vertical one.
 // Hanging positions take the coarse face's interpolant of zs and of the
 // reference state (host tables), so the mesh stays watertight.
-template <int NP, int LPC, typename T, bool TER, bool DISS, bool KZ>
-__global__ void __launch_bounds__(((NP * NP * (LPC * (NP - 1) + 1) + 63) / 64) * 64, DISS ? 2 : 4)
+template <int NP, int LPC, typename T, bool TER, bool DISS, int ORD>
+__global__ void __launch_bounds__((col_threads<NP, LPC, ORD>()), DISS ? 2 : 4)
 k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double b, double c,
                 const double* __restrict__ qn, const double* __restrict__ qs,
                 double* __restrict__ qo) {
     constexpr int NP2 = NP * NP, N = NP - 1;
     constexpr int NK = LPC * N + 1;               // vertical nodes of a full chunk
-    constexpr int WGT = wg_threads<NP, LPC>();
+    constexpr bool SE = ORD == 2;
+    constexpr int WGT = wg_threads<NP, LPC, SE>();
     __shared__ T tile[4][NP2 * NK];               // rho u, rho v, rho w, u: [field][p][kzl], kzl fastest
     __shared__ double carry[2][NF][NP2];
     __shared__ T sD[NP2];
@@ -173,7 +203,15 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
     // and the terms (the autotuner times both).
     constexpr int RG = LPC * (N - 1) + 2;
     int kzl, p;
-    if constexpr (sizeof(T) == 4 || KZ) {
+    int el_t = 0, kk_t = 0;                       // SE: the thread's element and local node
+    if constexpr (SE) {
+        constexpr int NE = LPC * NP;
+        p = tid < NP2 * NE ? tid / NE : NP2;
+        const int r = tid < NP2 * NE ? tid - p * NE : 0;
+        el_t = r / NP;
+        kk_t = r - el_t * NP;
+        kzl = el_t * N + kk_t;
+    } else if constexpr (ORD == 1) {
         p = tid < NP2 * NK ? tid / NK : NP2;
         kzl = tid < NP2 * NK ? tid - p * NK : 0;
     } else {
@@ -265,7 +303,14 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
         const int L0 = ch * LPC;
         const int L1 = min(L0 + LPC, m.n_z);
         const int nk = (L1 - L0) * N + 1;
-        const bool active = lane_ok && (kzl < nk);
+        bool active = lane_ok && (kzl < nk);
+        // SE: the lower thread of a plane between two elements of the chunk
+        // only computes (dupe); the node's other work is its upper thread's
+        bool dupe = false;
+        if constexpr (SE) {
+            active = lane_ok && el_t < L1 - L0;
+            dupe = kk_t == N && el_t + 1 < L1 - L0;
+        }
         const int kz = L0 * N + kzl;
         const int lidx = pc * NK + kzl;
         double qv[NF] = {0, 0, 0, 0, 0};
@@ -305,6 +350,7 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
             }
             rho = T(r0d) + T(qv[0]);
             const T u = T(qv[1]), v = T(qv[2]), w = T(qv[3]);
+            if (!dupe) {
             tile[0][lidx] = rho * u;
             tile[1][lidx] = rho * v;
             tile[2][lidx] = rho * w;
@@ -328,12 +374,13 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
                 pt.y = T(qv[4]);
                 tpr[1][lidx] = pt;
             }
+            }
         }
         __syncthreads();
         // update base of the nodes finished in this chunk (q^n for the first
         // contributor, not read when a = 0; the partial q_out for later colours)
         double base[NF] = {0, 0, 0, 0, 0};
-        if (!TER && active && g >= 0 && !(kzl == nk - 1 && L1 < m.n_z) && (!first || a != 0.0)) {
+        if (!TER && active && !dupe && g >= 0 && !(kzl == nk - 1 && L1 < m.n_z) && (!first || a != 0.0)) {
             const double* bp = first ? qn : qo;
             const int64_t o = s_row[pc] + kz;
 #pragma unroll
@@ -346,8 +393,8 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
         // needs those registers for its metric terms)
         if (!TER && ch + 1 < n_chunk && lane_ok && g >= 0) {
             const int L0n = L0 + LPC;
-            const int nkn = (min(L0n + LPC, m.n_z) - L0n) * N + 1;
-            if (kzl < nkn) {
+            const int neln = min(L0n + LPC, m.n_z) - L0n;
+            if (SE ? el_t < neln : kzl < neln * N + 1) {
                 const int64_t o = s_row[pc] + L0n * N + kzl;
 #pragma unroll
                 for (int f = 0; f < NF; ++f) pf[f] = qs[f * fs + o];
@@ -431,8 +478,8 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
             }
             // elements of this chunk holding the node: (element, local k)
             const bool inner_plane = (kzl % N == 0) && kzl > 0 && kzl < nk - 1;
-            const int e_first = (kzl == nk - 1) ? (kzl - 1) / N : (inner_plane ? kzl / N - 1 : kzl / N);
-            const int n_el = inner_plane ? 2 : 1;
+            const int e_first = SE ? el_t : (kzl == nk - 1) ? (kzl - 1) / N : (inner_plane ? kzl / N - 1 : kzl / N);
+            const int n_el = (!SE && inner_plane) ? 2 : 1;
             for (int s2 = 0; s2 < n_el; ++s2) {
                 const int el = e_first + s2;
                 const int kk = kzl - el * N;
@@ -512,8 +559,13 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
                     R[4] = Rh[4] - w * z3;
                 }
                 const double mass = s_mij[pc] * sW[kk] * dzl;
+                {
+                    // each element's part rounded on its own (no fused
+                    // multiply-add into the sum), as the split order forms it
+#pragma clang fp contract(off)
 #pragma unroll
-                for (int fl = 0; fl < NF; ++fl) acc[fl] += mass * double(R[fl]);
+                    for (int fl = 0; fl < NF; ++fl) acc[fl] += mass * double(R[fl]);
+                }
                 if constexpr (DISS) {
                     // absorbing layer: -R(z) q' for every field
                     if (m.sponge) {
@@ -530,8 +582,8 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
             __syncthreads();
             if (active && m.cs > 0.0) {
                 const bool inner_plane = (kzl % N == 0) && kzl > 0 && kzl < nk - 1;
-                const int e_first = (kzl == nk - 1) ? (kzl - 1) / N : (inner_plane ? kzl / N - 1 : kzl / N);
-                const int n_el = inner_plane ? 2 : 1;
+                const int e_first = SE ? el_t : (kzl == nk - 1) ? (kzl - 1) / N : (inner_plane ? kzl / N - 1 : kzl / N);
+                const int n_el = (!SE && inner_plane) ? 2 : 1;
                 for (int s2 = 0; s2 < n_el; ++s2) {
                     const int el = e_first + s2;
                     const int kk = kzl - el * N;
@@ -557,8 +609,17 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
                 }
             }
         }
+        // SE: the lower element's part of a plane node, from the previous
+        // lane (summed in the order of the other thread orders)
+        if constexpr (SE) {
+#pragma unroll
+            for (int fl = 0; fl < NF; ++fl) {
+                const double lo = __shfl_up(acc[fl], 1);
+                if (active && kk_t == 0 && el_t > 0) acc[fl] = lo + acc[fl];
+            }
+        }
         // the carry of the chunk's top plane, or the node's update
-        if (active) {
+        if (active && !dupe) {
             if (kzl == nk - 1 && L1 < m.n_z) {
                 // top plane of the chunk: finished by the next chunk
 #pragma unroll
@@ -1107,15 +1168,16 @@ __global__ void k_stage_tail(DevMesh m, TailTables tl, double a, double b, doubl
     X(7, 1) X(7, 2)                 \
     X(8, 1)
 
-template <typename T, bool TER, bool DISS, bool KZ>
+template <typename T, bool TER, bool DISS, int ORD>
 int launch_k(const DevMesh& m, const FusedTables& t, int col0, int ncol, double a, double b,
              double c, const double* qn, const double* qs, double* qo, hipStream_t s) {
     switch (m.N * 32 + t.layers_per_chunk) {
-#define CASE(NN, LP)                                                                      \
-    case NN * 32 + LP:                                                                    \
-        hipLaunchKernelGGL((k_stage_columns<NN + 1, LP, T, TER, DISS, KZ>), dim3(ncol),   \
-                           dim3(wg_threads<NN + 1, LP>()), 0, s, m, t, col0, ncol, a, b,   \
-                           c, qn, qs, qo);                                                \
+#define CASE(NN, LP)                                                                        \
+    case NN * 32 + LP:                                                                      \
+        hipLaunchKernelGGL((k_stage_columns<NN + 1, LP, T, TER, DISS,                       \
+                                            eff_order<NN + 1, LP, T, ORD>()>),              \
+                           dim3(ncol), dim3(col_threads<NN + 1, LP, eff_order<NN + 1, LP, T, ORD>()>()), \
+                           0, s, m, t, col0, ncol, a, b, c, qn, qs, qo);                    \
         break;
         SEM_FUSED_INSTANCES(CASE)
 #undef CASE
@@ -1129,11 +1191,13 @@ template <typename T, bool TER, bool DISS = false>
 int launch_t(const DevMesh& m, const FusedTables& t, int col0, int ncol, double a, double b,
              double c, const double* qn, const double* qs, double* qo, hipStream_t s) {
     if constexpr (sizeof(T) == 4)
-        return launch_k<T, TER, DISS, true>(m, t, col0, ncol, a, b, c, qn, qs, qo, s);
-    else if (t.kz_order)
-        return launch_k<T, TER, DISS, true>(m, t, col0, ncol, a, b, c, qn, qs, qo, s);
+        return launch_k<T, TER, DISS, 1>(m, t, col0, ncol, a, b, c, qn, qs, qo, s);
+    else if (t.thread_order == 2)
+        return launch_k<T, TER, DISS, 2>(m, t, col0, ncol, a, b, c, qn, qs, qo, s);
+    else if (t.thread_order == 1)
+        return launch_k<T, TER, DISS, 1>(m, t, col0, ncol, a, b, c, qn, qs, qo, s);
     else
-        return launch_k<T, TER, DISS, false>(m, t, col0, ncol, a, b, c, qn, qs, qo, s);
+        return launch_k<T, TER, DISS, 0>(m, t, col0, ncol, a, b, c, qn, qs, qo, s);
 }
 
 }  // namespace
@@ -1145,6 +1209,15 @@ bool fused_lpc_supported(int N, int lpc) {
 #undef CASE
         default: return false;
     }
+}
+
+bool fused_split_supported(int N, int lpc) {
+    if (!fused_lpc_supported(N, lpc) || lpc < 2) return false;
+    const int np = N + 1;
+    for (int p = 0; p < np * np; ++p)
+        for (int el = 1; el < lpc; ++el)
+            if ((p * lpc * np + el * np) % 64 == 0) return false;
+    return true;
 }
 
 bool fused_blocks_supported(const HostMesh& H) {
@@ -1187,7 +1260,8 @@ std::vector<int32_t> colour_units(const HostMesh& H, const std::vector<int32_t>&
 
 int fused_plan_build(const HostMesh& H, int layout, int param, FusedPlan& P) {
     const int np2 = H.np1 * H.np1;
-    const bool columns = layout == SEM_LAYOUT_COLUMNS || layout == SEM_LAYOUT_COLUMNS_KZ;
+    const bool columns = layout == SEM_LAYOUT_COLUMNS || layout == SEM_LAYOUT_COLUMNS_KZ ||
+                         layout == SEM_LAYOUT_COLUMNS_SPLIT;
     int lpc = columns ? param : 0;
     if (lpc < 1) {
         // default: the deepest supported chunk of at most 512 threads
@@ -1195,6 +1269,7 @@ int fused_plan_build(const HostMesh& H, int layout, int param, FusedPlan& P) {
         while (fused_lpc_supported(H.N, lpc * 2) && np2 * (2 * lpc * H.N + 1) <= 512) lpc *= 2;
     }
     if (!fused_lpc_supported(H.N, lpc)) return SEM_ERR_ARG;
+    if (layout == SEM_LAYOUT_COLUMNS_SPLIT && !fused_split_supported(H.N, lpc)) return SEM_ERR_ARG;
     if (layout == SEM_LAYOUT_BLOCKS && !fused_blocks_supported(H)) return SEM_ERR_ARG;
     if (!columns && layout != SEM_LAYOUT_BLOCKS) return SEM_ERR_ARG;
     auto up = [&](const void* src, size_t bytes, void** dst) -> int {
@@ -1372,10 +1447,10 @@ int fused_plan_build(const HostMesh& H, int layout, int param, FusedPlan& P) {
         P.tail.cH = P.t.cH;
         P.t.n_color = n_color;
         P.t.layers_per_chunk = lpc;
-        P.t.kz_order = layout == SEM_LAYOUT_COLUMNS_KZ ? 1 : 0;
+        P.t.thread_order = layout == SEM_LAYOUT_COLUMNS_KZ ? 1 : layout == SEM_LAYOUT_COLUMNS_SPLIT ? 2 : 0;
         P.color_ptr_host = cptr;
     }
-    P.layout = layout == SEM_LAYOUT_COLUMNS_KZ ? SEM_LAYOUT_COLUMNS_KZ : SEM_LAYOUT_COLUMNS;
+    P.layout = columns ? layout : SEM_LAYOUT_COLUMNS;
     if (columns) return SEM_OK;
 
     // ---- block layout: units are the 2 x 2 blocks and the columns in no block
@@ -1481,7 +1556,7 @@ int fused_plan_build(const HostMesh& H, int layout, int param, FusedPlan& P) {
     P.ts.first = static_cast<const uint8_t*>(d);
     P.ts.color_ptr = nullptr;
     P.ts.n_color = n_color;
-    P.ts.kz_order = 0;
+    P.ts.thread_order = 0;
     P.blk_ptr_host = bptr;
     P.single_ptr_host = sptr;
     P.n_unit_color = n_color;

@@ -91,7 +91,7 @@ def test_dissipation_matches_oracle(name, kw):
     want, _ = timestep.run_stages(f, q, c["dt"], 3)
     fused_on = {}
     for lay in ((api.SEM_LAYOUT_COLUMNS, 2), (api.SEM_LAYOUT_COLUMNS_KZ, 2),
-                (api.SEM_LAYOUT_BLOCKS, 1)):
+                (api.SEM_LAYOUT_COLUMNS_SPLIT, 2), (api.SEM_LAYOUT_BLOCKS, 1)):
         try:
             api.sem_stage_set_layout(gm, *lay)
         except native.SemError:

@@ -300,10 +300,13 @@ def test_api_rejects_bad_calls():
 
 
 # work layouts of the fused stage: single columns in chunks of 1, 2, 4, 8
-# layers in either FP64 thread order (0: planes between elements first, 2:
-# vertical index fastest); 2 x 2 column blocks in 1, 2 or 4 vertical segments
-TUNES = [(0, 1), (0, 2), (0, 4), (0, 8), (2, 1), (2, 2), (2, 4), (2, 8), (1, 1), (1, 2), (1, 4)]
-TUNE_IDS = ["col1", "col2", "col4", "col8", "kz1", "kz2", "kz4", "kz8", "blk1", "blk2", "blk4"]
+# layers in each FP64 thread order (0: planes between elements first, 2:
+# vertical index fastest, 3: split element, two or more layers); 2 x 2 column
+# blocks in 1, 2 or 4 vertical segments
+TUNES = [(0, 1), (0, 2), (0, 4), (0, 8), (2, 1), (2, 2), (2, 4), (2, 8), (3, 2), (3, 4), (3, 8),
+         (1, 1), (1, 2), (1, 4)]
+TUNE_IDS = ["col1", "col2", "col4", "col8", "kz1", "kz2", "kz4", "kz8", "split2", "split4", "split8",
+            "blk1", "blk2", "blk4"]
 DECOMP = [0, 2, 4, 5, 6, 7]
 
 
@@ -365,11 +368,11 @@ def test_layouts_agree_with_each_other():
 
 
 def test_thread_orders_bit_identical():
-    """The two FP64 thread orders of the column layout assign the same
-    arithmetic to every node and sum the columns in the same colour order: a
-    stage (and its right-hand side alone) is bit-identical between them, at
-    every chunk depth, on every mesh (hanging points and side columns
-    included)."""
+    """The FP64 thread orders of the column layout assign the same arithmetic
+    to every node (each element's part rounded on its own, summed lower
+    element first) and sum the columns in the same colour order: a stage (and
+    its right-hand side alone) is bit-identical between them, at every chunk
+    depth, on every mesh (hanging points and side columns included)."""
     for k in DECOMP:
         S = get(*CASES[k])
         torch, api = S.torch, S.api
@@ -382,11 +385,12 @@ def test_thread_orders_bit_identical():
                 if lpc > 2 * n_z:
                     continue
                 outs = []
-                for lay in (api.SEM_LAYOUT_COLUMNS, api.SEM_LAYOUT_COLUMNS_KZ):
+                for lay in (api.SEM_LAYOUT_COLUMNS, api.SEM_LAYOUT_COLUMNS_KZ,
+                            api.SEM_LAYOUT_COLUMNS_SPLIT):
                     try:
                         api.sem_stage_set_layout(S.gm, lay, lpc)
                     except SemError:
-                        break
+                        continue
                     for a, b, cc in ((0.75, 0.25, 0.25 * S.c["dt"]), (0.0, 0.0, 1.0)):
                         out = torch.zeros_like(S.q_g)
                         api.sem_stage(S.gm, a, b, cc, S.q_g, S.q_g, out, api.SEM_FP64)
@@ -394,8 +398,9 @@ def test_thread_orders_bit_identical():
                 torch.cuda.synchronize()
                 if len(outs) < 4:
                     continue
-                say("  orders", IDS[k], "lpc", lpc)
-                assert torch.equal(outs[0], outs[2]) and torch.equal(outs[1], outs[3])
+                say("  orders", IDS[k], "lpc", lpc, "layouts compared", len(outs) // 2)
+                for j in range(2, len(outs), 2):
+                    assert torch.equal(outs[0], outs[j]) and torch.equal(outs[1], outs[j + 1])
                 tried += 1
         finally:
             api.sem_stage_set_layout(S.gm, *saved)

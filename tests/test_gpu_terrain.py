@@ -123,9 +123,16 @@ def test_terrain_rhs_matches_oracle_every_chunk_depth(name, kw, shape, periodic)
         err = metrics.rel_l2(got, want, metrics.RHS_FLOORS)
         say("  rel", err)
         assert err.max() <= TOL64
-        # the other FP64 thread order: the same values, bit for bit
+        # the other FP64 thread orders: the same values, bit for bit
         S.api.sem_stage_set_layout(S.gm, S.api.SEM_LAYOUT_COLUMNS_KZ, lpc)
         assert np.array_equal(S.gpu_rhs(), got)
+        if lpc > 1:
+            try:
+                S.api.sem_stage_set_layout(S.gm, S.api.SEM_LAYOUT_COLUMNS_SPLIT, lpc)
+            except Exception:
+                pass                               # a pair across two waves
+            else:
+                assert np.array_equal(S.gpu_rhs(), got)
         tried += 1
     assert tried >= 2
 
