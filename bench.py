@@ -97,9 +97,11 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload=WORKLOAD):
+def measured_traffic(workload=WORKLOAD, kernel=None):
     """HBM bytes per stage from the committed rocprofv3 counter summary, or
-    None when it is missing or was taken on a different kernel source."""
+    None when it is missing, was taken on a different kernel source, or (when
+    `kernel` names the instance timed, e.g. "k_stage_columns<5, 4, double,
+    false, false, 1>") on another instance."""
     path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
     if not os.path.exists(path):
         return None
@@ -107,7 +109,22 @@ def measured_traffic(workload=WORKLOAD):
         t = json.load(fh)
     if t.get("kernel_source_hash") != kernel_source_hash():
         return None
+    if kernel is not None and kernel not in t.get("kernel", ""):
+        return None
     return t.get("hbm_bytes_per_stage")
+
+
+def column_instance(N, lpc, layout, fp64, diss_inline):
+    """Name of the column-kernel instance a stage runs (template arguments:
+    N + 1, layers per chunk, precision, terrain, dissipation, thread order),
+    or None for the block layout."""
+    order = {0: 0, 2: 1, 3: 2}.get(layout)
+    if order is None:
+        return None
+    if not fp64:
+        order = 1
+    return (f"k_stage_columns<{N + 1}, {lpc}, {'double' if fp64 else 'float'}, false, "
+            f"{'true' if diss_inline else 'false'}, {order}>")
 
 
 def traffic_from_counters(fetch_csv, write_csv, workload=WORKLOAD, launches_per_stage=4, out_dir=None):
@@ -145,6 +162,10 @@ def traffic_from_counters(fetch_csv, write_csv, workload=WORKLOAD, launches_per_
         raise ValueError("counter files hold no calibration kernel or no column kernel")
     calib_k = max(calib, key=lambda k: len(fetch[k]))
     main_k = max(cols, key=lambda k: len(fetch[k]))
+    main_w = max((k for k in write if "k_stage_columns" in k), key=lambda k: len(write[k]), default=None)
+    if main_w != main_k:
+        raise ValueError("the FETCH_SIZE and WRITE_SIZE runs timed different column kernels "
+                         f"({main_k} / {main_w}); pin the layout with --layout")
     f_fac = calib_bytes / (statistics.median(fetch[calib_k]) * 1024)
     w_fac = calib_bytes / (statistics.median(write[calib_k]) * 1024)
     f_kib, w_kib = statistics.median(fetch[main_k]), statistics.median(write[main_k])
@@ -716,7 +737,9 @@ def main():
         for _ in range(5):
             torch.mul(src, 1.0, out=dst)
         torch.cuda.synchronize()
-    traffic = measured_traffic(args.workload)
+    traffic = measured_traffic(args.workload, column_instance(
+        case["N"], lpc, layout, prec == api.SEM_FP64,
+        bool(args.dissipation) and prec == api.SEM_FP64 and layout != api.SEM_LAYOUT_BLOCKS))
     stages = 3 * n_steps
     res = {
         "metric": METRIC,

@@ -15,7 +15,8 @@ HEADER = ["Correlation_Id", "Dispatch_Id", "Agent_Id", "Queue_Id", "Process_Id",
           "Scratch_Size", "VGPR_Count", "Accum_VGPR_Count", "SGPR_Count", "Counter_Name",
           "Counter_Value", "Start_Timestamp", "End_Timestamp"]
 CALIB = "void at::native::vectorized_elementwise_kernel<4, at::native::AUnaryFunctor<double, double, double>>"
-COLS = "void sem::k_stage_columns<5, 4, double, false, false>(sem::DevMesh)"
+COLS = "void sem::k_stage_columns<5, 4, double, false, false, 1>(sem::DevMesh)"
+COLS0 = "void sem::k_stage_columns<5, 4, double, false, false, 0>(sem::DevMesh)"
 
 
 def _write(path, counter, rows):
@@ -48,6 +49,12 @@ def test_traffic_from_counters(tmp_path):
     assert out["kernel"] == COLS and out["dispatches"] == 9
     saved = json.load(open(tmp_path / "traffic_vortex_8x8x4_n4.json"))
     assert saved["kernel_source_hash"] == bench.kernel_source_hash()
+    # two counter runs whose autotuners chose different instances are refused
+    _write(tmp_path / "w2.csv", "WRITE_SIZE",
+           [(CALIB, calib_bytes / 1024)] * 5 + [(COLS0, 100.0)] * 9 + [(COLS, 100.0)] * 2)
+    with pytest.raises(ValueError):
+        bench.traffic_from_counters(str(tmp_path / "f.csv"), str(tmp_path / "w2.csv"),
+                                    "vortex_8x8x4_n4", out_dir=str(tmp_path))
 
 
 def test_measured_traffic_is_null_for_other_sources(tmp_path, monkeypatch):
@@ -63,3 +70,22 @@ def test_measured_traffic_is_null_for_other_sources(tmp_path, monkeypatch):
     assert bench.measured_traffic("x") is None
     assert bench.measured_traffic("y") == 2.0
     assert bench.measured_traffic("z") is None
+
+
+def test_measured_traffic_only_for_the_instance_timed(tmp_path, monkeypatch):
+    """A figure taken on one thread order or chunk depth is not reported for another."""
+    import bench
+    h = bench.kernel_source_hash()
+    d = tmp_path / "profiles"
+    d.mkdir()
+    json.dump({"kernel_source_hash": h, "hbm_bytes_per_stage": 3.0, "kernel": COLS},
+              open(d / "traffic_w.json", "w"))
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: h)
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    timed = bench.column_instance(4, 4, 2, True, False)
+    assert timed == "k_stage_columns<5, 4, double, false, false, 1>"
+    assert bench.measured_traffic("w", timed) == 3.0
+    assert bench.measured_traffic("w", bench.column_instance(4, 4, 0, True, False)) is None
+    assert bench.measured_traffic("w", bench.column_instance(4, 2, 2, True, False)) is None
+    assert bench.column_instance(4, 4, 1, True, False) is None          # block layout
+    assert bench.column_instance(4, 4, 3, False, False).endswith("float, false, false, 1>")
