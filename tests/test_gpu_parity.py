@@ -307,7 +307,7 @@ TUNES = [(0, 1), (0, 2), (0, 4), (0, 8), (2, 1), (2, 2), (2, 4), (2, 8), (3, 2),
          (1, 1), (1, 2), (1, 4)]
 TUNE_IDS = ["col1", "col2", "col4", "col8", "kz1", "kz2", "kz4", "kz8", "split2", "split4", "split8",
             "blk1", "blk2", "blk4"]
-DECOMP = [0, 2, 4, 5, 6, 7]
+DECOMP = [0, 1, 2, 4, 5, 6, 7]
 
 
 @pytest.mark.parametrize("name,kw", [CASES[k] for k in DECOMP], ids=[IDS[k] for k in DECOMP])
