@@ -21,7 +21,8 @@ struct HostMesh;
 // contributor of its node: the first contributor writes the node, later ones
 // add to it (plain read-modify-write, ordered by the launches).
 struct FusedTables {
-    const int32_t* col_order;   // columns sorted by colour (Morton order inside)
+    const int32_t* col_order;   // columns sorted by colour; inside a colour by
+                                // decreasing work (hanging positions), then Morton
     const int32_t* color_ptr;   // n_color + 1 offsets into col_order (host copy below)
     int n_color;
     const uint8_t* first;       // per (column, position)

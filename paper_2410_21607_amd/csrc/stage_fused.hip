@@ -183,11 +183,12 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
     };
     if (tid < SL) slice[0][tid] = slice_value(0);
 
-    // Workgroups go to the 8 XCDs round-robin by id; give each XCD a
-    // contiguous (Morton-ordered) range of this colour's columns.
-    const int G = gridDim.x;
-    const int xcd = blockIdx.x & 7, rr = blockIdx.x >> 3;
-    const int item = xcd * (G >> 3) + min(xcd, G & 7) + rr;
+    // Workgroups start in block order (and go to the 8 XCDs round-robin);
+    // the plan lists each colour's columns by decreasing work, so that the
+    // costliest start first and the last, partly filled round of resident
+    // workgroups holds the cheapest.  Columns of one colour share no node and
+    // no cache line, so their order does not matter to the L2s.
+    const int item = blockIdx.x;
     const int col = ft.col_order[col0 + min(item, ncol - 1)];
 
     // Thread -> node of the chunk.  KZ (and always in float): the natural
@@ -1321,12 +1322,22 @@ int fused_plan_build(const HostMesh& H, int layout, int param, FusedPlan& P) {
                 side_of_col[cidx] = int32_t(side_cols.size());
                 side_cols.push_back(cidx);
             }
+        // each colour's columns (the first colour's with the side columns)
+        // by decreasing work: the hanging positions of a column interpolate
+        // their values and store to the hanging buffer.  Stable, so equal
+        // columns keep the caller's (Morton) order.
+        std::vector<int32_t> n_hang(static_cast<size_t>(H.n_col), 0);
+        for (int cidx = 0; cidx < H.n_col; ++cidx)
+            for (int pos = 0; pos < np2; ++pos) n_hang[cidx] += H.gmap[size_t(cidx) * np2 + pos] < 0;
         std::vector<int32_t> order, cptr(1, 0);
         for (int k = 0; k < n_color; ++k) {
             if (small[k]) continue;
+            const size_t k0 = order.size();
             for (int cidx = 0; cidx < H.n_col; ++cidx)
                 if (color[cidx] == k) order.push_back(cidx);
             if (cptr.size() == 1) order.insert(order.end(), side_cols.begin(), side_cols.end());
+            std::stable_sort(order.begin() + k0, order.end(),
+                             [&](int32_t x, int32_t y) { return n_hang[x] > n_hang[y]; });
             cptr.push_back(int32_t(order.size()));
         }
         n_color = int(cptr.size()) - 1;
