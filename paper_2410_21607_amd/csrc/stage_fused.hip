@@ -6,8 +6,10 @@
 //
 // Column kernel.  A workgroup owns one column and marches up through it in
 // chunks of `layers_per_chunk` stacked elements; one thread per unique node of
-// the chunk (vertical index fastest, so that the accesses of one horizontal
-// position are contiguous in the [field][h][kz] state layout):
+// the chunk, or (split-element order) per element and local node, so that a
+// node between two stacked elements has two (the thread orders are described
+// at the mapping below; the accesses of one horizontal position are
+// contiguous in the [field][h][kz] state layout):
 //   * load the node of q_s (hanging positions interpolate the coarse face
 //     nodes: the scatter of Section 3.1) and evaluate the pointwise fields of
 //     Section 2 (rho u, rho v, rho w, u, v, w, p', theta') into LDS;
@@ -24,7 +26,8 @@
 //     buffer instead (Z^T below).
 // Columns are coloured so that no two columns of one colour share a node: each
 // colour is one launch, so the read-modify-writes never race and the order of
-// the sums is fixed (deterministic results).
+// the sums is fixed (deterministic results).  Within a launch the columns
+// start in order of decreasing work.
 // Hanging-point kernel (meshes with hanging nodes): every coarse face node
 // adds c M^-1 sum_hh w_hh c_hh, the transpose of the scatter (Section 3.1).
 #include "stage_fused.h"
@@ -191,17 +194,21 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
     const int item = blockIdx.x;
     const int col = ft.col_order[col0 + min(item, ncol - 1)];
 
-    // Thread -> node of the chunk.  KZ (and always in float): the natural
-    // order, kzl fastest within a position, so that the global loads and
-    // stores of a wave cover few rows and lines; every wave then carries the
-    // same LDS load.  Otherwise (FP64): nodes on the planes between two
-    // stacked elements (LPC-1 per position, two z derivatives each) come
-    // first, so that they fill waves of their own instead of making every
-    // wave run a second pass of FP64 z derivatives with most lanes masked,
-    // and so that these longest waves are the oldest, which issue first;
-    // nodes inside an element or on the chunk's bottom/top follow (RG per
-    // position).  Which order is faster depends on the order, the chunk depth
-    // and the terms (the autotuner times both).
+    // Thread -> node of the chunk, by the thread order ORD.
+    //  1 (and always in float): natural, kzl fastest within a position, so
+    //    that the global loads and stores of a wave cover few rows and lines;
+    //    every wave then carries the same LDS load.
+    //  0 (FP64): nodes on the planes between two stacked elements (LPC-1 per
+    //    position, two z derivatives each) come first, so that they fill
+    //    waves of their own instead of making every wave run a second pass of
+    //    FP64 z derivatives with most lanes masked, and so that these longest
+    //    waves are the oldest, which issue first; nodes inside an element or
+    //    on the chunk's bottom/top follow (RG per position).
+    //  2 (SE, FP64): a thread per (element, local node) of each position,
+    //    elements in order; the lower thread of a plane between two elements
+    //    (dupe) only computes its element's part and hands it to the next lane.
+    // Which order is faster depends on the order N, the chunk depth and the
+    // terms (the autotuner times all three).
     constexpr int RG = LPC * (N - 1) + 2;
     int kzl, p;
     int el_t = 0, kk_t = 0;                       // SE: the thread's element and local node
