@@ -268,6 +268,19 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
             r_end = ft.hang_ptr[-g];
         }
     }
+    // q_s of the next chunk (direct nodes).  Split-element order: the first
+    // chunk's is requested here already, so that it arrives while the
+    // per-position tables are set up (in the other orders that measured
+    // slower, so their first chunk loads in the chunk loop)
+    double pf[NF] = {0, 0, 0, 0, 0};
+    if constexpr (!TER && SE) {
+        const bool act0 = lane_ok && el_t < min(LPC, m.n_z);
+        if (act0 && g >= 0) {
+            const int64_t o = int64_t(g) * m.ldz + kzl;
+#pragma unroll
+            for (int f = 0; f < NF; ++f) pf[f] = qs[f * fs + o];
+        }
+    }
     // per-position constants in LDS rather than in every thread's registers:
     // the horizontal inverse mass and the horizontal mass weight
     __shared__ double s_mh[NP2], s_mij[NP2];
@@ -306,7 +319,6 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
     }
 
     const int n_chunk = (m.n_z + LPC - 1) / LPC;
-    double pf[NF] = {0, 0, 0, 0, 0};              // q_s of the next chunk (direct nodes)
     for (int ch = 0; ch < n_chunk; ++ch) {
         const int L0 = ch * LPC;
         const int L1 = min(L0 + LPC, m.n_z);
@@ -325,7 +337,7 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
         T rho = T(1);
         if (active) {
             if (g >= 0) {
-                if (!TER && ch > 0) {
+                if (!TER && (SE || ch > 0)) {
 #pragma unroll
                     for (int f = 0; f < NF; ++f) qv[f] = pf[f];
                 } else {
