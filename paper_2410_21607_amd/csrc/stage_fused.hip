@@ -104,9 +104,12 @@ __device__ __forceinline__ double pow1p_minus1(const DevMesh& m, double x) {
 
 // At least four waves per SIMD: two workgroups share a CU, so that one can
 // compute while the other waits on memory.  The instance with the sub-grid
-// stress (DISS) needs about 155 VGPRs: held to 128 it spilled some 40 of them
-// and ran 15% slower than with the bound relaxed to two waves (it then
-// runs at three).  Within a workgroup the global
+// stress (DISS) needs about 155 VGPRs in the planes-first and natural orders:
+// held to 128 it spilled some 40 of them and ran 15% slower than with the
+// bound relaxed to two waves (it then runs at three).  In the split-element
+// order it needs about 150; held to 128 it spills about 20 and runs 13%
+// faster than at three waves, so that order keeps the bound of four.
+// Within a workgroup the global
 // loads of a chunk are issued one phase early: while the derivatives of chunk
 // ch run, the update base of its nodes, the next chunk's q_s (direct nodes)
 // and the next chunk's slice of the per-level tables are already in flight.
@@ -123,7 +126,7 @@ __device__ __forceinline__ double pow1p_minus1(const DevMesh& m, double x) {
 // Hanging positions take the coarse face's interpolant of zs and of the
 // reference state (host tables), so the mesh stays watertight.
 template <int NP, int LPC, typename T, bool TER, bool DISS, int ORD>
-__global__ void __launch_bounds__((col_threads<NP, LPC, ORD>()), DISS ? 2 : 4)
+__global__ void __launch_bounds__((col_threads<NP, LPC, ORD>()), (DISS && ORD != 2) ? 2 : 4)
 k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double b, double c,
                 const double* __restrict__ qn, const double* __restrict__ qs,
                 double* __restrict__ qo) {
