@@ -133,6 +133,9 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
     constexpr int NP2 = NP * NP, N = NP - 1;
     constexpr int NK = LPC * N + 1;               // vertical nodes of a full chunk
     constexpr bool SE = ORD == 2;
+    // loads issued one phase early (next chunk's q_s, the update base after
+    // the tile barrier): box elements always, terrain in the split order
+    constexpr bool PRE = !TER || SE;
     constexpr int WGT = wg_threads<NP, LPC, SE>();
     __shared__ T tile[4][NP2 * NK];               // rho u, rho v, rho w, u: [field][p][kzl], kzl fastest
     __shared__ double carry[2][NF][NP2];
@@ -276,7 +279,7 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
     // per-position tables are set up (in the other orders that measured
     // slower, so their first chunk loads in the chunk loop)
     double pf[NF] = {0, 0, 0, 0, 0};
-    if constexpr (!TER && SE) {
+    if constexpr (SE) {
         const bool act0 = lane_ok && el_t < min(LPC, m.n_z);
         if (act0 && g >= 0) {
             const int64_t o = int64_t(g) * m.ldz + kzl;
@@ -340,7 +343,7 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
         T rho = T(1);
         if (active) {
             if (g >= 0) {
-                if (!TER && (SE || ch > 0)) {
+                if (PRE && (SE || ch > 0)) {
 #pragma unroll
                     for (int f = 0; f < NF; ++f) qv[f] = pf[f];
                 } else {
@@ -403,7 +406,7 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
         // update base of the nodes finished in this chunk (q^n for the first
         // contributor, not read when a = 0; the partial q_out for later colours)
         double base[NF] = {0, 0, 0, 0, 0};
-        if (!TER && active && !dupe && g >= 0 && !(kzl == nk - 1 && L1 < m.n_z) && (!first || a != 0.0)) {
+        if (PRE && active && !dupe && g >= 0 && !(kzl == nk - 1 && L1 < m.n_z) && (!first || a != 0.0)) {
             const double* bp = first ? qn : qo;
             const int64_t o = s_row[pc] + kz;
 #pragma unroll
@@ -412,9 +415,10 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
         const double* sb = slice[ch & 1];
         double sl_next = 0.0;
         if (tid < SL && ch + 1 < n_chunk) sl_next = slice_value(ch + 1);
-        // prefetch the next chunk's q_s (box elements: the terrain instance
-        // needs those registers for its metric terms)
-        if (!TER && ch + 1 < n_chunk && lane_ok && g >= 0) {
+        // prefetch the next chunk's q_s (PRE: box elements, and terrain in
+        // the split-element order; the other terrain instances need those
+        // registers for their metric terms)
+        if (PRE && ch + 1 < n_chunk && lane_ok && g >= 0) {
             const int L0n = L0 + LPC;
             const int neln = min(L0n + LPC, m.n_z) - L0n;
             if (SE ? el_t < neln : kzl < neln * N + 1) {
@@ -674,8 +678,9 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
                     }
                     const double mi = c * s_mh[pc] * sb[5 * NK + kzl];
                     const int64_t o = s_row[pc] + kz;
-                    if (TER && (!first || a != 0.0)) {
-                        // the terrain instance loads its base here (registers)
+                    if (!PRE && (!first || a != 0.0)) {
+                        // the terrain instances outside the split-element
+                        // order load their base here (registers)
                         const double* bp = first ? qn : qo;
 #pragma unroll
                         for (int f = 0; f < NF; ++f) base[f] = bp[f * fs + o];
