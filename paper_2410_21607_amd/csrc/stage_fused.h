@@ -51,11 +51,14 @@ struct FusedTables {
 struct TailTables {
     const int32_t* h;           // n: unique horizontal node
     const uint8_t* first;       // n: no column launch writes the node first
-    const int32_t *sptr, *sslot;    // side slots of the node
-    const int32_t *hptr, *hh;       // hanging points it gathers (Z^T rows)
-    const double* hw;
-    const int32_t *hh_sptr, *hh_sslot;  // side slots of every hanging point
-    const uint8_t* hh_cvalid;   // n_hh: some column launch writes cH there
+    // per node a flat list of contribution rows (hanging or pseudo hanging
+    // points of cH) in groups: the node's side slots (weight 1), then per
+    // hanging point of its Z^T row that point (when a column launch writes
+    // it) and its side slots (weight w of the row); estart marks a group's
+    // first entry and carries its weight; row -1 adds nothing
+    const int32_t *eptr, *erow;
+    const double* ew;
+    const uint8_t* estart;
     const double* cH;           // hanging and pseudo hanging points
     int n;
     int64_t fsh;                // field stride of cH

@@ -1131,29 +1131,29 @@ __global__ void k_stage_tail(DevMesh m, TailTables tl, double a, double b, doubl
          t += int64_t(gridDim.x) * blockDim.x) {
         const int li = int(t / nzn), kz = int(t - int64_t(li) * nzn);
         const int h = tl.h[li];
-        double s[NF] = {0, 0, 0, 0, 0};
-        for (int r = tl.sptr[li]; r < tl.sptr[li + 1]; ++r) {
-            const int64_t o = int64_t(tl.sslot[r]) * m.ldz + kz;
+        // the node's groups of contribution rows (side slots; per hanging
+        // point of its Z^T row, that point and its side slots), each summed
+        // and then added times its weight
+        double s[NF] = {0, 0, 0, 0, 0}, v[NF] = {0, 0, 0, 0, 0};
+        double wc = 0.0;
+        for (int e = tl.eptr[li]; e < tl.eptr[li + 1]; ++e) {
+            if (tl.estart[e]) {
 #pragma unroll
-            for (int f = 0; f < NF; ++f) s[f] += tl.cH[f * fsh + o];
-        }
-        for (int r = tl.hptr[li]; r < tl.hptr[li + 1]; ++r) {
-            const int hh = tl.hh[r];
-            double v[NF] = {0, 0, 0, 0, 0};
-            if (tl.hh_cvalid[hh]) {
-                const int64_t o = int64_t(hh) * m.ldz + kz;
-#pragma unroll
-                for (int f = 0; f < NF; ++f) v[f] = tl.cH[f * fsh + o];
+                for (int f = 0; f < NF; ++f) {
+                    s[f] += wc * v[f];
+                    v[f] = 0.0;
+                }
+                wc = tl.ew[e];
             }
-            for (int q = tl.hh_sptr[hh]; q < tl.hh_sptr[hh + 1]; ++q) {
-                const int64_t o = int64_t(tl.hh_sslot[q]) * m.ldz + kz;
+            const int row = tl.erow[e];
+            if (row >= 0) {
+                const int64_t o = int64_t(row) * m.ldz + kz;
 #pragma unroll
                 for (int f = 0; f < NF; ++f) v[f] += tl.cH[f * fsh + o];
             }
-            const double w = tl.hw[r];
-#pragma unroll
-            for (int f = 0; f < NF; ++f) s[f] += w * v[f];
         }
+#pragma unroll
+        for (int f = 0; f < NF; ++f) s[f] += wc * v[f];
         bool lid = (kz == 0) || (kz == nzn - 1);
         double mi = c * m.minv_h[h] * m.minv_v[kz];
         if (m.zs) {
@@ -1459,17 +1459,38 @@ int fused_plan_build(const HostMesh& H, int layout, int param, FusedPlan& P) {
                 hsptr.push_back(int32_t(hsslot.size()));
             }
             if (hsptr.size() == 1) hsptr.push_back(0);
+            // one flat list per tail node: its side slots (a group of weight
+            // 1), then per hanging point of its Z^T row a group of weight w:
+            // the point's own contribution (if a column writes it) and its
+            // side slots.  A group sums its rows first and enters the node's
+            // sum times its weight, in the order of Z^T; a group with no row
+            // gets one entry of row -1 (adds nothing).
+            std::vector<int32_t> eptr(1, 0), erow;
+            std::vector<double> ew;
+            std::vector<uint8_t> estart;
+            auto entry = [&](int32_t row, bool start, double w) {
+                erow.push_back(row);
+                estart.push_back(start ? 1 : 0);
+                ew.push_back(w);
+            };
+            for (size_t li = 0; li < th.size(); ++li) {
+                for (int32_t q = tsptr[li]; q < tsptr[li + 1]; ++q) entry(tsslot[q], q == tsptr[li], 1.0);
+                for (int32_t r = thptr[li]; r < thptr[li + 1]; ++r) {
+                    const int32_t hh = thh[r];
+                    bool any = false;
+                    if (hvalid[hh]) { entry(hh, true, thw[r]); any = true; }
+                    for (int32_t q = hsptr[hh]; q < hsptr[hh + 1]; ++q) { entry(hsslot[q], !any, thw[r]); any = true; }
+                    if (!any) entry(-1, true, thw[r]);
+                }
+                eptr.push_back(int32_t(erow.size()));
+            }
             TailTables& T = P.tail;
             if ((rc = upv(th, &T.h)) != SEM_OK) return rc;
             if ((rc = upv(tfirst, &T.first)) != SEM_OK) return rc;
-            if ((rc = upv(tsptr, &T.sptr)) != SEM_OK) return rc;
-            if ((rc = upv(tsslot, &T.sslot)) != SEM_OK) return rc;
-            if ((rc = upv(thptr, &T.hptr)) != SEM_OK) return rc;
-            if ((rc = upv(thh, &T.hh)) != SEM_OK) return rc;
-            if ((rc = upv(thw, &T.hw)) != SEM_OK) return rc;
-            if ((rc = upv(hsptr, &T.hh_sptr)) != SEM_OK) return rc;
-            if ((rc = upv(hsslot, &T.hh_sslot)) != SEM_OK) return rc;
-            if ((rc = upv(hvalid, &T.hh_cvalid)) != SEM_OK) return rc;
+            if ((rc = upv(eptr, &T.eptr)) != SEM_OK) return rc;
+            if ((rc = upv(erow, &T.erow)) != SEM_OK) return rc;
+            if ((rc = upv(ew, &T.ew)) != SEM_OK) return rc;
+            if ((rc = upv(estart, &T.estart)) != SEM_OK) return rc;
             T.n = int(th.size());
             T.fsh = P.t.fsh;
             P.has_tail = true;
