@@ -107,11 +107,14 @@ def measured_traffic(workload=WORKLOAD, kernel=None):
         return None
     with open(path) as fh:
         t = json.load(fh)
-    if t.get("kernel_source_hash") != kernel_source_hash():
-        return None
-    if kernel is not None and kernel not in t.get("kernel", ""):
-        return None
-    return t.get("hbm_bytes_per_stage")
+    # one record per counted instance (a single record in older files)
+    for rec in t.get("records", [t]):
+        if rec.get("kernel_source_hash") != kernel_source_hash():
+            continue
+        if kernel is not None and kernel not in rec.get("kernel", ""):
+            continue
+        return rec.get("hbm_bytes_per_stage")
+    return None
 
 
 def column_instance(N, lpc, layout, fp64, diss_inline):
@@ -176,9 +179,16 @@ def traffic_from_counters(fetch_csv, write_csv, workload=WORKLOAD, launches_per_
            "fetch_factor": f_fac, "write_factor": w_fac, "calibration_bytes": calib_bytes,
            "dispatches": len(fetch[main_k]),
            "source": f"profiles/fused_stage_{workload}.md"}
+    # kept beside the records of other instances taken on the same sources
     path = os.path.join(out_dir or os.path.join(ROOT, "profiles"), f"traffic_{workload}.json")
+    records = []
+    if os.path.exists(path):
+        with open(path) as fh:
+            old = json.load(fh)
+        records = [r for r in old.get("records", [old])
+                   if r.get("kernel_source_hash") == out["kernel_source_hash"] and r.get("kernel") != main_k]
     with open(path, "w") as fh:
-        json.dump(out, fh, indent=1)
+        json.dump({"records": records + [out]}, fh, indent=1)
     return out
 
 

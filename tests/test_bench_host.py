@@ -47,8 +47,17 @@ def test_traffic_from_counters(tmp_path):
     assert out["fetch_factor"] == pytest.approx(2.0) and out["write_factor"] == pytest.approx(1.0)
     assert out["hbm_bytes_per_stage"] == pytest.approx(4 * 1024 * (300.0 * 2 + 100.0))
     assert out["kernel"] == COLS and out["dispatches"] == 9
-    saved = json.load(open(tmp_path / "traffic_vortex_8x8x4_n4.json"))
-    assert saved["kernel_source_hash"] == bench.kernel_source_hash()
+    saved = json.load(open(tmp_path / "traffic_vortex_8x8x4_n4.json"))["records"]
+    assert len(saved) == 1 and saved[0]["kernel_source_hash"] == bench.kernel_source_hash()
+    # a second instance's counters join the file; the same instance replaces its record
+    _write(tmp_path / "f0.csv", "FETCH_SIZE", [(CALIB, calib_bytes / 2048)] * 5 + [(COLS0, 400.0)] * 9)
+    _write(tmp_path / "w0.csv", "WRITE_SIZE", [(CALIB, calib_bytes / 1024)] * 5 + [(COLS0, 100.0)] * 9)
+    bench.traffic_from_counters(str(tmp_path / "f0.csv"), str(tmp_path / "w0.csv"),
+                                "vortex_8x8x4_n4", out_dir=str(tmp_path))
+    bench.traffic_from_counters(str(tmp_path / "f.csv"), str(tmp_path / "w.csv"),
+                                "vortex_8x8x4_n4", out_dir=str(tmp_path))
+    saved = json.load(open(tmp_path / "traffic_vortex_8x8x4_n4.json"))["records"]
+    assert sorted(r["kernel"] for r in saved) == sorted([COLS, COLS0])
     # two counter runs whose autotuners chose different instances are refused
     _write(tmp_path / "w2.csv", "WRITE_SIZE",
            [(CALIB, calib_bytes / 1024)] * 5 + [(COLS0, 100.0)] * 9 + [(COLS, 100.0)] * 2)
@@ -70,6 +79,21 @@ def test_measured_traffic_is_null_for_other_sources(tmp_path, monkeypatch):
     assert bench.measured_traffic("x") is None
     assert bench.measured_traffic("y") == 2.0
     assert bench.measured_traffic("z") is None
+
+
+def test_measured_traffic_picks_the_record_of_the_instance(tmp_path, monkeypatch):
+    import bench
+    h = bench.kernel_source_hash()
+    d = tmp_path / "profiles"
+    d.mkdir()
+    json.dump({"records": [{"kernel_source_hash": h, "hbm_bytes_per_stage": 5.0, "kernel": COLS0},
+                           {"kernel_source_hash": h, "hbm_bytes_per_stage": 6.0, "kernel": COLS}]},
+              open(d / "traffic_v.json", "w"))
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: h)
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.measured_traffic("v", bench.column_instance(4, 4, 0, True, False)) == 5.0
+    assert bench.measured_traffic("v", bench.column_instance(4, 4, 2, True, False)) == 6.0
+    assert bench.measured_traffic("v", bench.column_instance(4, 4, 3, True, False)) is None
 
 
 def test_measured_traffic_only_for_the_instance_timed(tmp_path, monkeypatch):
