@@ -34,6 +34,26 @@ def test_exports_every_declared_symbol():
         assert n in native.SIGNATURES, n
 
 
+def test_binding_constants_match_the_header():
+    """Every integer constant of include/sem.h that the binding restates has
+    the header's value (native.py for the core codes, api.py for the work
+    layouts); the forecaster sizes match the network the header states."""
+    from paper_2410_21607_amd import api
+    text = open(os.path.join(ROOT, "include", "sem.h")).read()
+    defs = {k: int(v) for k, v in re.findall(r"^#define\s+(SEM_\w+)\s+(-?\d+)", text, flags=re.M)}
+    assert {"SEM_OK", "SEM_FP64", "SEM_LAYOUT_COLUMNS_SPLIT", "SEM_MLP_NPARAM"} <= set(defs)
+    checked = 0
+    for name, value in defs.items():
+        for mod in (native, api):
+            if hasattr(mod, name):
+                assert getattr(mod, name) == value, (mod.__name__, name)
+                checked += 1
+    assert checked >= 20
+    i, h, o = defs["SEM_MLP_IN"], defs["SEM_MLP_HIDDEN"], defs["SEM_MLP_OUT"]
+    assert defs["SEM_MLP_NPARAM"] == h * i + h + h * h + h + o * h + o
+    assert defs["SEM_NFEAT"] == i
+
+
 CASES = [("vortex_8x8x4_n4", {}), ("small_uniform", {"N": 3}), ("small_amr2", {}),
          ("small_amr2", {"N": 7}), ("small_amr3", {}), ("small_amr3", {"N": 7}),
          ("small_amr3", {"periodic": False}), ("small_amr3", {"periodic": False, "N": 5}),
