@@ -33,8 +33,9 @@ struct FusedTables {
                                 // 2 = split element
     // Position map and interpolation rows the kernel reads (the mesh's own,
     // extended when the plan has side columns).  Side columns (the columns
-    // of the small colour classes of an uneven mesh) run in the first
-    // colour's launch; every position of theirs maps to a pseudo hanging
+    // of the small colour classes of an uneven mesh) run in the launches of
+    // the other colours, spread to even them out; every position of theirs
+    // maps to a pseudo hanging
     // point past the mesh's n_hh, whose row is the unit row of its node (or a
     // copy of its hanging row), so that the kernel stores the position's
     // contribution in cH unchanged; the tail launch assembles them.

@@ -1335,9 +1335,9 @@ int fused_plan_build(const HostMesh& H, int layout, int param, FusedPlan& P) {
         std::vector<int32_t> color = colour_units(H, unit_of_col, H.n_col, corder, n_color);
         // side columns: the colour classes beyond the fourth that hold fewer
         // than a quarter of the largest class's columns.  Their launches
-        // would be short and latency-bound; instead they run in the first
-        // colour's launch (they only read q_s and write their own slots)
-        // and the tail launch assembles their contributions.
+        // would be short and latency-bound; instead they run in the launches
+        // of the other colours (they only read q_s and write their own
+        // slots) and the tail launch assembles their contributions.
         std::vector<int32_t> csize(size_t(n_color), 0);
         for (int cidx = 0; cidx < H.n_col; ++cidx) ++csize[color[cidx]];
         const int32_t cmax = *std::max_element(csize.begin(), csize.end());
@@ -1356,13 +1356,26 @@ int fused_plan_build(const HostMesh& H, int layout, int param, FusedPlan& P) {
         std::vector<int32_t> n_hang(static_cast<size_t>(H.n_col), 0);
         for (int cidx = 0; cidx < H.n_col; ++cidx)
             for (int pos = 0; pos < np2; ++pos) n_hang[cidx] += H.gmap[size_t(cidx) * np2 + pos] < 0;
+        // the side columns go to the launches with the fewest columns (one at
+        // a time, in their order), so that the launches come out even
+        std::vector<std::vector<int32_t>> side_of_k(static_cast<size_t>(n_color));
+        {
+            std::vector<int64_t> load(static_cast<size_t>(n_color), INT64_MAX);
+            for (int k = 0; k < n_color; ++k)
+                if (!small[k]) load[k] = csize[k];
+            for (int32_t sc : side_cols) {
+                const int k = int(std::min_element(load.begin(), load.end()) - load.begin());
+                side_of_k[k].push_back(sc);
+                ++load[k];
+            }
+        }
         std::vector<int32_t> order, cptr(1, 0);
         for (int k = 0; k < n_color; ++k) {
             if (small[k]) continue;
             const size_t k0 = order.size();
             for (int cidx = 0; cidx < H.n_col; ++cidx)
                 if (color[cidx] == k) order.push_back(cidx);
-            if (cptr.size() == 1) order.insert(order.end(), side_cols.begin(), side_cols.end());
+            order.insert(order.end(), side_of_k[k].begin(), side_of_k[k].end());
             std::stable_sort(order.begin() + k0, order.end(),
                              [&](int32_t x, int32_t y) { return n_hang[x] > n_hang[y]; });
             cptr.push_back(int32_t(order.size()));
