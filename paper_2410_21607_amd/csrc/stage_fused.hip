@@ -203,7 +203,12 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
     // Thread -> node of the chunk, by the thread order ORD.
     //  1 (and always in float): natural, kzl fastest within a position, so
     //    that the global loads and stores of a wave cover few rows and lines;
-    //    every wave then carries the same LDS load.
+    //    every wave then carries the same LDS load.  A position's first
+    //    LPC*N nodes take consecutive threads and the chunk's top plane (the
+    //    next chunk's bottom) follows in the last threads: at N = 4 a wave then
+    //    holds four whole 16-node row segments, each one aligned 128-byte line
+    //    per field, instead of 17-node segments that straddle two lines and
+    //    start anywhere in a wave.
     //  0 (FP64): nodes on the planes between two stacked elements (LPC-1 per
     //    position, two z derivatives each) come first, so that they fill
     //    waves of their own instead of making every wave run a second pass of
@@ -226,8 +231,17 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
         kk_t = r - el_t * NP;
         kzl = el_t * N + kk_t;
     } else if constexpr (ORD == 1) {
-        p = tid < NP2 * NK ? tid / NK : NP2;
-        kzl = tid < NP2 * NK ? tid - p * NK : 0;
+        constexpr int NB = NK - 1;                // nodes below the chunk's top plane
+        if (tid < NP2 * NB) {
+            p = tid / NB;
+            kzl = tid - p * NB;
+        } else if (tid < NP2 * NK) {
+            p = tid - NP2 * NB;
+            kzl = NB;
+        } else {
+            p = NP2;
+            kzl = 0;
+        }
     } else {
         constexpr int NI = (LPC > 1) ? NP2 * (LPC - 1) : 0;
         if (tid < NI) {
