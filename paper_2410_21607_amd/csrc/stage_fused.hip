@@ -132,12 +132,18 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
                 double* __restrict__ qo) {
     constexpr int NP2 = NP * NP, N = NP - 1;
     constexpr int NK = LPC * N + 1;               // vertical nodes of a full chunk
+    // LDS tile stride per position: one pad double at N = 4 (18 instead of
+    // 17 at four layers per chunk: stages 1-1.5 % faster in the natural and
+    // split-element orders and in float).  Not at N = 7: with two layers a
+    // pad of one or two takes the workgroup from 78 KB of LDS to 82-87 KB,
+    // so only one instead of two fits a CU's 160 KB (7 % slower measured)
+    constexpr int TS = NK + (NP == 5 ? 1 : 0);
     constexpr bool SE = ORD == 2;
     // loads issued one phase early (next chunk's q_s, the update base after
     // the tile barrier): box elements always, terrain in the split order
     constexpr bool PRE = !TER || SE;
     constexpr int WGT = wg_threads<NP, LPC, SE>();
-    __shared__ T tile[4][NP2 * NK];               // rho u, rho v, rho w, u: [field][p][kzl], kzl fastest
+    __shared__ T tile[4][NP2 * TS];               // rho u, rho v, rho w, u: [field][p][kzl], kzl fastest
     __shared__ double carry[2][NF][NP2];
     __shared__ T sD[NP2];
     // per position and tap, the x and y coefficients side by side: one 2-wide
@@ -146,7 +152,7 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
     __shared__ T2 sDxy[NP2 * NP];
     // (v, w) and (p', theta'), always differentiated together: one 2-wide
     // element per node, so one LDS read per tap serves both fields
-    __shared__ T2 tpr[2][NP2 * NK];
+    __shared__ T2 tpr[2][NP2 * TS];
     __shared__ double sW[NP];
     // the chunk's slice of the per-level tables, double-buffered: rho0,
     // 1/rho0, 1/theta0, p0, dtheta0/dz, 1/M_v at its NK levels, then dz and
@@ -319,7 +325,7 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
     __syncthreads();
     for (int t = tid; t < NP2; t += WGT) s_mij[t] = sW[t % NP] * sW[t / NP] * 0.125 * dxc * dyc;
     const T2* Dxy = &sDxy[pc * NP];
-    const int lx0 = (j * NP) * NK + kzl, ly0 = i * NK + kzl;
+    const int lx0 = (j * NP) * TS + kzl, ly0 = i * TS + kzl;
     // terrain: g_s and g_s times the box derivatives of zs per position (LDS)
     if constexpr (TER) {
         for (int t = tid; t < NP2; t += WGT) {
@@ -352,7 +358,7 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
             dupe = kk_t == N && el_t + 1 < L1 - L0;
         }
         const int kz = L0 * N + kzl;
-        const int lidx = pc * NK + kzl;
+        const int lidx = pc * TS + kzl;
         double qv[NF] = {0, 0, 0, 0, 0};
         T rho = T(1);
         if (active) {
@@ -457,10 +463,10 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
                 for (int mm = 0; mm < NP; ++mm) {
                     const T2 cxy = Dxy[mm];
                     const T cx = cxy.x, cy = cxy.y;
-                    ax += cx * tile[tx][lx0 + mm * NK];
-                    ay += cy * tile[ty][ly0 + mm * NP * NK];
-                    ax2 += cx * tile[tx2][lx0 + mm * NK];
-                    ay2 += cy * tile[ty2][ly0 + mm * NP * NK];
+                    ax += cx * tile[tx][lx0 + mm * TS];
+                    ay += cy * tile[ty][ly0 + mm * NP * TS];
+                    ax2 += cx * tile[tx2][lx0 + mm * TS];
+                    ay2 += cy * tile[ty2][ly0 + mm * NP * TS];
                 }
                 asm volatile("" : "+v"(ax), "+v"(ay), "+v"(ax2), "+v"(ay2) : : "memory");
                 ox = ax * sx;
@@ -475,7 +481,7 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
                 for (int mm = 0; mm < NP; ++mm) {
                     const T2 cxy = Dxy[mm];
                     const T cx = cxy.x, cy = cxy.y;
-                    const T2 a = tpr[pr][lx0 + mm * NK], b = tpr[pr][ly0 + mm * NP * NK];
+                    const T2 a = tpr[pr][lx0 + mm * TS], b = tpr[pr][ly0 + mm * NP * TS];
                     ax += cx * a.x;
                     ay += cy * b.x;
                     ax2 += cx * a.y;
@@ -527,7 +533,7 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
                 const double dzl = sb[6 * NK + el];
                 const T sz = T(sb[6 * NK + LPC + el]);
                 const T* Dz = &sD[kk * NP];
-                const int lz0 = pc * NK + el * N;
+                const int lz0 = pc * TS + el * N;
                 // two fields per call, as for d/dx and d/dy
                 auto ddz = [&](int tz, int tz2, T& oz, T& oz2) {
                     T az = 0, az2 = 0;
