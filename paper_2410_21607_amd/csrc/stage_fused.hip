@@ -134,9 +134,10 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
     constexpr int NK = LPC * N + 1;               // vertical nodes of a full chunk
     // LDS tile stride per position: one pad double at N = 4 (18 instead of
     // 17 at four layers per chunk: stages 1-1.5 % faster in the natural and
-    // split-element orders and in float).  Not at N = 7: with two layers a
-    // pad of one or two takes the workgroup from 78 KB of LDS to 82-87 KB,
-    // so only one instead of two fits a CU's 160 KB (7 % slower measured)
+    // split-element orders and in float).  Not at N = 7: with two layers in
+    // the split-element order a pad of one or two measured 7 % slower, with
+    // the same count of LDS bank conflicts and more wave cycles waiting on
+    // memory (its 16-wave workgroup runs one per CU either way)
     constexpr int TS = NK + (NP == 5 ? 1 : 0);
     constexpr bool SE = ORD == 2;
     // loads issued one phase early (next chunk's q_s, the update base after
