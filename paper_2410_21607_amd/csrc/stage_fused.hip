@@ -1152,6 +1152,23 @@ __global__ void k_stage_tail(DevMesh m, TailTables tl, double a, double b, doubl
          t += int64_t(gridDim.x) * blockDim.x) {
         const int li = int(t / nzn), kz = int(t - int64_t(li) * nzn);
         const int h = tl.h[li];
+        const bool fst = tl.first[li] != 0;
+        const int64_t ob = int64_t(h) * m.ldz + kz;
+        // the node's own values first: they depend only on the node, so
+        // their round trips overlap the contribution sums below
+        double bn[NF], bs[NF], br[NF];
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            if (fst) {
+                bn[f] = a != 0.0 ? qn[f * fs + ob] : 0.0;
+                bs[f] = qs[f * fs + ob];
+                br[f] = m.rx ? m.rx[f * fs + ob] : 0.0;
+            } else {
+                bn[f] = qo[f * fs + ob];
+                bs[f] = 0.0;
+                br[f] = 0.0;
+            }
+        }
         // the node's groups of contribution rows (side slots; per hanging
         // point of its Z^T row, that point and its side slots), each summed
         // and then added times its weight
@@ -1188,18 +1205,18 @@ __global__ void k_stage_tail(DevMesh m, TailTables tl, double a, double b, doubl
             }
             lid = (kz == nzn - 1);
         }
-        const int64_t o = int64_t(h) * m.ldz + kz;
-        if (tl.first[li]) {
+        const int64_t o = ob;
+        if (fst) {
 #pragma unroll
             for (int f = 0; f < NF; ++f) {
                 const double tend = (f == 3 && lid) ? 0.0 : mi * s[f];
-                const double rx = m.rx ? c * m.rx[f * fs + o] : 0.0;
-                qo[f * fs + o] = (a != 0.0 ? a * qn[f * fs + o] : 0.0) + b * qs[f * fs + o] + tend + rx;
+                const double rx = m.rx ? c * br[f] : 0.0;
+                qo[f * fs + o] = (a != 0.0 ? a * bn[f] : 0.0) + b * bs[f] + tend + rx;
             }
         } else {
 #pragma unroll
             for (int f = 0; f < NF; ++f)
-                if (!(f == 3 && lid)) qo[f * fs + o] += mi * s[f];
+                if (!(f == 3 && lid)) qo[f * fs + o] = bn[f] + mi * s[f];
         }
     }
 }
