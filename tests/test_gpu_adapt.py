@@ -10,7 +10,6 @@ import pytest
 
 from harness import match, oracle_mesh, oracle_reference_local
 from oracle import adapt, amr, assembly, metrics, timestep
-from oracle.mesh import OracleMesh
 from synth import cases
 from synth import columns as sc
 

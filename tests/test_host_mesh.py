@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 from harness import match, oracle_mesh
-from synth import cases, columns
+from synth import cases
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 

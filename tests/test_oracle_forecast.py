@@ -6,7 +6,7 @@ import numpy as np
 
 from harness import oracle_mesh
 from oracle import assembly, forecast
-from synth import cases, columns
+from synth import cases
 
 
 def setup(name, **kw):

@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 from oracle.mesh import OracleMesh
-from oracle import assembly, euler, timestep, amr
+from oracle import assembly, timestep, amr
 from synth import cases, columns, atmosphere
 
 
