@@ -308,8 +308,8 @@ int sem_stage_get_tune(const sem_mesh *mesh, int *layers_per_chunk);
  *     too (fewer rows per wave in the global loads and stores, the second z
  *     derivative spread over every wave).  In this natural order a
  *     position's nodes below the chunk's top plane take consecutive threads
- *     and the top plane's nodes come last, so that at N = 4 a wave's loads
- *     and stores cover whole 128-byte lines;
+ *     and the top plane's nodes come last, so that at N = 4 with four layers
+ *     per chunk a wave's loads and stores cover whole 128-byte lines;
  *   SEM_LAYOUT_COLUMNS_SPLIT: in FP64 a thread per (element, local node) of
  *     each position, so that each thread takes one element's z derivatives
  *     and a node between two elements has two threads (the lower hands its

@@ -212,10 +212,10 @@ k_stage_columns(DevMesh m, FusedTables ft, int col0, int ncol, double a, double 
     //    that the global loads and stores of a wave cover few rows and lines;
     //    every wave then carries the same LDS load.  A position's first
     //    LPC*N nodes take consecutive threads and the chunk's top plane (the
-    //    next chunk's bottom) follows in the last threads: at N = 4 a wave then
-    //    holds four whole 16-node row segments, each one aligned 128-byte line
-    //    per field, instead of 17-node segments that straddle two lines and
-    //    start anywhere in a wave.
+    //    next chunk's bottom) follows in the last threads: at N = 4 with four
+    //    layers a wave then holds four whole 16-node row segments, each one
+    //    aligned 128-byte line per field, instead of 17-node segments that
+    //    straddle two lines and start anywhere in a wave.
     //  0 (FP64): nodes on the planes between two stacked elements (LPC-1 per
     //    position, two z derivatives each) come first, so that they fill
     //    waves of their own instead of making every wave run a second pass of
